@@ -1,0 +1,223 @@
+"""Pins of the ray-tracer (sect. 4, Eqs. 11-17) and its adjoint."""
+import math
+
+import numpy as np
+import pytest
+
+import mcrt_inputs as mi
+
+D = 1e20
+
+
+def small_model(n=(5, 4, 6), seed=0, nl=6, ns=2, rho=None, lum=0.0):
+    rng = np.random.default_rng(seed)
+    m = mi.cube(n=4, n_packets=1000, nl=nl)
+    m.nx, m.ny, m.nz = n
+    m.dcell = 1e14
+    m.origin = -0.5 * np.array(n, float) * m.dcell + np.array([0.13, -0.21, 0.05]) * m.dcell
+    m.rho = rng.uniform(0.2, 1.5, n[::-1]) * 1e-18 if rho is None else rho
+    m.mass_frac = np.full(ns, 1.0 / ns)
+    m.kabs = rng.uniform(1e3, 2e4, (ns, nl))
+    m.ksca = rng.uniform(0, 1e4, (ns, nl))
+    m.g = rng.uniform(-0.3, 0.7, (ns, nl))
+    m.src_lum = np.array([lum])
+    return m
+
+
+def pixel_rays(m, theta, phi, npx, npy):
+    th, ph = math.radians(theta), math.radians(phi)
+    k = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    ex = np.array([math.cos(th) * math.cos(ph), math.cos(th) * math.sin(ph), -math.sin(th)])
+    ey = np.array([-math.sin(ph), math.cos(ph), 0.0])
+    n = np.array([m.nx, m.ny, m.nz])
+    ctr = m.origin + 0.5 * n * m.dcell
+    fov = math.sqrt(3.0) * n.max() * m.dcell
+    out = []
+    for iy in range(npy):
+        for ix in range(npx):
+            xp = (ix + 0.5) * fov / npx - fov / 2
+            yp = (iy + 0.5) * fov / npy - fov / 2
+            out.append((ix, iy, ctr + xp * ex + yp * ey + fov * k, -k))
+    return out, (fov / npx) * (fov / npy)
+
+
+def brute_segments(m, r0, d):
+    segs = []
+    for iz in range(m.nz):
+        for iy in range(m.ny):
+            for ix in range(m.nx):
+                lo = m.origin + np.array([ix, iy, iz]) * m.dcell
+                hi = lo + m.dcell
+                t0, t1 = -np.inf, np.inf
+                for a in range(3):
+                    if d[a] != 0:
+                        u, v = (lo[a] - r0[a]) / d[a], (hi[a] - r0[a]) / d[a]
+                        t0, t1 = max(t0, min(u, v)), min(t1, max(u, v))
+                    elif not lo[a] <= r0[a] <= hi[a]:
+                        t0, t1 = 1, 0
+                if t1 - t0 > 0:
+                    segs.append((t0, (iz * m.ny + iy) * m.nx + ix, t1 - t0))
+    segs.sort()
+    return segs
+
+
+def test_isothermal_absorber_closed_form(orc):
+    """kappa_sca = 0, constant T: I = B(T)(1 - exp(-rho kappa chord))."""
+    m = small_model(nl=5, ns=1)
+    m.rho = np.full(m.rho.shape, 3e-18)
+    m.ksca[:] = 0.0
+    views = np.array([[30.0, 20.0], [90.0, 0.0], [0.0, 0.0]])
+    idx = np.array([0, 2, 4], np.int32)
+    o = orc.Oracle(m, views=views, img_idx=idx, distance=D)
+    T = np.full((1, m.nx * m.ny * m.nz), 700.0)
+    img, sed = o.raytrace(7, 9, T=T)
+    nu, w = orc.freq_grid(m.lam_um)
+    lo = m.origin
+    hi = m.origin + np.array([m.nx, m.ny, m.nz]) * m.dcell
+    for v, (th, ph) in enumerate(views):
+        rays, apix = pixel_rays(m, th, ph, 7, 9)
+        for ix, iy, r0, d in rays:
+            t0, t1 = -np.inf, np.inf
+            for a in range(3):
+                if d[a] != 0:
+                    u, s = (lo[a] - r0[a]) / d[a], (hi[a] - r0[a]) / d[a]
+                    t0, t1 = max(t0, min(u, s)), min(t1, max(u, s))
+                elif not lo[a] <= r0[a] <= hi[a]:
+                    t0, t1 = 1, 0
+            chord = max(t1 - t0, 0.0)
+            for q, j in enumerate(idx):
+                I = orc.planck(nu[j], 700.0) * -np.expm1(-3e-18 * m.kabs[0, j] * chord)
+                assert img[v, q, iy, ix] == pytest.approx(apix / D**2 * I, rel=1e-10, abs=1e-300)
+
+
+def test_empty_grid_star_only(orc):
+    m = small_model(nl=5, ns=1, lum=3.8e33)
+    m.rho = np.zeros(m.rho.shape)
+    views = np.array([[40.0, 10.0], [120.0, 250.0]])
+    idx = np.array([1, 3], np.int32)
+    o = orc.Oracle(m, views=views, img_idx=idx, distance=D)
+    img, sed = o.raytrace(8, 8, T=np.zeros((1, m.nx * m.ny * m.nz)))
+    nu, w = orc.freq_grid(m.lam_um)
+    B = np.array([orc.planck(x, 5800.0) for x in nu])
+    lnu = 3.8e33 * B / np.sum(w * B)
+    for v in range(2):
+        for q, j in enumerate(idx):
+            assert sed[v, q] == pytest.approx(lnu[j] / (4 * np.pi * D**2), rel=1e-13)
+            assert np.count_nonzero(img[v, q]) == 1
+            assert img[v, q].sum() == pytest.approx(sed[v, q], rel=1e-13)
+
+
+def test_rotation_symmetry(orc):
+    """Rotating the grid by +90 deg about z and the view azimuth by 90 deg
+    leaves the image unchanged."""
+    n = 6
+    rng = np.random.default_rng(3)
+    m = small_model(n=(n, n, n), nl=4, ns=1)
+    m.origin = -0.5 * n * m.dcell * np.ones(3)
+    rho1 = rng.uniform(0.1, 2.0, (n, n, n)) * 1e-18
+    T1 = rng.uniform(100, 900, (n, n, n))
+    # rho2(x, y, z) = rho1(y, -x, z)  ->  rho2[iz, iy, ix] = rho1[iz, n-1-ix, iy]
+    rho2 = np.transpose(rho1, (0, 2, 1))[:, :, ::-1]
+    T2 = np.transpose(T1, (0, 2, 1))[:, :, ::-1]
+    idx = np.array([0, 3], np.int32)
+    m.rho = rho1
+    a = orc.Oracle(m, views=np.array([[70.0, 0.0]]), img_idx=idx, distance=D)
+    ia, sa = a.raytrace(9, 9, T=T1.reshape(1, -1))
+    m.rho = rho2
+    b = orc.Oracle(m, views=np.array([[70.0, 90.0]]), img_idx=idx, distance=D)
+    ib, sb = b.raytrace(9, 9, T=T2.reshape(1, -1))
+    np.testing.assert_allclose(ia, ib, rtol=1e-9, atol=1e-12 * ia.max())
+
+
+def test_brute_force_formal_solution(orc):
+    m = small_model(seed=7)
+    nc = m.nx * m.ny * m.nz
+    rng = np.random.default_rng(8)
+    views = np.array([[33.0, 71.0], [121.0, -40.0]])
+    idx = np.array([1, 4], np.int32)
+    T = rng.uniform(50, 1500, (2, nc))
+    ssca = rng.uniform(0, 1e20, (2, 2, nc))
+    o = orc.Oracle(m, views=views, img_idx=idx, distance=D)
+    img, _ = o.raytrace(6, 5, T=T, ssca=ssca)
+    nu, w = orc.freq_grid(m.lam_um)
+    kabs_mix = 0.5 * m.kabs[0] + 0.5 * m.kabs[1]
+    kext = kabs_mix + 0.5 * m.ksca[0] + 0.5 * m.ksca[1]
+    V = m.dcell**3
+    rhof = m.rho.ravel()
+    for v, (th, ph) in enumerate(views):
+        rays, apix = pixel_rays(m, th, ph, 6, 5)
+        for ix, iy, r0, d in rays:
+            segs = brute_segments(m, r0, d)
+            for q, j in enumerate(idx):
+                I, tr = 0.0, 1.0
+                for _, c, ell in segs:
+                    em = sum(0.5 * m.kabs[s, j] * orc.planck(nu[j], T[s, c]) for s in range(2))
+                    S = (rhof[c] * em + ssca[v, q, c] / (V * w[j])) / (rhof[c] * kext[j])
+                    dt = rhof[c] * kext[j] * ell
+                    I += tr * S * -np.expm1(-dt)
+                    tr *= np.exp(-dt)
+                assert img[v, q, iy, ix] == pytest.approx(apix / D**2 * I, rel=1e-9, abs=1e-300)
+
+
+def test_scattered_light_normalisation(orc):
+    """Thin isotropic scatterer: the HG-weighted event sum is N_sca xi/(4 pi)
+    and the ray-traced scattered flux integrates to it (thin limit)."""
+    m = mi.cube(n=8, n_packets=40000, tau_v=0.02, nl=4, albedo=1.0, g=0.0)
+    views = np.array([[20.0, 0.0], [75.0, 40.0]])
+    idx = np.arange(4, dtype=np.int32)
+    o = orc.Oracle(m, views=views, img_idx=idx, distance=D)
+    o.run(mode=orc.BW_EPOCH, lucy_tau=0.0)
+    xi = o.xi()
+    for v in range(2):
+        assert o.ssca[v].sum() * 4 * np.pi / xi == pytest.approx(o.stats["scatters"], rel=1e-12)
+    img, sed = o.raytrace(64, 64, T=np.zeros((1, o.ncells)), ssca=o.ssca)
+    nu, w = orc.freq_grid(m.lam_um)
+    for v in range(2):
+        for q in range(4):
+            star = 0.0  # star enters the SED separately: remove it
+            L = m.src_lum[0]
+            B = np.array([orc.planck(x, 5800.0) for x in nu])
+            lnu = L * B / np.sum(w * B)
+            # attenuated star term is bounded by the unattenuated one
+            dust = sed[v, q] - lnu[q] / (4 * np.pi * D**2) * np.exp(-0.02 * 1.0)
+            tot = o.ssca[v, q].sum() / (w[q] * D**2)
+            if tot > 0:
+                assert dust == pytest.approx(tot, rel=0.05)
+
+
+# ------------------------------------------------------------------ adjoint
+
+def test_adjoint_matches_central_differences(orc):
+    m = small_model(n=(4, 4, 4), seed=11, nl=5, lum=3.8e33)
+    m.origin = -2.0 * m.dcell * np.ones(3) + np.array([0.3, 0.1, -0.2]) * m.dcell
+    nc = 64
+    rng = np.random.default_rng(12)
+    views = np.array([[25.0, 10.0], [100.0, 200.0]])
+    idx = np.array([0, 3], np.int32)
+    T = rng.uniform(100, 1200, (2, nc))
+    ssca = rng.uniform(0, 1e21, (2, 2, nc))
+    npx = npy = 6
+    w_img = rng.normal(size=(2, 2, npy, npx))
+    w_sed = rng.normal(size=(2, 2))
+    rho = m.rho.ravel().copy()
+    o = orc.Oracle(m, views=views, img_idx=idx, distance=D)
+    g = o.raytrace_adjoint(npx, npy, w_img=w_img, w_sed=w_sed, T=T, ssca=ssca)
+
+    def loss():
+        img, sed = o.raytrace(npx, npy, T=T, ssca=ssca)
+        return np.sum(w_img * img) + np.sum(w_sed * sed)
+
+    fd = np.zeros(nc)
+    for c in range(nc):
+        h = 1e-4 * rho[c]
+        o.rho.flat[c] = rho[c] + h
+        lp = loss()
+        o.rho.flat[c] = rho[c] - h
+        lm = loss()
+        o.rho.flat[c] = rho[c]
+        fd[c] = (lp - lm) / (2 * h)
+    assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
+    # linearity in the weights
+    g2 = o.raytrace_adjoint(npx, npy, w_img=2 * w_img, w_sed=None, T=T, ssca=ssca)
+    g3 = o.raytrace_adjoint(npx, npy, w_img=None, w_sed=w_sed, T=T, ssca=ssca)
+    np.testing.assert_allclose(0.5 * g2 + g3, g, rtol=1e-12, atol=1e-12 * np.abs(g).max())
