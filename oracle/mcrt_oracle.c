@@ -1042,23 +1042,27 @@ static int walk(const orc_model *m, const double p0[3], const double d[3], int c
 }
 
 /* Source function per imaged wavelength (sect. 4, Eqs. 14 and 16 read as
- * emissivity over extinction): S = [rho sum_s f_s kabs_s B(T_s) +
- * Ssca/(V dnu)] / (rho kext). */
+ * emissivity over extinction): S = sum_s f_s kabs_s B(T_s)/kext +
+ * Ssca/(V dnu rho kext), with rho the model density that produced the
+ * scattering events (emissivity per unit mass fixed). */
 static double source_fn(const tab_t *t, const orc_model *m, const double *T,
-                        const double *ssca, int v, int q, int64_t c, double rho) {
+                        const double *ssca, int v, int q, int64_t c) {
   int j = m->img_idx[q], nl = t->nl;
   double em = 0.0;
   for (int s = 0; s < t->ns; s++) {
     if (s == m->pah_species) continue;
     em += m->mass_frac[s] * m->kabs[s * nl + j] * orc_planck(t->nu[j], T[(int64_t)s * t->ncell + c]);
   }
-  double jsum = rho * em;
-  if (ssca) jsum += ssca[((int64_t)v * m->nimg + q) * t->ncell + c] / (t->V * t->w[j]);
-  return jsum / (rho * t->kext[j]);
+  double S = em / t->kext[j];
+  double rho = m->rho[c];
+  if (ssca && rho > 0.0)
+    S += ssca[((int64_t)v * m->nimg + q) * t->ncell + c] / (t->V * t->w[j] * rho * t->kext[j]);
+  return S;
 }
 
-int orc_raytrace(const orc_model *m, const double *T, const double *ssca, int npx, int npy,
-                 double *img, double *sed) {
+int orc_raytrace(const orc_model *m, const double *T, const double *ssca, const double *rho_rt,
+                 int npx, int npy, double *img, double *sed) {
+  if (!rho_rt) rho_rt = m->rho;
   tab_t t;
   tab_init(&t, m);
   int maxs = m->nx + m->ny + m->nz + 3;
@@ -1079,10 +1083,10 @@ int orc_raytrace(const orc_model *m, const double *T, const double *ssca, int np
           int j = m->img_idx[q];
           double I = 0.0, tr = 1.0;
           for (int s = 0; s < nseg; s++) {
-            double rho = m->rho[cells[s]];
+            double rho = rho_rt[cells[s]];
             if (!(rho > 0.0)) continue;
             double dtau = rho * t.kext[j] * lens[s];
-            double S = source_fn(&t, m, T, ssca, v, q, cells[s], rho);
+            double S = source_fn(&t, m, T, ssca, v, q, cells[s]);
             I += tr * S * (-expm1(-dtau));
             tr *= exp(-dtau);
           }
@@ -1106,7 +1110,7 @@ int orc_raytrace(const orc_model *m, const double *T, const double *ssca, int np
       for (int q = 0; q < m->nimg; q++) {
         int j = m->img_idx[q];
         double tau = 0.0;
-        for (int g = 0; g < nseg; g++) tau += m->rho[cells[g]] * t.kext[j] * lens[g];
+        for (int g = 0; g < nseg; g++) tau += rho_rt[cells[g]] * t.kext[j] * lens[g];
         double F = t.lnu[s * t.nl + j] / (4.0 * PI_D * D2) * exp(-tau);
         if (ix >= 0 && ix < npx && iy >= 0 && iy < npy)
           img[(((int64_t)v * m->nimg + q) * npy + iy) * npx + ix] += F;
@@ -1125,8 +1129,10 @@ int orc_raytrace(const orc_model *m, const double *T, const double *ssca, int np
  * dI/d(dtau_i) = T_<i S_i e^{-dtau_i} - (I - A_i), A_i the intensity
  * gathered up to and including cell i. A first sweep gives I, a second
  * recomputes the transmittance and A_i. */
-int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca, int npx,
-                         int npy, const double *w_img, const double *w_sed, double *drho) {
+int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca,
+                         const double *rho_rt, int npx, int npy, const double *w_img,
+                         const double *w_sed, double *drho) {
+  if (!rho_rt) rho_rt = m->rho;
   tab_t t;
   tab_init(&t, m);
   int maxs = m->nx + m->ny + m->nz + 3;
@@ -1150,20 +1156,20 @@ int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca
           if (W == 0.0) continue;
           double I = 0.0, tr = 1.0;
           for (int s = 0; s < nseg; s++) {
-            double rho = m->rho[cells[s]];
+            double rho = rho_rt[cells[s]];
             if (!(rho > 0.0)) continue;
             double dtau = rho * t.kext[j] * lens[s];
-            double S = source_fn(&t, m, T, ssca, v, q, cells[s], rho);
+            double S = source_fn(&t, m, T, ssca, v, q, cells[s]);
             I += tr * S * (-expm1(-dtau));
             tr *= exp(-dtau);
           }
           double A = 0.0;
           tr = 1.0;
           for (int s = 0; s < nseg; s++) {
-            double rho = m->rho[cells[s]];
+            double rho = rho_rt[cells[s]];
             if (!(rho > 0.0)) continue;
             double dtau = rho * t.kext[j] * lens[s];
-            double S = source_fn(&t, m, T, ssca, v, q, cells[s], rho);
+            double S = source_fn(&t, m, T, ssca, v, q, cells[s]);
             double e = exp(-dtau);
             A += tr * S * (-expm1(-dtau));
             double dI = tr * S * e - (I - A);
@@ -1190,7 +1196,7 @@ int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca
                    ((inimg && w_img) ? w_img[(((int64_t)v * m->nimg + q) * npy + iy) * npx + ix] : 0.0);
         if (W == 0.0) continue;
         double tau = 0.0;
-        for (int g = 0; g < nseg; g++) tau += m->rho[cells[g]] * t.kext[j] * lens[g];
+        for (int g = 0; g < nseg; g++) tau += rho_rt[cells[g]] * t.kext[j] * lens[g];
         double F = t.lnu[s * t.nl + j] / (4.0 * PI_D * D2) * exp(-tau);
         for (int g = 0; g < nseg; g++) drho[cells[g]] += -W * t.kext[j] * lens[g] * F;
       }

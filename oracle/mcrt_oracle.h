@@ -121,13 +121,15 @@ int orc_pah_pass(const orc_model *m, const orc_opts *o, uint64_t seed, orc_state
 /* Eq. 4 for every cell and species from the current tallies. */
 void orc_finalize_T(const orc_model *m, const orc_opts *o, orc_state *st);
 
-/* Ray-tracer (sect. 4): images [nview][nimg][npy][npx], SED [nview][nimg]. */
-int orc_raytrace(const orc_model *m, const double *T, const double *ssca,
+/* Ray-tracer (sect. 4): images [nview][nimg][npy][npx], SED [nview][nimg].
+ * rho_rt (NULL = model density) is the density used for extinction; the
+ * source function keeps the model's values (emissivity per unit mass). */
+int orc_raytrace(const orc_model *m, const double *T, const double *ssca, const double *rho_rt,
                  int npx, int npy, double *img, double *sed);
-/* Gradient of sum(w_img*img) + sum(w_sed*sed) with respect to rho [cells]. */
+/* Gradient of sum(w_img*img) + sum(w_sed*sed) with respect to rho_rt [cells]. */
 int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca,
-                         int npx, int npy, const double *w_img, const double *w_sed,
-                         double *drho);
+                         const double *rho_rt, int npx, int npy, const double *w_img,
+                         const double *w_sed, double *drho);
 
 /* Voxelizers (model set-up). */
 void orc_voxelize_torus(int nx, int ny, int nz, const double origin[3], double dcell,

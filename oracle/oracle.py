@@ -117,8 +117,8 @@ def lib():
                               C.c_uint64, C.POINTER(State)]
         L.orc_pah_pass.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint64, C.POINTER(State)]
         L.orc_finalize_T.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.POINTER(State)]
-        L.orc_raytrace.argtypes = [C.POINTER(Model), _dp, _dp, C.c_int, C.c_int, _dp, _dp]
-        L.orc_raytrace_adjoint.argtypes = [C.POINTER(Model), _dp, _dp, C.c_int, C.c_int,
+        L.orc_raytrace.argtypes = [C.POINTER(Model), _dp, _dp, _dp, C.c_int, C.c_int, _dp, _dp]
+        L.orc_raytrace_adjoint.argtypes = [C.POINTER(Model), _dp, _dp, _dp, C.c_int, C.c_int,
                                            _dp, _dp, _dp]
         L.orc_voxelize_torus.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_double, C.c_int,
                                          _dp, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -366,19 +366,23 @@ class Oracle:
             raise RuntimeError("maxseg too small")
         return cells[:n], lens[:n]
 
-    def raytrace(self, npx, npy, T=None, ssca=None):
+    def raytrace(self, npx, npy, T=None, ssca=None, rho_rt=None):
+        """Images [view][img][npy][npx] and SED [view][img]; rho_rt replaces the
+        density in the optical depths only (source functions keep the model's)."""
         T = _f64(self.T if T is None else T)
         nv, ni = self.views.shape[0], self.img_idx.size
         img = np.zeros((nv, ni, npy, npx))
         sed = np.zeros((nv, ni))
         ss = None if ssca is None else _f64(ssca)
-        lib().orc_raytrace(C.byref(self.m), _p(T), _p(ss), npx, npy, _p(img), _p(sed))
+        rr = None if rho_rt is None else _f64(rho_rt)
+        lib().orc_raytrace(C.byref(self.m), _p(T), _p(ss), _p(rr), npx, npy, _p(img), _p(sed))
         return img, sed
 
-    def raytrace_adjoint(self, npx, npy, w_img=None, w_sed=None, T=None, ssca=None):
+    def raytrace_adjoint(self, npx, npy, w_img=None, w_sed=None, T=None, ssca=None, rho_rt=None):
         T = _f64(self.T if T is None else T)
         ss = None if ssca is None else _f64(ssca)
+        rr = None if rho_rt is None else _f64(rho_rt)
         drho = np.zeros(self.ncells)
-        lib().orc_raytrace_adjoint(C.byref(self.m), _p(T), _p(ss), npx, npy, _p(_f64(w_img)),
-                                   _p(_f64(w_sed)), _p(drho))
+        lib().orc_raytrace_adjoint(C.byref(self.m), _p(T), _p(ss), _p(rr), npx, npy,
+                                   _p(_f64(w_img)), _p(_f64(w_sed)), _p(drho))
         return drho

@@ -188,6 +188,10 @@ def test_scattered_light_normalisation(orc):
 # ------------------------------------------------------------------ adjoint
 
 def test_adjoint_matches_central_differences(orc):
+    """Full Jacobian of a 4^3 model against central differences of the
+    forward ray-tracer in the extinction density, with thermal emission,
+    scattered light (dominant at the short imaged wavelength) and an
+    embedded point source."""
     m = small_model(n=(4, 4, 4), seed=11, nl=5, lum=3.8e33)
     m.origin = -2.0 * m.dcell * np.ones(3) + np.array([0.3, 0.1, -0.2]) * m.dcell
     nc = 64
@@ -199,24 +203,37 @@ def test_adjoint_matches_central_differences(orc):
     npx = npy = 6
     w_img = rng.normal(size=(2, 2, npy, npx))
     w_sed = rng.normal(size=(2, 2))
-    rho = m.rho.ravel().copy()
+    rho0 = m.rho.ravel().copy()
     o = orc.Oracle(m, views=views, img_idx=idx, distance=D)
-    g = o.raytrace_adjoint(npx, npy, w_img=w_img, w_sed=w_sed, T=T, ssca=ssca)
+    g = o.raytrace_adjoint(npx, npy, w_img=w_img, w_sed=w_sed, T=T, ssca=ssca, rho_rt=rho0)
+    img0, _ = o.raytrace(npx, npy, T=T, ssca=ssca)
+    # both terms of S are present in the images
+    assert np.all(img0[:, 0].sum(axis=(1, 2)) > 0) and np.all(img0[:, 1].sum(axis=(1, 2)) > 0)
 
-    def loss():
-        img, sed = o.raytrace(npx, npy, T=T, ssca=ssca)
+    def loss(rr):
+        img, sed = o.raytrace(npx, npy, T=T, ssca=ssca, rho_rt=rr)
         return np.sum(w_img * img) + np.sum(w_sed * sed)
 
     fd = np.zeros(nc)
     for c in range(nc):
-        h = 1e-4 * rho[c]
-        o.rho.flat[c] = rho[c] + h
-        lp = loss()
-        o.rho.flat[c] = rho[c] - h
-        lm = loss()
-        o.rho.flat[c] = rho[c]
-        fd[c] = (lp - lm) / (2 * h)
+        h = 1e-4 * rho0[c]
+        rp = rho0.copy(); rp[c] += h
+        rm = rho0.copy(); rm[c] -= h
+        fd[c] = (loss(rp) - loss(rm)) / (2 * h)
     assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
+    # per wavelength the check holds too (scattered light alone at index 0)
+    for q in range(2):
+        wq = np.zeros_like(w_img); wq[:, q] = w_img[:, q]
+        gq = o.raytrace_adjoint(npx, npy, w_img=wq, T=T, ssca=ssca)
+        fq = np.zeros(nc)
+        for c in range(nc):
+            h = 1e-4 * rho0[c]
+            rp = rho0.copy(); rp[c] += h
+            rm = rho0.copy(); rm[c] -= h
+            ip, _ = o.raytrace(npx, npy, T=T, ssca=ssca, rho_rt=rp)
+            im, _ = o.raytrace(npx, npy, T=T, ssca=ssca, rho_rt=rm)
+            fq[c] = np.sum(wq * (ip - im)) / (2 * h)
+        assert np.linalg.norm(gq - fq) <= 1e-6 * np.linalg.norm(fq)
     # linearity in the weights
     g2 = o.raytrace_adjoint(npx, npy, w_img=2 * w_img, w_sed=None, T=T, ssca=ssca)
     g3 = o.raytrace_adjoint(npx, npy, w_img=None, w_sed=w_sed, T=T, ssca=ssca)
