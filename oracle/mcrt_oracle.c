@@ -1212,32 +1212,53 @@ int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca
 
 /* Clumpy torus by the cell-centre test: clump density inside any clump
  * (overlaps keep the single-clump density), inter-clump density inside the
- * wedge r_in <= r <= r_out, |z| <= r sin(theta1), empty elsewhere. */
+ * wedge r_in <= r <= r_out, |z| <= r sin(theta1), empty elsewhere. Clumps
+ * are visited one by one over the cells near them (a box one cell wider
+ * than the clump on each side), which selects exactly the cells whose
+ * centre passes the distance test. */
 void orc_voxelize_torus(int nx, int ny, int nz, const double origin[3], double dcell,
                         int ncl, const double *C, double r_clump, double rho_clump,
                         double rho_inter, double r_in, double r_out, double s1,
                         double *rho) {
   double rc2 = r_clump * r_clump, ri2 = r_in * r_in, ro2 = r_out * r_out, s12 = s1 * s1;
+  int64_t nc = (int64_t)nx * ny * nz;
+  unsigned char *in = calloc((size_t)nc, 1);
+  int n[3] = {nx, ny, nz};
+  for (int k = 0; k < ncl; k++) {
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+      lo[a] = (int)floor((C[3 * k + a] - r_clump - origin[a]) / dcell) - 1;
+      hi[a] = (int)floor((C[3 * k + a] + r_clump - origin[a]) / dcell) + 1;
+      if (lo[a] < 0) lo[a] = 0;
+      if (hi[a] > n[a] - 1) hi[a] = n[a] - 1;
+    }
+    for (int iz = lo[2]; iz <= hi[2]; iz++)
+      for (int iy = lo[1]; iy <= hi[1]; iy++)
+        for (int ix = lo[0]; ix <= hi[0]; ix++) {
+          double x = origin[0] + ((double)ix + 0.5) * dcell;
+          double y = origin[1] + ((double)iy + 0.5) * dcell;
+          double z = origin[2] + ((double)iz + 0.5) * dcell;
+          double dx = x - C[3 * k], dy = y - C[3 * k + 1], dz = z - C[3 * k + 2];
+          if (dx * dx + dy * dy + dz * dz <= rc2) in[((int64_t)iz * ny + iy) * nx + ix] = 1;
+        }
+  }
   for (int iz = 0; iz < nz; iz++)
     for (int iy = 0; iy < ny; iy++)
       for (int ix = 0; ix < nx; ix++) {
+        int64_t c = ((int64_t)iz * ny + iy) * nx + ix;
         double x = origin[0] + ((double)ix + 0.5) * dcell;
         double y = origin[1] + ((double)iy + 0.5) * dcell;
         double z = origin[2] + ((double)iz + 0.5) * dcell;
         double v = 0.0;
-        int hit = 0;
-        for (int k = 0; k < ncl && !hit; k++) {
-          double dx = x - C[3 * k], dy = y - C[3 * k + 1], dz = z - C[3 * k + 2];
-          if (dx * dx + dy * dy + dz * dz <= rc2) hit = 1;
-        }
-        if (hit) {
+        if (in[c]) {
           v = rho_clump;
         } else {
           double r2 = x * x + y * y + z * z;
           if (r2 >= ri2 && r2 <= ro2 && z * z <= r2 * s12) v = rho_inter;
         }
-        rho[((int64_t)iz * ny + iy) * nx + ix] = v;
+        rho[c] = v;
       }
+  free(in);
 }
 
 /* Gauss-Legendre nodes/weights on [-1,1] by Newton on P_n. */
