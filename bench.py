@@ -1,0 +1,177 @@
+#!/usr/bin/env python
+"""Throughput of the Monte Carlo dust transport and the ray-tracer on one MI355X.
+
+One step runs the whole hot path on the clumpy AGN torus (256^3 cells, 2000
+clumps, 100 wavelengths, 1e8 packets, FP32 walk): packet transport with
+immediate Bjorkman & Wood re-emission, Lucy estimator, modified random walk
+in cells with Rosseland depth > 50, HG scattering events for 8 views, the
+PAH second stage, Eq. 4 temperatures (FP64), then the ray-tracer forward
+(512x512 pixels, 16 wavelengths, 8 views) and its adjoint. Inputs are
+resident on the GPU before the timed region.
+
+Prints one JSON line (see the keys below); the CPU oracle is timed on a
+bounded sample of the same model as the reference baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photon packets/s & cell-crossings/s (256^3 torus); ray-trace px/s fwd+bwd"
+HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(st, ns_thermal, nview):
+    """Bytes the transport must move for its events (FP32 density walk):
+    4 per crossing (density gather), 24 per absorption (count read-modify-
+    write 16 + path-energy read 8), 16 per Lucy deposit and thermal species,
+    8 per scattering and view (event sum read-modify-write, an upper bound:
+    only scatterings at imaged wavelengths write), 16 per MRW step and
+    thermal species. Packet state stays in registers (no queue traffic)."""
+    return (4 * st["crossings"] + 24 * st["absorptions"] + 16 * ns_thermal * st["lucy_deposits"]
+            + 8 * nview * st["scatters"] + 16 * ns_thermal * st["mrw_steps"])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--packets", type=int, default=100_000_000)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--npix", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=10_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the method is not sharded here); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import mcrt_inputs as mi
+    import paper_1203_2941_amd as mc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    N = args.packets
+    m = mi.torus(n=args.grid, n_packets=N)
+    views, idx = mi.image_views(n_views=8, n_img=16, nl=m.nl)
+    D = 15.0 * mi.MPC_CM
+    log(f"setup: torus {args.grid}^3, {N} packets, views {len(views)}, imaged {len(idx)}")
+    ctx = mc.Context(0, "fp32").from_inputs(m, views=views, img_idx=idx, distance=D)
+    npx = npy = args.npix
+    rng = np.random.default_rng(5)
+    w_img = torch.tensor(rng.random((len(views), len(idx), npy, npx), dtype=np.float32),
+                         device="cuda")
+    img = torch.empty_like(w_img)
+    sed = torch.empty((len(views), len(idx)), dtype=torch.float64, device="cuda")
+    grad = torch.empty(ctx.ncells, dtype=torch.float32, device="cuda")
+    opts = dict(mode="bw_ticket", n_total=N, mrw_tau=50.0, mrw_gamma=2.0, lucy_tau=1e-2,
+                max_interactions=10_000_000, sed_theta_bins=10)
+
+    def step(seed):
+        ctx.reset()
+        st = ctx.run_packets(0, N, seed, **opts)
+        sp = ctx.run_pah(seed, **opts)
+        ctx.finalize_temperatures()
+        ctx.raytrace_device(npx, npy, img=img, sed=sed)
+        t = ctx.timings()
+        ctx.raytrace_adjoint_device(npx, npy, w_img=w_img, out=grad)
+        t2 = ctx.timings()
+        return st, sp, t["rt_fwd_ms"], t2["rt_adj_ms"]
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        step(1000 + w)
+        torch.cuda.synchronize()
+        log(f"warmup {w}: {time.perf_counter() - t0:.2f} s")
+    times, rec = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, sp, fwd_ms, adj_ms = step(k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        times.append(dt)
+        rec.append((st, sp, fwd_ms, adj_ms))
+        log(f"step {k}: {dt:.3f} s, transport {st['kernel_ms']:.1f} ms, pah {sp['kernel_ms']:.1f} ms,"
+            f" rt fwd {fwd_ms:.2f} ms, adj {adj_ms:.2f} ms, crossings {st['crossings']}")
+    ms = 1000.0 * float(np.mean(times))
+    st0 = rec[-1][0]
+    cross = np.mean([r[0]["crossings"] + r[1]["crossings"] for r in rec])
+    t_tr = np.mean([r[0]["kernel_ms"] for r in rec]) / 1e3
+    fwd = np.mean([r[2] for r in rec]) / 1e3
+    adj = np.mean([r[3] for r in rec]) / 1e3
+    rays = len(views) * npx * npy
+    ns_th = m.ns - (1 if m.pah_species >= 0 else 0)
+    b_alg = np.mean([algorithmic_bytes(r[0], ns_th, len(views)) for r in rec])
+    out = {
+        "metric": METRIC,
+        "value": N / (ms / 1e3),
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"clumpy AGN torus {args.grid}^3, 2000 clumps r=0.02 r_out, contrast 100, "
+                         f"100 wavelengths, {N} packets, immediate B&W, MRW tau_R>50, PAH; "
+                         f"ray-tracer {npx}x{npy} px x 16 wavelengths x 8 views fwd+adjoint"),
+            "packets": N, "grid": args.grid, "wavelengths": int(m.nl), "views": len(views),
+            "imaged_wavelengths": len(idx), "pixels": [npx, npy], "precision": "fp32 walk, fp64 Eq. 4",
+        },
+        "cell_crossings_per_s": cross / (ms / 1e3),
+        "transport_packets_per_s": N / t_tr,
+        "transport_crossings_per_s": st0["crossings"] / t_tr,
+        "raytrace_px_per_s_fwd_bwd": rays / (fwd + adj),
+        "raytrace_px_per_s_fwd": rays / fwd,
+        "raytrace_fwd_ms": fwd * 1e3,
+        "raytrace_adj_ms": adj * 1e3,
+        "transport_ms": t_tr * 1e3,
+        "events_per_step": {k: int(v) for k, v in st0.items() if k != "kernel_ms"},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_transport<float>",
+            "achieved": b_alg / t_tr / 1e9,
+            "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s",
+            "frac": b_alg / t_tr / HBM_PEAK,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        oracle.build(force=False)
+        n = args.cpu_sample
+        log(f"cpu baseline: oracle on {n} packets of the same torus (FP64, one core)")
+        o = oracle.Oracle(m)
+        t0 = time.perf_counter()
+        o.run(n=n, mode=oracle.BW_EPOCH, epoch=1 << 30, mrw_tau=50.0, n_total=N)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": n / dt, "unit": "packets/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} source packets of the 256^3 torus (no PAH stage, no ray-tracing), "
+                      f"FP64 Bjorkman & Wood with one epoch, {o.stats['crossings']} crossings in {dt:.1f} s",
+            "crossings_per_s": o.stats["crossings"] / dt,
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,225 @@
+/*
+ * mcrt.h - C ABI of the MI355X Monte Carlo dust radiative-transfer library.
+ *
+ * Method: Heymann & Siebenmorgen, "GPU-based Monte Carlo dust radiative
+ * transfer scheme applied to AGN". Photon packets of equal energy (sect. 2,
+ * Eq. 1) march cell by cell through a Cartesian dust grid, sample optical
+ * depth (Eqs. 2-3), scatter with the Henyey-Greenstein phase function
+ * (Eq. 15) or are absorbed and re-emitted (Eqs. 4-5 iterative scheme, Eq. 10
+ * Bjorkman & Wood), with Lucy's estimator in thin cells (sect. 3.1, Eq. 9),
+ * a modified random walk in very thick cells (sect. 3.2) and the PAH
+ * two-stage emission (sect. 2.1, Eqs. 6-7). A ray-tracer (sect. 4, Eqs.
+ * 11-17) forms images and SEDs; its adjoint gives d(loss)/d(density).
+ *
+ * Conventions
+ *  - cgs units; wavelengths in micrometres, strictly increasing.
+ *  - Grid: nx*ny*nz cubic cells of side `dcell` cm, low corner `origin`;
+ *    linear index (iz*ny + iy)*nx + ix (x fastest).
+ *  - Frequency integrals are sums over the wavelength grid with bin widths
+ *    w_j (Hz) spanning the geometric midpoints of neighbouring wavelengths.
+ *  - Per-species arrays are [ns][cells] or [ns][nl], species fastest-outer.
+ *  - `mem` says where a caller pointer lives: MCRT_HOST or MCRT_DEVICE
+ *    (a device pointer from the same GPU, e.g. torch.Tensor.data_ptr()).
+ *  - `stream` is a hipStream_t (NULL = default stream). Calls enqueue work
+ *    on it and return; results written to caller memory are complete after
+ *    the caller synchronises the stream. Host outputs are synchronous.
+ *  - Ownership: mcrt_set_* copy their inputs into library-owned device
+ *    memory; the library never keeps or frees caller pointers.
+ *  - Errors: every call returns an mcrt_status; mcrt_last_error(ctx) holds
+ *    the message until the next call on that context. Nothing is printed.
+ *  - One context per host thread at a time; calls on one context are not
+ *    thread-safe. Floating-point type of grids, images and gradients is the
+ *    context precision (MCRT_FP64 -> double, MCRT_FP32 -> float).
+ */
+#ifndef MCRT_H
+#define MCRT_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcrt_ctx mcrt_ctx;
+
+typedef enum {
+  MCRT_OK = 0,
+  MCRT_EINVAL = -1,  /* bad argument (shape, value, pointer) */
+  MCRT_ENOMEM = -2,  /* device allocation failed */
+  MCRT_ESTATE = -3,  /* call out of order (e.g. run before grid/dust/sources) */
+  MCRT_EDEVICE = -4  /* HIP runtime or kernel launch error */
+} mcrt_status;
+
+enum { MCRT_HOST = 0, MCRT_DEVICE = 1 };
+enum { MCRT_FP64 = 0, MCRT_FP32 = 1 };
+/* Re-emission rule: FROZEN = iterative scheme of sect. 2 (Eq. 5 with the
+ * previous pass's temperatures, n_iter passes, Eq. 4 after each);
+ * BW_EPOCH = Bjorkman & Wood (Eq. 10) with temperatures refreshed at fixed
+ * packet-id epochs (deterministic); BW_TICKET = Bjorkman & Wood with the
+ * temperature updated at every absorption (sect. 3.3; order set by the GPU). */
+enum { MCRT_FROZEN = 0, MCRT_BW_EPOCH = 1, MCRT_BW_TICKET = 2 };
+enum { MCRT_ESCAPED = 1, MCRT_KILLED = 2, MCRT_PAH_STOP = 3 };
+
+typedef struct {
+  int32_t mode;              /* MCRT_FROZEN / MCRT_BW_EPOCH / MCRT_BW_TICKET */
+  int32_t n_iter;            /* FROZEN passes (paper: 3-5) */
+  uint64_t epoch_packets;    /* BW_EPOCH epoch length in packet ids (>= 1) */
+  uint64_t n_total;          /* packets defining xi = L/n_total (0 -> n) */
+  double lucy_tau;           /* Lucy threshold on rho*max(kext)*dcell; <= 0 off (paper 1e-2) */
+  double mrw_tau;            /* MRW on cells with Rosseland depth > mrw_tau; <= 0 off */
+  double mrw_gamma;          /* MRW sphere >= gamma Rosseland mean free paths */
+  uint64_t max_interactions; /* per-packet cap; 0 = none; capped packets are killed */
+  int32_t sed_theta_bins;    /* photon-counting SED bins, equal in cos(theta) */
+  int32_t record;            /* 1: keep one mcrt_packet_record per packet */
+  int32_t block_size;        /* threads per block, multiple of 64 up to 256 (0 = 256) */
+  int32_t blocks_per_cu;     /* persistent blocks per compute unit (0 = 4) */
+} mcrt_run_opts;
+
+typedef struct {
+  uint64_t packets, escaped, killed, pah_stopped, crossings, scatters,
+      absorptions, mrw_steps, lucy_deposits, clamped_T;
+  double kernel_ms;          /* device time of the transport launches */
+} mcrt_run_stats;
+
+typedef struct {
+  uint64_t pid;
+  double pos[3], dir[3];     /* escape/stop point (cm) and direction */
+  int32_t j, status;         /* wavelength index, MCRT_ESCAPED/KILLED/PAH_STOP */
+  double weight;             /* packet energy xi (erg/s) */
+  uint64_t n_cross, n_scat, n_abs, n_mrw, n_lucy;
+  double min_margin;         /* distance of the closest decision from a tie */
+} mcrt_packet_record;
+
+/* Create a context on HIP device `device` computing in `precision`
+ * (MCRT_FP64 or MCRT_FP32; FP32 keeps Eq. 4 and the diffusion solve in
+ * FP64 and accumulates energies in FP64). *out is NULL on failure. */
+mcrt_status mcrt_create(mcrt_ctx **out, int device, int precision);
+/* Free all device memory of the context. NULL is accepted. */
+void mcrt_destroy(mcrt_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none); NULL ctx -> creation error. */
+const char *mcrt_last_error(const mcrt_ctx *ctx);
+
+/* Grid of sect. 2: cubes of constant density rho (g/cm^3, [nz][ny][nx]).
+ * dtype MCRT_FP64 (double) or MCRT_FP32 (float); converted to the context
+ * precision. EINVAL: n <= 0, dcell <= 0, rho negative or not finite.
+ * Resets tallies and temperatures. */
+mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
+                          double dcell, const void *rho, int dtype, int mem);
+/* Clumpy torus of sect. 6 (Eq. 21 clump centres given, host [n][3] cm):
+ * a cell takes rho_clump if its centre lies inside any clump (overlaps keep
+ * the single-clump density), rho_inter inside the wedge r_in <= r <= r_out,
+ * |z| <= r sin_theta1, else 0. Builds the grid on the device. */
+mcrt_status mcrt_voxelize_torus(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
+                                double dcell, int n_clumps, const double *centres,
+                                double r_clump, double rho_clump, double rho_inter,
+                                double r_in, double r_out, double sin_theta1);
+/* Spherical shell rho0 (r_in/r)^2 on [r_in, r_out], cell averages by an
+ * 8^3 Gauss-Legendre rule (the shell of sect. 3.6 / 5.1). */
+mcrt_status mcrt_voxelize_shell(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
+                                double dcell, double rho0, double r_in, double r_out);
+
+/* Dust of sect. 2: n_lambda wavelengths (um, increasing, 2..256), n_species
+ * (1..4) with mass fractions and kabs, ksca (cm^2 per g of dust) and HG g,
+ * each [ns][nl] (host). pah_species = -1 or the species treated as PAH
+ * (sect. 2.1) with n_pah_rows emissivity rows eps_n [rows][nl] and rows-1
+ * increasing edges on the absorbed PAH power per PAH mass and steradian. */
+mcrt_status mcrt_set_dust(mcrt_ctx *ctx, int n_lambda, const double *lambda_um, int n_species,
+                          const double *mass_frac, const double *kabs, const double *ksca,
+                          const double *g, int pah_species, int n_pah_rows,
+                          const double *pah_emis, const double *pah_row_edges);
+/* Point sources (host): positions [n][3] cm inside the grid, luminosities
+ * erg/s, spectral shape ~L_nu [n][nl] or NULL with blackbody temperatures
+ * t_bb [n]. 1 <= n <= 8. */
+mcrt_status mcrt_set_sources(mcrt_ctx *ctx, int n_src, const double *pos_cm, const double *lum,
+                             const double *lnu_shape, const double *t_bb);
+/* Observer views for scattering events and the ray-tracer (sect. 4):
+ * (theta, phi) degrees [n][2] (n <= 16), imaged wavelength indices
+ * [n_img] (<= 16, distinct), distance D in cm. */
+mcrt_status mcrt_set_views(mcrt_ctx *ctx, int n_views, const double *theta_phi_deg,
+                           int n_img, const int32_t *lambda_idx, double distance_cm);
+
+/* Zero counts, energies, PAH counts, SED, scattering events and epoch state. */
+mcrt_status mcrt_reset(mcrt_ctx *ctx, void *stream);
+/* Initial guess of the iterative scheme: optically thin equilibrium
+ * temperature at every cell centre (Eq. 4 with the unattenuated sources). */
+mcrt_status mcrt_init_temperatures(mcrt_ctx *ctx, void *stream);
+/* Replace temperatures [ns][cells] (FP64). */
+mcrt_status mcrt_set_temperatures(mcrt_ctx *ctx, const double *T, int mem, void *stream);
+/* Replace the HG-weighted scattering sums [views][n_img][cells] (FP64, erg/s/sr). */
+mcrt_status mcrt_set_scattering(mcrt_ctx *ctx, const double *ssca, int mem, void *stream);
+
+/* Transport packets first .. first+n-1 with the counter-based stream of
+ * `seed` (Philox4x32-10 keyed by seed, counter = draw block, packet id,
+ * iteration, model and stream tag). Tallies accumulate across calls, so a
+ * run split into consecutive ranges equals the whole run (FROZEN resets per
+ * pass). `stats` (nullable) receives counters after the call completes
+ * (the call then synchronises the stream). ESTATE before grid, dust and
+ * sources are set; EINVAL for bad options. */
+mcrt_status mcrt_run_packets(mcrt_ctx *ctx, uint64_t first, uint64_t n, uint64_t seed,
+                             const mcrt_run_opts *opts, mcrt_run_stats *stats, void *stream);
+/* Second PAH stage (sect. 2.1): every cell re-emits its pass-1 PAH
+ * absorptions with wavelengths from its eps_n row (Eq. 7) and the packets
+ * are transported as in run_packets (ids n_total + prefix). */
+mcrt_status mcrt_run_pah(mcrt_ctx *ctx, uint64_t seed, const mcrt_run_opts *opts,
+                         mcrt_run_stats *stats, void *stream);
+/* Eq. 4 for every cell and thermal species from the tallies: T_out
+ * [ns][cells] FP64 (PAH species and empty cells 0); E_out (nullable)
+ * absorbed power [ns][cells] FP64 erg/s. */
+mcrt_status mcrt_temperatures(mcrt_ctx *ctx, double *T_out, double *E_out, int mem, void *stream);
+/* Copy of the context's temperature field [ns][cells] FP64 as it stands
+ * (initial guess, values set by the caller, or the last Eq. 4 result);
+ * unlike mcrt_temperatures nothing is recomputed. */
+mcrt_status mcrt_get_temperatures(mcrt_ctx *ctx, double *T_out, int mem, void *stream);
+/* Copy of the grid density [cells] in the context precision. */
+mcrt_status mcrt_density(mcrt_ctx *ctx, void *rho_out, int mem, void *stream);
+/* Raw tallies: counts [ns][cells] u64, path energy [ns][cells] FP64,
+ * PAH counts [cells] u32 (each nullable). */
+mcrt_status mcrt_tallies(mcrt_ctx *ctx, uint64_t *k_out, double *epath_out, uint32_t *kpah_out,
+                         int mem, void *stream);
+/* Photon-counting SED (sect. 4): flux density [theta_bins][nl] in
+ * erg/s/cm^2/Hz at the view distance (counts * xi / (dOmega D^2 w_j)),
+ * and raw counts (nullable). */
+mcrt_status mcrt_sed(mcrt_ctx *ctx, double *sed_out, uint64_t *counts_out, int mem, void *stream);
+/* HG-weighted scattering sums [views][n_img][cells] FP64. */
+mcrt_status mcrt_scattering(mcrt_ctx *ctx, double *ssca_out, int mem, void *stream);
+/* Copy min(n, recorded) packet records of the last run_packets/run_pah
+ * call with record = 1 (host or device destination). */
+mcrt_status mcrt_packet_records(mcrt_ctx *ctx, mcrt_packet_record *out, uint64_t n, int mem);
+
+/* Ray-tracer (sect. 4, Eqs. 11-17): npx*npy parallel rays per view over a
+ * square field of side sqrt(3)*max box edge, front to back; per cell
+ * S = sum_s f_s kabs_s B(T_s)/kext + Ssca/(V w rho kext) and
+ * I += T S (1 - e^-dtau), T *= e^-dtau with dtau = rho kext l; pixel flux
+ * A_pix I / D^2 plus attenuated point sources. img_out [views][n_img][npy][npx]
+ * (context precision), sed_out [views][n_img] FP64 (nullable).
+ * rho_rt (nullable, device, context precision) replaces the grid density in
+ * dtau only; S keeps the grid's values (emissivity per unit mass fixed). */
+mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt,
+                                void *img_out, double *sed_out, int mem, void *stream);
+/* Adjoint of mcrt_raytrace_image: given dL/dimg (context precision,
+ * nullable) and dL/dsed (FP64, nullable), writes dL/drho_rt [cells]
+ * (context precision). Transmittance is recomputed in a second front-to-
+ * back sweep per ray; nothing of the forward pass is stored. */
+mcrt_status mcrt_raytrace_adjoint(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt,
+                                  const void *dL_dimg, const double *dL_dsed, void *dL_drho,
+                                  int mem, void *stream);
+
+/* Batched transport: n_models contexts (same device and precision, each
+ * with grid, dust and sources set) run packets 0..n_packets[m]-1 with
+ * seeds[m] in one persistent launch captured in a HIP graph; blocks pick
+ * models with work left and refill their lanes from per-model counters.
+ * Modes FROZEN (n_iter = 1) and BW_TICKET. Tallies are reset first and
+ * temperatures finalised (Eq. 4, FP64) inside the same graph. stats
+ * (nullable) [n_models]. */
+mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models, const uint64_t *n_packets,
+                           const uint64_t *seeds, const mcrt_run_opts *opts,
+                           mcrt_run_stats *stats, void *stream);
+
+/* Device time in ms of the last ray-tracer forward / adjoint kernel and of
+ * the last transport launch sequence (HIP events on the call's stream). */
+mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_ms, double *rt_fwd_ms,
+                              double *rt_adj_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

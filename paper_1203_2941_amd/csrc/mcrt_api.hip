@@ -1,0 +1,1439 @@
+// mcrt_api.hip - host side of the C ABI declared in include/mcrt.h.
+//
+// Owns device memory per context, validates inputs, builds the packed
+// per-model tables (frequency quadrature, mixture opacities, Planck
+// constants, source spectra, ln Phi(ln T) tables for Eq. 4) and sequences
+// the kernels: epochs of the Bjorkman & Wood mode, passes of the iterative
+// scheme, the PAH second stage, the ray-tracer and its adjoint, and the
+// batched launch captured in a HIP graph.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mcrt.h"
+#include "mcrt_rtargs.h"
+
+namespace mcrt {
+size_t transport_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64);
+hipError_t launch_transport(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int grid,
+                            int block, size_t lds, hipStream_t st);
+hipError_t launch_epoch_snapshot(const ModelDev *d, hipStream_t st);
+hipError_t launch_finalize_T(const ModelDev *d, bool fp64, double *T, double *E, hipStream_t st);
+hipError_t launch_init_T(const ModelDev *d, bool fp64, double *T, hipStream_t st);
+hipError_t launch_build_S(const ModelDev *d, int v, bool fp64, void *S, hipStream_t st);
+hipError_t launch_vox_torus(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
+                            int ncl, const double *dC, double r_clump, double rho_cl,
+                            double rho_int, double r_in, double r_out, double s1, void *rho,
+                            hipStream_t st);
+hipError_t launch_vox_shell(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
+                            double rho0, double r_in, double r_out, int ng, const double *dgx,
+                            const double *dgw, void *rho, hipStream_t st);
+hipError_t launch_rt_fwd(const RtArgs *dA, const RtArgs &hA, bool fp64, void *img, double *sed,
+                         hipStream_t st);
+hipError_t launch_rt_adj(const RtArgs *dA, const RtArgs &hA, bool fp64, const void *w_img,
+                         const double *w_sed, void *drho, hipStream_t st);
+}  // namespace mcrt
+
+using namespace mcrt;
+
+struct mcrt_ctx {
+  int device = 0;
+  bool fp64 = true;
+  std::string err;
+  // grid
+  bool has_grid = false;
+  int nx = 0, ny = 0, nz = 0;
+  double origin[3] = {0, 0, 0}, dcell = 0;
+  uint64_t ncell = 0;
+  void *d_rho = nullptr;
+  // dust
+  bool has_dust = false;
+  int nl = 0, ns = 0, pah = -1, nrows = 0;
+  std::vector<double> lam, frac, kabs, ksca, g, pah_emis, pah_edges;
+  // sources
+  bool has_src = false;
+  int nsrc = 0;
+  std::vector<double> src_pos, src_lum, src_lnu;  // lnu [nsrc][nl] erg/s/Hz
+  // views
+  int nview = 0, nimg = 0;
+  std::vector<double> views;
+  std::vector<int32_t> img_idx;
+  double distance = 1.0;
+  // tables
+  std::vector<double> h_tab;
+  double kext_max = 0.0, ltot = 0.0;
+  double *d_tab = nullptr;
+  void *d_rtab = nullptr;
+  int32_t *d_imgmap = nullptr;
+  size_t tab_cap = 0, rtab_cap = 0;
+  bool tables_ok = false;
+  // state
+  uint64_t state_cells = 0;
+  int state_ns = 0;
+  uint64_t *d_k = nullptr;
+  double *d_epath = nullptr, *d_T = nullptr, *d_esnap = nullptr, *d_tt = nullptr, *d_tmp = nullptr;
+  uint8_t *d_dirty = nullptr;
+  uint32_t *d_kpah = nullptr;
+  uint64_t *d_prefix = nullptr;
+  uint64_t *d_sed = nullptr;
+  int sed_cap = 0, ntheta = 10;
+  void *d_ssca = nullptr;
+  size_t ssca_cap = 0;
+  void *d_rec = nullptr;
+  uint64_t rec_cap = 0, rec_n = 0;
+  uint64_t *d_counter = nullptr;
+  unsigned long long *d_stats = nullptr;
+  ModelDev *d_model = nullptr;
+  ModelDev h_model;
+  double xi = 0.0;
+  uint64_t n_total = 0;
+  // ray-tracer
+  void *d_S = nullptr;
+  size_t S_cap = 0;
+  bool S_ok = false;
+  RtArgs *d_rt = nullptr;
+  void *d_img_tmp = nullptr;
+  size_t img_cap = 0;
+  double *d_sed_tmp = nullptr;
+  // staging (pinned) for small structures
+  void *h_stage = nullptr;
+  hipEvent_t ev_stage = nullptr, ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evf0 = nullptr, evf1 = nullptr, eva0 = nullptr, eva1 = nullptr;
+  bool have_f = false, have_a = false;
+  double t_transport = 0.0;
+  size_t sed_tmp_cap = 0;
+  size_t lds_max = 65536;
+  int num_cu = 256;
+  // batch
+  ModelDev *d_batch = nullptr;
+  int batch_cap = 0;
+  void *d_temp = nullptr;
+  size_t temp_cap = 0;
+};
+
+static thread_local std::string g_create_err;
+
+static mcrt_status fail(mcrt_ctx *c, mcrt_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf; else g_create_err = buf;
+  return s;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? MCRT_ENOMEM : MCRT_EDEVICE, "%s: %s", \
+                  #call, hipGetErrorString(e_));                                      \
+  } while (0)
+
+static hipError_t dev_alloc(void **p, size_t bytes) {
+  if (*p) {
+    (void)hipFree(*p);
+    *p = nullptr;
+  }
+  if (bytes == 0) return hipSuccess;
+  return hipMalloc(p, bytes);
+}
+
+template <typename T>
+static hipError_t fill(T *p, T v, uint64_t n, hipStream_t st) {
+  if (!p || n == 0) return hipSuccess;
+  unsigned g = (unsigned)((n + 255) / 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+// Small structures go through one pinned buffer; the event guards reuse.
+static hipError_t stage_copy(mcrt_ctx *ctx, void *dst, const void *src, size_t bytes,
+                             hipStream_t st) {
+  hipError_t e = hipEventSynchronize(ctx->ev_stage);
+  if (e != hipSuccess) return e;
+  memcpy(ctx->h_stage, src, bytes);
+  e = hipMemcpyAsync(dst, ctx->h_stage, bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(ctx->ev_stage, st);
+}
+
+static const size_t STAGE_BYTES = 1 << 20;
+
+extern "C" mcrt_status mcrt_create(mcrt_ctx **out, int device, int precision) {
+  mcrt_ctx *ctx = nullptr;
+  if (!out) return fail(nullptr, MCRT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (precision != MCRT_FP64 && precision != MCRT_FP32)
+    return fail(nullptr, MCRT_EINVAL, "precision must be MCRT_FP64 or MCRT_FP32");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, MCRT_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(nullptr, MCRT_EINVAL, "device %d out of range", device);
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, MCRT_EDEVICE, "hipSetDevice failed");
+  ctx = new mcrt_ctx();
+  ctx->device = device;
+  ctx->fp64 = (precision == MCRT_FP64);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    ctx->num_cu = prop.multiProcessorCount;
+    ctx->lds_max = prop.sharedMemPerBlock;
+  }
+  if (hipHostMalloc(&ctx->h_stage, STAGE_BYTES, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&ctx->ev_stage) != hipSuccess || hipEventCreate(&ctx->ev0) != hipSuccess ||
+      hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->evf0) != hipSuccess ||
+      hipEventCreate(&ctx->evf1) != hipSuccess || hipEventCreate(&ctx->eva0) != hipSuccess ||
+      hipEventCreate(&ctx->eva1) != hipSuccess ||
+      hipMalloc((void **)&ctx->d_counter, sizeof(uint64_t)) != hipSuccess ||
+      hipMalloc((void **)&ctx->d_stats, sizeof(unsigned long long) * NSTAT) != hipSuccess ||
+      hipMalloc((void **)&ctx->d_model, sizeof(ModelDev)) != hipSuccess ||
+      hipMalloc((void **)&ctx->d_rt, sizeof(RtArgs)) != hipSuccess) {
+    mcrt_destroy(ctx);
+    return fail(nullptr, MCRT_ENOMEM, "context allocation failed");
+  }
+  (void)hipEventRecord(ctx->ev_stage, 0);
+  *out = ctx;
+  return MCRT_OK;
+}
+
+extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  void *ps[] = {ctx->d_rho, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_k, ctx->d_epath,
+                ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
+                ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_counter, ctx->d_stats,
+                ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
+                ctx->d_temp};
+  for (void *p : ps)
+    if (p) (void)hipFree(p);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  hipEvent_t evs[] = {ctx->evf0, ctx->evf1, ctx->eva0, ctx->eva1};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+extern "C" const char *mcrt_last_error(const mcrt_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+static size_t rsize(const mcrt_ctx *c) { return c->fp64 ? 8 : 4; }
+
+// ----------------------------------------------------------------- state
+
+static mcrt_status ensure_state(mcrt_ctx *ctx, hipStream_t st) {
+  if (ctx->state_cells == ctx->ncell && ctx->state_ns == ctx->ns && ctx->d_k) return MCRT_OK;
+  uint64_t n = ctx->ncell * (uint64_t)ctx->ns;
+  HIPCHK(dev_alloc((void **)&ctx->d_k, n * 8));
+  HIPCHK(dev_alloc((void **)&ctx->d_epath, n * 8));
+  HIPCHK(dev_alloc((void **)&ctx->d_T, n * 8));
+  HIPCHK(dev_alloc((void **)&ctx->d_esnap, n * 8));
+  HIPCHK(dev_alloc((void **)&ctx->d_tt, n * 8));
+  HIPCHK(dev_alloc((void **)&ctx->d_tmp, n * 8));
+  HIPCHK(dev_alloc((void **)&ctx->d_dirty, ctx->ncell));
+  HIPCHK(dev_alloc((void **)&ctx->d_kpah, ctx->ncell * 4));
+  HIPCHK(dev_alloc((void **)&ctx->d_prefix, ctx->ncell * 8));
+  ctx->state_cells = ctx->ncell;
+  ctx->state_ns = ctx->ns;
+  HIPCHK(fill<double>(ctx->d_T, 0.0, n, st));
+  HIPCHK(fill<uint64_t>(ctx->d_k, 0ull, n, st));
+  HIPCHK(fill<double>(ctx->d_epath, 0.0, n, st));
+  HIPCHK(fill<uint32_t>(ctx->d_kpah, 0u, ctx->ncell, st));
+  HIPCHK(fill<double>(ctx->d_esnap, 0.0, n, st));
+  HIPCHK(fill<double>(ctx->d_tt, -1.0, n, st));
+  HIPCHK(fill<uint8_t>(ctx->d_dirty, (uint8_t)0, ctx->ncell, st));
+  ctx->ssca_cap = 0;
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+static mcrt_status ensure_ssca(mcrt_ctx *ctx) {
+  size_t need = (size_t)ctx->nview * ctx->nimg * ctx->ncell * rsize(ctx);
+  if (need == 0) return MCRT_OK;
+  if (ctx->ssca_cap == need && ctx->d_ssca) return MCRT_OK;
+  HIPCHK(dev_alloc(&ctx->d_ssca, need));
+  ctx->ssca_cap = need;
+  HIPCHK(hipMemset(ctx->d_ssca, 0, need));
+  HIPCHK(hipDeviceSynchronize());
+  return MCRT_OK;
+}
+
+static mcrt_status ensure_sed(mcrt_ctx *ctx, int ntheta) {
+  int need = ntheta * ctx->nl;
+  if (ctx->sed_cap == need && ctx->d_sed) return MCRT_OK;
+  HIPCHK(dev_alloc((void **)&ctx->d_sed, (size_t)need * 8));
+  ctx->sed_cap = need;
+  HIPCHK(hipMemset(ctx->d_sed, 0, (size_t)need * 8));
+  HIPCHK(hipDeviceSynchronize());
+  return MCRT_OK;
+}
+
+static mcrt_status zero_tallies(mcrt_ctx *ctx, hipStream_t st) {
+  uint64_t n = ctx->ncell * (uint64_t)ctx->ns;
+  HIPCHK(fill<uint64_t>(ctx->d_k, 0ull, n, st));
+  HIPCHK(fill<double>(ctx->d_epath, 0.0, n, st));
+  HIPCHK(fill<uint32_t>(ctx->d_kpah, 0u, ctx->ncell, st));
+  HIPCHK(fill<uint64_t>(ctx->d_sed, 0ull, (uint64_t)ctx->sed_cap, st));
+  if (ctx->d_ssca) {
+    uint64_t m = (uint64_t)ctx->nview * ctx->nimg * ctx->ncell;
+    if (ctx->fp64) HIPCHK(fill<double>((double *)ctx->d_ssca, 0.0, m, st));
+    else HIPCHK(fill<float>((float *)ctx->d_ssca, 0.0f, m, st));
+  }
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+static mcrt_status zero_epoch(mcrt_ctx *ctx, hipStream_t st) {
+  uint64_t n = ctx->ncell * (uint64_t)ctx->ns;
+  HIPCHK(fill<double>(ctx->d_esnap, 0.0, n, st));
+  HIPCHK(fill<double>(ctx->d_tt, -1.0, n, st));
+  HIPCHK(fill<uint8_t>(ctx->d_dirty, (uint8_t)0, ctx->ncell, st));
+  return MCRT_OK;
+}
+
+// ---------------------------------------------------------------- tables
+
+static double h_planck(double nu, double T) {
+  if (!(T > 0.0)) return 0.0;
+  double x = H_PL * nu / (K_BO * T);
+  if (x > 700.0) return 0.0;
+  return 2.0 * H_PL * nu * nu * nu / (C_LI * C_LI) / expm1(x);
+}
+
+static mcrt_status build_tables(mcrt_ctx *ctx) {
+  if (!(ctx->has_dust && ctx->has_src)) return MCRT_OK;
+  const int nl = ctx->nl, ns = ctx->ns;
+  TabOff o = tab_offsets(nl, ns, ctx->nsrc, ctx->nrows);
+  std::vector<double> t(o.dtotal, 0.0);
+  std::vector<double> nu(nl), w(nl);
+  for (int j = 0; j < nl; ++j) nu[j] = C_LI / (ctx->lam[j] * 1e-4);
+  for (int j = 0; j < nl; ++j) {
+    const double *L = ctx->lam.data();
+    double lo = (j == 0) ? L[0] * std::sqrt(L[0] / L[1]) : std::sqrt(L[j - 1] * L[j]);
+    double hi = (j == nl - 1) ? L[nl - 1] * std::sqrt(L[nl - 1] / L[nl - 2]) : std::sqrt(L[j] * L[j + 1]);
+    w[j] = C_LI / (lo * 1e-4) - C_LI / (hi * 1e-4);
+  }
+  std::vector<double> kabsm(nl), kscam(nl), kext(nl);
+  ctx->kext_max = 0.0;
+  for (int j = 0; j < nl; ++j) {
+    double a = 0.0, s = 0.0;
+    for (int q = 0; q < ns; ++q) {
+      a += ctx->frac[q] * ctx->kabs[q * nl + j];
+      s += ctx->frac[q] * ctx->ksca[q * nl + j];
+    }
+    kabsm[j] = a;
+    kscam[j] = s;
+    kext[j] = a + s;
+    if (kext[j] > ctx->kext_max) ctx->kext_max = kext[j];
+  }
+  for (int j = 0; j < nl; ++j) {
+    t[o.w + j] = w[j];
+    t[o.hnu + j] = H_PL * nu[j];
+    t[o.a + j] = 2.0 * H_PL * nu[j] * nu[j] * nu[j] / (C_LI * C_LI);
+    t[o.kext + j] = kext[j];
+    for (int s = 0; s < ns; ++s) {
+      t[o.wk + s * nl + j] = w[j] * ctx->kabs[s * nl + j];
+      t[o.wfk + s * nl + j] = w[j] * ctx->frac[s] * ctx->kabs[s * nl + j];
+      t[o.kabs + s * nl + j] = ctx->kabs[s * nl + j];
+    }
+  }
+  for (int s = 0; s < ns; ++s) t[o.frac + s] = ctx->frac[s];
+  ctx->ltot = 0.0;
+  for (int s = 0; s < ctx->nsrc; ++s) {
+    for (int j = 0; j < nl; ++j) {
+      t[o.lnu + s * nl + j] = ctx->src_lnu[s * nl + j];
+      t[o.srcf + s * nl + j] = w[j] * ctx->src_lnu[s * nl + j];
+    }
+    t[o.lum + s] = ctx->src_lum[s];
+    for (int k = 0; k < 3; ++k) t[o.srcpos + 3 * s + k] = ctx->src_pos[3 * s + k];
+    ctx->ltot += ctx->src_lum[s];
+  }
+  for (int r = 0; r < ctx->nrows; ++r) {
+    for (int j = 0; j < nl; ++j) t[o.pahw + r * nl + j] = w[j] * ctx->pah_emis[r * nl + j];
+    if (r < ctx->nrows - 1) t[o.pahe + r] = ctx->pah_edges[r];
+  }
+  const double lt0 = std::log(T_TAB_MIN), dlt = (std::log(T_MAX) - lt0) / (NT_TAB - 1);
+  for (int s = 0; s < ns; ++s)
+    for (int k = 0; k < NT_TAB; ++k) {
+      double T = std::exp(lt0 + k * dlt), ph = 0.0;
+      for (int j = nl - 1; j >= 0; --j) ph += t[o.wk + s * nl + j] * h_planck(nu[j], T);
+      t[o.logphi + s * NT_TAB + k] = std::log(ph);  // -inf where Phi underflows
+    }
+  // walk-precision table
+  std::vector<double> r(o.r_total, 0.0);
+  for (int j = 0; j < nl; ++j) {
+    r[o.r_kext + j] = kext[j];
+    r[o.r_kabsm + j] = kabsm[j];
+    r[o.r_alb + j] = (kext[j] > 0.0) ? kscam[j] / kext[j] : 0.0;
+    r[o.r_hnu + j] = t[o.hnu + j];
+    r[o.r_a + j] = t[o.a + j];
+    for (int s = 0; s < ns; ++s) {
+      r[o.r_fsca + s * nl + j] = ctx->frac[s] * ctx->ksca[s * nl + j];
+      r[o.r_fabs + s * nl + j] = ctx->frac[s] * ctx->kabs[s * nl + j];
+      r[o.r_g + s * nl + j] = ctx->g[s * nl + j];
+      r[o.r_lucy + s * nl + j] =
+          (s != ctx->pah && kabsm[j] > 0.0) ? ctx->frac[s] * ctx->kabs[s * nl + j] / kabsm[j] : 0.0;
+      r[o.r_wk + s * nl + j] = t[o.wk + s * nl + j];
+    }
+  }
+  std::vector<int32_t> im(nl, -1);
+  for (int q = 0; q < ctx->nimg; ++q) im[ctx->img_idx[q]] = q;
+  mcrt_ctx *c = ctx;
+  size_t tb = (size_t)o.dtotal * 8, rb = (size_t)o.r_total * rsize(c);
+  if (tb > ctx->tab_cap) {
+    HIPCHK(dev_alloc((void **)&ctx->d_tab, tb));
+    ctx->tab_cap = tb;
+  }
+  if (rb > ctx->rtab_cap) {
+    HIPCHK(dev_alloc(&ctx->d_rtab, rb));
+    ctx->rtab_cap = rb;
+  }
+  HIPCHK(dev_alloc((void **)&ctx->d_imgmap, (size_t)nl * 4));
+  HIPCHK(hipMemcpy(ctx->d_tab, t.data(), tb, hipMemcpyHostToDevice));
+  if (ctx->fp64) {
+    HIPCHK(hipMemcpy(ctx->d_rtab, r.data(), rb, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> rf(r.begin(), r.end());
+    HIPCHK(hipMemcpy(ctx->d_rtab, rf.data(), rb, hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMemcpy(ctx->d_imgmap, im.data(), (size_t)nl * 4, hipMemcpyHostToDevice));
+  ctx->h_tab = t;
+  ctx->tables_ok = true;
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+// ------------------------------------------------------------------- set
+
+static bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+extern "C" mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
+                                     double dcell, const void *rho, int dtype, int mem) {
+  if (!ctx) return MCRT_EINVAL;
+  if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, MCRT_EINVAL, "grid dimensions must be > 0");
+  if (!origin || !rho) return fail(ctx, MCRT_EINVAL, "origin and rho must be non-NULL");
+  if (!(dcell > 0.0) || !std::isfinite(dcell)) return fail(ctx, MCRT_EINVAL, "dcell must be > 0");
+  if (dtype != MCRT_FP64 && dtype != MCRT_FP32) return fail(ctx, MCRT_EINVAL, "bad dtype");
+  if (mem != MCRT_HOST && mem != MCRT_DEVICE) return fail(ctx, MCRT_EINVAL, "bad mem flag");
+  uint64_t n = (uint64_t)nx * ny * nz;
+  if (n > (1ull << 34)) return fail(ctx, MCRT_EINVAL, "grid too large");
+  HIPCHK(hipSetDevice(ctx->device));
+  // copy to host for validation and conversion
+  std::vector<double> h(n);
+  size_t es = dtype == MCRT_FP64 ? 8 : 4;
+  std::vector<unsigned char> raw(n * es);
+  if (mem == MCRT_DEVICE) HIPCHK(hipMemcpy(raw.data(), rho, n * es, hipMemcpyDeviceToHost));
+  else memcpy(raw.data(), rho, n * es);
+  for (uint64_t i = 0; i < n; ++i) {
+    double v = dtype == MCRT_FP64 ? ((double *)raw.data())[i] : (double)((float *)raw.data())[i];
+    if (!finite_nonneg(v)) return fail(ctx, MCRT_EINVAL, "rho[%llu] is negative or not finite", (unsigned long long)i);
+    h[i] = v;
+  }
+  HIPCHK(dev_alloc(&ctx->d_rho, n * rsize(ctx)));
+  if (ctx->fp64) {
+    HIPCHK(hipMemcpy(ctx->d_rho, h.data(), n * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(h.begin(), h.end());
+    HIPCHK(hipMemcpy(ctx->d_rho, f.data(), n * 4, hipMemcpyHostToDevice));
+  }
+  ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
+  for (int k = 0; k < 3; ++k) ctx->origin[k] = origin[k];
+  ctx->dcell = dcell;
+  ctx->ncell = n;
+  ctx->has_grid = true;
+  ctx->S_ok = false;
+  if (ctx->has_dust) {
+    mcrt_status s = ensure_state(ctx, 0);
+    if (s) return s;
+    s = zero_tallies(ctx, 0);
+    if (s) return s;
+    s = zero_epoch(ctx, 0);
+    if (s) return s;
+    HIPCHK(hipDeviceSynchronize());
+  }
+  return MCRT_OK;
+}
+
+static mcrt_status grid_geom(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3], double dcell) {
+  if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, MCRT_EINVAL, "grid dimensions must be > 0");
+  if (!origin) return fail(ctx, MCRT_EINVAL, "origin is NULL");
+  if (!(dcell > 0.0) || !std::isfinite(dcell)) return fail(ctx, MCRT_EINVAL, "dcell must be > 0");
+  uint64_t n = (uint64_t)nx * ny * nz;
+  if (n > (1ull << 34)) return fail(ctx, MCRT_EINVAL, "grid too large");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(dev_alloc(&ctx->d_rho, n * rsize(ctx)));
+  ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
+  for (int k = 0; k < 3; ++k) ctx->origin[k] = origin[k];
+  ctx->dcell = dcell;
+  ctx->ncell = n;
+  return MCRT_OK;
+}
+
+static mcrt_status grid_done(mcrt_ctx *ctx) {
+  ctx->has_grid = true;
+  ctx->S_ok = false;
+  if (ctx->has_dust) {
+    mcrt_status s = ensure_state(ctx, 0);
+    if (s) return s;
+    s = zero_tallies(ctx, 0);
+    if (s) return s;
+    s = zero_epoch(ctx, 0);
+    if (s) return s;
+  }
+  HIPCHK(hipDeviceSynchronize());
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_voxelize_torus(mcrt_ctx *ctx, int nx, int ny, int nz,
+                                           const double origin[3], double dcell, int n_clumps,
+                                           const double *centres, double r_clump,
+                                           double rho_clump, double rho_inter, double r_in,
+                                           double r_out, double sin_theta1) {
+  if (!ctx) return MCRT_EINVAL;
+  if (n_clumps < 0 || (n_clumps > 0 && !centres)) return fail(ctx, MCRT_EINVAL, "bad clump list");
+  if (!finite_nonneg(rho_clump) || !finite_nonneg(rho_inter) || !finite_nonneg(r_clump) ||
+      !finite_nonneg(r_in) || !(r_out >= r_in) || !(sin_theta1 >= 0.0 && sin_theta1 <= 1.0))
+    return fail(ctx, MCRT_EINVAL, "bad torus parameters");
+  mcrt_status s = grid_geom(ctx, nx, ny, nz, origin, dcell);
+  if (s) return s;
+  double *dC = nullptr;
+  if (n_clumps > 0) {
+    HIPCHK(hipMalloc((void **)&dC, (size_t)n_clumps * 24));
+    HIPCHK(hipMemcpy(dC, centres, (size_t)n_clumps * 24, hipMemcpyHostToDevice));
+  }
+  hipError_t e = launch_vox_torus(ctx->fp64, nx, ny, nz, origin, dcell, n_clumps, dC, r_clump,
+                                  rho_clump, rho_inter, r_in, r_out, sin_theta1, ctx->d_rho, 0);
+  hipError_t e2 = hipDeviceSynchronize();
+  if (dC) (void)hipFree(dC);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(ctx, MCRT_EDEVICE, "torus voxelizer: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  return grid_done(ctx);
+}
+
+// Gauss-Legendre rule: roots of P_n by Newton from Chebyshev-like guesses.
+static void gl_rule(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double pm = 1.0, pc = z;  // P_0, P_1
+      for (int k = 2; k <= n; ++k) {
+        double pn = ((2.0 * k - 1.0) * z * pc - (k - 1.0) * pm) / k;
+        pm = pc;
+        pc = pn;
+      }
+      dp = n * (z * pc - pm) / (z * z - 1.0);
+      double dz = pc / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-15) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+extern "C" mcrt_status mcrt_voxelize_shell(mcrt_ctx *ctx, int nx, int ny, int nz,
+                                           const double origin[3], double dcell, double rho0,
+                                           double r_in, double r_out) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!finite_nonneg(rho0) || !(r_in > 0.0) || !(r_out >= r_in) || !std::isfinite(r_out))
+    return fail(ctx, MCRT_EINVAL, "bad shell parameters");
+  mcrt_status s = grid_geom(ctx, nx, ny, nz, origin, dcell);
+  if (s) return s;
+  std::vector<double> gx, gw;
+  gl_rule(8, gx, gw);
+  double *dg = nullptr;
+  HIPCHK(hipMalloc((void **)&dg, 16 * 8));
+  HIPCHK(hipMemcpy(dg, gx.data(), 64, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dg + 8, gw.data(), 64, hipMemcpyHostToDevice));
+  hipError_t e = launch_vox_shell(ctx->fp64, nx, ny, nz, origin, dcell, rho0, r_in, r_out, 8, dg,
+                                  dg + 8, ctx->d_rho, 0);
+  hipError_t e2 = hipDeviceSynchronize();
+  (void)hipFree(dg);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(ctx, MCRT_EDEVICE, "shell voxelizer: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  return grid_done(ctx);
+}
+
+extern "C" mcrt_status mcrt_set_dust(mcrt_ctx *ctx, int n_lambda, const double *lambda_um,
+                                     int n_species, const double *mass_frac, const double *kabs,
+                                     const double *ksca, const double *g, int pah_species,
+                                     int n_pah_rows, const double *pah_emis,
+                                     const double *pah_row_edges) {
+  if (!ctx) return MCRT_EINVAL;
+  if (n_lambda < 2 || n_lambda > MAX_NL) return fail(ctx, MCRT_EINVAL, "n_lambda must be 2..%d", MAX_NL);
+  if (n_species < 1 || n_species > MAX_NS) return fail(ctx, MCRT_EINVAL, "n_species must be 1..%d", MAX_NS);
+  if (!lambda_um || !mass_frac || !kabs || !ksca || !g) return fail(ctx, MCRT_EINVAL, "NULL dust array");
+  for (int j = 0; j < n_lambda; ++j) {
+    if (!(lambda_um[j] > 0.0) || !std::isfinite(lambda_um[j]))
+      return fail(ctx, MCRT_EINVAL, "lambda must be positive");
+    if (j > 0 && !(lambda_um[j] > lambda_um[j - 1]))
+      return fail(ctx, MCRT_EINVAL, "lambda must be strictly increasing");
+  }
+  for (int s = 0; s < n_species; ++s) {
+    if (!finite_nonneg(mass_frac[s])) return fail(ctx, MCRT_EINVAL, "mass fractions must be >= 0");
+    for (int j = 0; j < n_lambda; ++j) {
+      int q = s * n_lambda + j;
+      if (!finite_nonneg(kabs[q]) || !finite_nonneg(ksca[q]))
+        return fail(ctx, MCRT_EINVAL, "kappa must be finite and >= 0");
+      if (!(std::fabs(g[q]) < 1.0)) return fail(ctx, MCRT_EINVAL, "|g| must be < 1");
+    }
+  }
+  if (pah_species >= n_species || pah_species < -1) return fail(ctx, MCRT_EINVAL, "bad pah_species");
+  if (pah_species >= 0) {
+    if (n_pah_rows < 1 || !pah_emis || (n_pah_rows > 1 && !pah_row_edges))
+      return fail(ctx, MCRT_EINVAL, "PAH species needs emissivity rows and edges");
+    for (int i = 0; i < n_pah_rows * n_lambda; ++i)
+      if (!finite_nonneg(pah_emis[i])) return fail(ctx, MCRT_EINVAL, "PAH emissivity must be >= 0");
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  ctx->nl = n_lambda;
+  ctx->ns = n_species;
+  ctx->lam.assign(lambda_um, lambda_um + n_lambda);
+  ctx->frac.assign(mass_frac, mass_frac + n_species);
+  ctx->kabs.assign(kabs, kabs + n_species * n_lambda);
+  ctx->ksca.assign(ksca, ksca + n_species * n_lambda);
+  ctx->g.assign(g, g + n_species * n_lambda);
+  ctx->pah = pah_species;
+  ctx->nrows = pah_species >= 0 ? n_pah_rows : 0;
+  ctx->pah_emis.assign(pah_species >= 0 ? pah_emis : nullptr,
+                       pah_species >= 0 ? pah_emis + n_pah_rows * n_lambda : nullptr);
+  ctx->pah_edges.clear();
+  if (pah_species >= 0 && n_pah_rows > 1) ctx->pah_edges.assign(pah_row_edges, pah_row_edges + n_pah_rows - 1);
+  ctx->has_dust = true;
+  ctx->has_src = false;  // source spectra live on the wavelength grid
+  if (ctx->has_grid) {
+    mcrt_status s = ensure_state(ctx, 0);
+    if (s) return s;
+  }
+  HIPCHK(hipDeviceSynchronize());
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_set_sources(mcrt_ctx *ctx, int n_src, const double *pos_cm,
+                                        const double *lum, const double *lnu_shape,
+                                        const double *t_bb) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!ctx->has_dust) return fail(ctx, MCRT_ESTATE, "set_dust before set_sources");
+  if (!ctx->has_grid) return fail(ctx, MCRT_ESTATE, "set the grid before set_sources");
+  if (n_src < 1 || n_src > MAX_SRC) return fail(ctx, MCRT_EINVAL, "n_src must be 1..%d", MAX_SRC);
+  if (!pos_cm || !lum || (!lnu_shape && !t_bb)) return fail(ctx, MCRT_EINVAL, "NULL source array");
+  const int nl = ctx->nl;
+  std::vector<double> nu(nl), w(nl);
+  for (int j = 0; j < nl; ++j) nu[j] = C_LI / (ctx->lam[j] * 1e-4);
+  for (int j = 0; j < nl; ++j) {
+    const double *L = ctx->lam.data();
+    double lo = (j == 0) ? L[0] * std::sqrt(L[0] / L[1]) : std::sqrt(L[j - 1] * L[j]);
+    double hi = (j == nl - 1) ? L[nl - 1] * std::sqrt(L[nl - 1] / L[nl - 2]) : std::sqrt(L[j] * L[j + 1]);
+    w[j] = C_LI / (lo * 1e-4) - C_LI / (hi * 1e-4);
+  }
+  std::vector<double> lnu((size_t)n_src * nl);
+  for (int s = 0; s < n_src; ++s) {
+    if (!finite_nonneg(lum[s])) return fail(ctx, MCRT_EINVAL, "luminosity must be >= 0");
+    for (int k = 0; k < 3; ++k) {
+      double p = pos_cm[3 * s + k];
+      double lo = ctx->origin[k];
+      double hi = ctx->origin[k] + (double)(k == 0 ? ctx->nx : k == 1 ? ctx->ny : ctx->nz) * ctx->dcell;
+      if (!(p >= lo && p <= hi)) return fail(ctx, MCRT_EINVAL, "source %d lies outside the grid", s);
+    }
+    std::vector<double> shape(nl);
+    for (int j = 0; j < nl; ++j) {
+      shape[j] = lnu_shape ? lnu_shape[s * nl + j] : h_planck(nu[j], t_bb[s]);
+      if (!finite_nonneg(shape[j])) return fail(ctx, MCRT_EINVAL, "source spectrum must be >= 0");
+    }
+    double norm = 0.0;
+    for (int j = nl - 1; j >= 0; --j) norm += w[j] * shape[j];
+    if (!(norm > 0.0)) return fail(ctx, MCRT_EINVAL, "source %d has an empty spectrum", s);
+    for (int j = 0; j < nl; ++j) lnu[s * nl + j] = lum[s] * shape[j] / norm;
+  }
+  ctx->nsrc = n_src;
+  ctx->src_pos.assign(pos_cm, pos_cm + 3 * n_src);
+  ctx->src_lum.assign(lum, lum + n_src);
+  ctx->src_lnu = lnu;
+  ctx->has_src = true;
+  return build_tables(ctx);
+}
+
+extern "C" mcrt_status mcrt_set_views(mcrt_ctx *ctx, int n_views, const double *theta_phi_deg,
+                                      int n_img, const int32_t *lambda_idx, double distance_cm) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!ctx->has_dust) return fail(ctx, MCRT_ESTATE, "set_dust before set_views");
+  if (n_views < 0 || n_views > MAX_VIEW) return fail(ctx, MCRT_EINVAL, "n_views must be 0..%d", MAX_VIEW);
+  if (n_img < 0 || n_img > MAX_IMG) return fail(ctx, MCRT_EINVAL, "n_img must be 0..%d", MAX_IMG);
+  if ((n_views > 0 && !theta_phi_deg) || (n_img > 0 && !lambda_idx))
+    return fail(ctx, MCRT_EINVAL, "NULL view arrays");
+  if (!(distance_cm > 0.0) || !std::isfinite(distance_cm)) return fail(ctx, MCRT_EINVAL, "distance must be > 0");
+  std::vector<int> seen(ctx->nl, 0);
+  for (int q = 0; q < n_img; ++q) {
+    if (lambda_idx[q] < 0 || lambda_idx[q] >= ctx->nl) return fail(ctx, MCRT_EINVAL, "imaged index out of range");
+    if (seen[lambda_idx[q]]++) return fail(ctx, MCRT_EINVAL, "imaged indices must be distinct");
+  }
+  ctx->nview = n_views;
+  ctx->nimg = n_img;
+  ctx->views.assign(theta_phi_deg, theta_phi_deg + 2 * n_views);
+  ctx->img_idx.assign(lambda_idx, lambda_idx + n_img);
+  ctx->distance = distance_cm;
+  ctx->ssca_cap = 0;
+  if (ctx->d_ssca) {
+    (void)hipFree(ctx->d_ssca);
+    ctx->d_ssca = nullptr;
+  }
+  if (ctx->has_grid) {
+    mcrt_status s = ensure_ssca(ctx);
+    if (s) return s;
+    uint64_t m = (uint64_t)ctx->nview * ctx->nimg * ctx->ncell;
+    if (ctx->d_ssca) {
+      if (ctx->fp64) HIPCHK(fill<double>((double *)ctx->d_ssca, 0.0, m, 0));
+      else HIPCHK(fill<float>((float *)ctx->d_ssca, 0.0f, m, 0));
+    }
+  }
+  ctx->S_ok = false;
+  mcrt_status s = build_tables(ctx);
+  if (s) return s;
+  HIPCHK(hipDeviceSynchronize());
+  return MCRT_OK;
+}
+
+static mcrt_status ready(mcrt_ctx *ctx) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!ctx->has_grid) return fail(ctx, MCRT_ESTATE, "grid not set");
+  if (!ctx->has_dust) return fail(ctx, MCRT_ESTATE, "dust not set");
+  if (!ctx->has_src) return fail(ctx, MCRT_ESTATE, "sources not set");
+  if (!ctx->tables_ok) return fail(ctx, MCRT_ESTATE, "tables not built");
+  return MCRT_OK;
+}
+
+// Host image of the model descriptor for a launch.
+static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int model_id) {
+  memset(&M, 0, sizeof(M));
+  M.nx = ctx->nx; M.ny = ctx->ny; M.nz = ctx->nz;
+  M.nl = ctx->nl; M.ns = ctx->ns; M.nsrc = ctx->nsrc; M.pah = ctx->pah; M.nrows = ctx->nrows;
+  M.nview = ctx->nview; M.nimg = ctx->nimg; M.ntheta = ctx->ntheta; M.model_id = model_id;
+  M.mode = o ? o->mode : M_BW_TICKET;
+  M.record = o ? o->record : 0;
+  M.pass = 1;
+  M.iter = 0;
+  for (int k = 0; k < 3; ++k) M.origin[k] = ctx->origin[k];
+  M.dcell = ctx->dcell;
+  M.V = ctx->dcell * ctx->dcell * ctx->dcell;
+  M.xi = ctx->xi;
+  M.lucy_tau = o ? o->lucy_tau : 0.0;
+  M.mrw_tau = o ? o->mrw_tau : 0.0;
+  M.mrw_gamma = o ? o->mrw_gamma : 2.0;
+  M.kext_max = ctx->kext_max;
+  M.max_int = o ? o->max_interactions : 0;
+  M.ncell = ctx->ncell;
+  M.rho = ctx->d_rho;
+  M.tab = ctx->d_tab;
+  M.rtab = ctx->d_rtab;
+  M.imgmap = ctx->d_imgmap;
+  M.k = ctx->d_k; M.epath = ctx->d_epath; M.T = ctx->d_T; M.esnap = ctx->d_esnap; M.tt = ctx->d_tt;
+  M.dirty = ctx->d_dirty; M.kpah = ctx->d_kpah; M.kpah_prefix = ctx->d_prefix;
+  M.sed = ctx->d_sed;
+  M.ssca = ctx->d_ssca;
+  M.rec = nullptr;
+  M.counter = ctx->d_counter;
+  M.stats = ctx->d_stats;
+  for (int v = 0; v < ctx->nview; ++v) {
+    double th = ctx->views[2 * v] * PI_D / 180.0, ph = ctx->views[2 * v + 1] * PI_D / 180.0;
+    M.kv[v][0] = std::sin(th) * std::cos(ph);
+    M.kv[v][1] = std::sin(th) * std::sin(ph);
+    M.kv[v][2] = std::cos(th);
+  }
+}
+
+static mcrt_status check_opts(mcrt_ctx *ctx, const mcrt_run_opts *o) {
+  if (!o) return fail(ctx, MCRT_EINVAL, "opts is NULL");
+  if (o->mode < MCRT_FROZEN || o->mode > MCRT_BW_TICKET) return fail(ctx, MCRT_EINVAL, "bad mode");
+  if (o->mode == MCRT_FROZEN && o->n_iter < 1) return fail(ctx, MCRT_EINVAL, "n_iter must be >= 1");
+  if (o->mode == MCRT_BW_EPOCH && o->epoch_packets < 1) return fail(ctx, MCRT_EINVAL, "epoch_packets must be >= 1");
+  if (o->sed_theta_bins < 1 || o->sed_theta_bins > 180) return fail(ctx, MCRT_EINVAL, "sed_theta_bins must be 1..180");
+  if (o->mrw_tau > 0.0 && !(o->mrw_gamma > 0.0)) return fail(ctx, MCRT_EINVAL, "mrw_gamma must be > 0");
+  if (!std::isfinite(o->lucy_tau) || !std::isfinite(o->mrw_tau)) return fail(ctx, MCRT_EINVAL, "non-finite threshold");
+  if (o->block_size < 0 || o->block_size > 256 || (o->block_size % 64) != 0)
+    return fail(ctx, MCRT_EINVAL, "block_size must be 64, 128, 192 or 256");
+  if (o->blocks_per_cu < 0 || o->blocks_per_cu > 32) return fail(ctx, MCRT_EINVAL, "blocks_per_cu must be 0..32");
+  return MCRT_OK;
+}
+
+static void launch_shape(mcrt_ctx *ctx, const mcrt_run_opts *o, int &grid, int &block) {
+  block = (o && o->block_size > 0) ? o->block_size : 256;
+  int bpc = (o && o->blocks_per_cu > 0) ? o->blocks_per_cu : 4;
+  grid = ctx->num_cu * bpc;
+}
+
+// Packet range of the next launch (device-side, in stream order).
+__global__ void k_set_range(ModelDev *m, uint64_t first, uint64_t n) {
+  m->first = first;
+  m->n = n;
+  *m->counter = 0;
+}
+
+static mcrt_status set_range(mcrt_ctx *ctx, uint64_t first, uint64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_range, dim3(1), dim3(1), 0, st, ctx->d_model, first, n);
+  HIPCHK(hipGetLastError());
+  return MCRT_OK;
+}
+
+static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, hipStream_t st) {
+  int grid, block;
+  launch_shape(ctx, o, grid, block);
+  size_t lds = transport_lds_bytes(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows, ctx->ntheta, ctx->fp64);
+  if (lds > ctx->lds_max)
+    return fail(ctx, MCRT_EINVAL, "tables need %zu bytes of LDS (limit %zu): fewer wavelengths, species or SED bins", lds, ctx->lds_max);
+  HIPCHK(launch_transport(ctx->d_model, 1, ctx->fp64, o->record != 0, grid, block, lds, st));
+  return MCRT_OK;
+}
+
+static mcrt_status read_stats(mcrt_ctx *ctx, mcrt_run_stats *stats, hipStream_t st) {
+  unsigned long long h[NSTAT];
+  HIPCHK(hipMemcpyAsync(h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  ctx->t_transport = ms;
+  if (stats) {
+    stats->packets = h[0]; stats->escaped = h[1]; stats->killed = h[2]; stats->pah_stopped = h[3];
+    stats->crossings = h[4]; stats->scatters = h[5]; stats->absorptions = h[6];
+    stats->mrw_steps = h[7]; stats->lucy_deposits = h[8]; stats->clamped_T = h[9];
+    stats->kernel_ms = ms;
+  }
+  return MCRT_OK;
+}
+
+static mcrt_status prepare_run(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n, hipStream_t st) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  s = check_opts(ctx, o);
+  if (s) return s;
+  HIPCHK(hipSetDevice(ctx->device));
+  s = ensure_state(ctx, st);
+  if (s) return s;
+  s = ensure_ssca(ctx);
+  if (s) return s;
+  if (o->sed_theta_bins != ctx->ntheta || !ctx->d_sed) {
+    ctx->ntheta = o->sed_theta_bins;
+    s = ensure_sed(ctx, ctx->ntheta);
+    if (s) return s;
+    HIPCHK(fill<uint64_t>(ctx->d_sed, 0ull, (uint64_t)ctx->sed_cap, st));
+  }
+  uint64_t nt = o->n_total ? o->n_total : n;
+  if (nt == 0) return fail(ctx, MCRT_EINVAL, "n_total is 0");
+  ctx->n_total = nt;
+  ctx->xi = ctx->ltot / (double)nt;
+  HIPCHK(fill<unsigned long long>(ctx->d_stats, 0ull, NSTAT, st));
+  return MCRT_OK;
+}
+
+static mcrt_status ensure_records(mcrt_ctx *ctx, uint64_t n) {
+  size_t need = (size_t)n * sizeof(mcrt_packet_record);
+  if (ctx->rec_cap < need) {
+    HIPCHK(dev_alloc(&ctx->d_rec, need));
+    ctx->rec_cap = need;
+  }
+  ctx->rec_n = n;
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_run_packets(mcrt_ctx *ctx, uint64_t first, uint64_t n, uint64_t seed,
+                                        const mcrt_run_opts *opts, mcrt_run_stats *stats,
+                                        void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  mcrt_status s = prepare_run(ctx, opts, n, st);
+  if (s) return s;
+  if (first + n > (1ull << 48)) return fail(ctx, MCRT_EINVAL, "packet ids must stay below 2^48");
+  if (opts->record) {
+    s = ensure_records(ctx, n);
+    if (s) return s;
+  }
+  ModelDev &M = ctx->h_model;
+  fill_model(ctx, M, opts, 0);
+  M.seed = seed;
+  M.rec = opts->record ? ctx->d_rec : nullptr;
+  M.first = first;
+  M.n = n;
+  M.id_base = 0;
+  M.rec_first = first;
+  HIPCHK(hipEventRecord(ctx->ev0, st));
+  if (opts->mode == MCRT_FROZEN) {
+    for (int it = 0; it < opts->n_iter; ++it) {
+      s = zero_tallies(ctx, st);
+      if (s) return s;
+      M.iter = it;
+      HIPCHK(stage_copy(ctx, ctx->d_model, &M, sizeof M, st));
+      s = set_range(ctx, first, n, st);
+      if (s) return s;
+      s = transport_launch(ctx, opts, st);
+      if (s) return s;
+      HIPCHK(launch_finalize_T(ctx->d_model, ctx->fp64, ctx->d_T, nullptr, st));
+    }
+  } else {
+    HIPCHK(stage_copy(ctx, ctx->d_model, &M, sizeof M, st));
+    if (opts->mode == MCRT_BW_TICKET) {
+      s = set_range(ctx, first, n, st);
+      if (s) return s;
+      s = transport_launch(ctx, opts, st);
+      if (s) return s;
+    } else {
+      const uint64_t P = opts->epoch_packets;
+      uint64_t a = first, end = first + n;
+      while (a < end) {
+        uint64_t b = (a / P + 1) * P;
+        if (b > end) b = end;
+        HIPCHK(launch_epoch_snapshot(ctx->d_model, st));
+        s = set_range(ctx, a, b - a, st);
+        if (s) return s;
+        s = transport_launch(ctx, opts, st);
+        if (s) return s;
+        a = b;
+      }
+    }
+  }
+  HIPCHK(hipEventRecord(ctx->ev1, st));
+  ctx->S_ok = false;
+  ctx->err.clear();
+  if (stats) return read_stats(ctx, stats, st);
+  return MCRT_OK;
+}
+
+__global__ void k_u32_to_u64(const uint32_t *a, uint64_t *b, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) b[i] = a[i];
+}
+
+extern "C" mcrt_status mcrt_run_pah(mcrt_ctx *ctx, uint64_t seed, const mcrt_run_opts *opts,
+                                    mcrt_run_stats *stats, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (ctx && ctx->pah < 0) return fail(ctx, MCRT_ESTATE, "no PAH species");
+  if (ctx && ctx->n_total == 0) return fail(ctx, MCRT_ESTATE, "run_packets before run_pah");
+  if (opts && opts->n_total && ctx && opts->n_total != ctx->n_total)
+    return fail(ctx, MCRT_EINVAL, "n_total differs from the source pass");
+  uint64_t nt = ctx ? ctx->n_total : 0;
+  mcrt_run_opts o2 = opts ? *opts : mcrt_run_opts{};
+  o2.n_total = nt;
+  mcrt_status s = prepare_run(ctx, &o2, nt, st);
+  if (s) return s;
+  // exclusive prefix of the pass-1 PAH counts (u64)
+  const uint64_t nc = ctx->ncell;
+  hipLaunchKernelGGL(k_u32_to_u64, dim3(4096), dim3(256), 0, st, ctx->d_kpah, (uint64_t *)ctx->d_tmp, nc);
+  HIPCHK(hipGetLastError());
+  size_t tb = 0;
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, (uint64_t *)ctx->d_tmp, ctx->d_prefix, (int)nc, st));
+  if (tb > ctx->temp_cap) {
+    HIPCHK(dev_alloc(&ctx->d_temp, tb));
+    ctx->temp_cap = tb;
+  }
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(ctx->d_temp, tb, (uint64_t *)ctx->d_tmp, ctx->d_prefix, (int)nc, st));
+  uint64_t last[2];
+  HIPCHK(hipMemcpyAsync(&last[0], ctx->d_prefix + nc - 1, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&last[1], (uint64_t *)ctx->d_tmp + nc - 1, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const uint64_t total = last[0] + last[1];
+  if (o2.record) {
+    s = ensure_records(ctx, total);
+    if (s) return s;
+  }
+  ModelDev &M = ctx->h_model;
+  fill_model(ctx, M, &o2, 0);
+  M.seed = seed;
+  M.pass = 2;
+  M.id_base = nt;
+  M.rec_first = 0;
+  M.rec = o2.record ? ctx->d_rec : nullptr;
+  HIPCHK(hipEventRecord(ctx->ev0, st));
+  HIPCHK(stage_copy(ctx, ctx->d_model, &M, sizeof M, st));
+  if (total > 0) {
+    if (o2.mode == MCRT_BW_EPOCH) {
+      const uint64_t P = o2.epoch_packets;
+      for (uint64_t a = 0; a < total;) {
+        uint64_t b = (a / P + 1) * P;
+        if (b > total) b = total;
+        HIPCHK(launch_epoch_snapshot(ctx->d_model, st));
+        s = set_range(ctx, a, b - a, st);
+        if (s) return s;
+        s = transport_launch(ctx, &o2, st);
+        if (s) return s;
+        a = b;
+      }
+    } else {
+      s = set_range(ctx, 0, total, st);
+      if (s) return s;
+      s = transport_launch(ctx, &o2, st);
+      if (s) return s;
+    }
+  }
+  HIPCHK(hipEventRecord(ctx->ev1, st));
+  ctx->S_ok = false;
+  if (stats) return read_stats(ctx, stats, st);
+  return MCRT_OK;
+}
+
+// ---------------------------------------------------------------- outputs
+
+static mcrt_status to_caller(mcrt_ctx *ctx, void *dst, const void *src, size_t bytes, int mem,
+                             hipStream_t st) {
+  if (!dst) return MCRT_OK;
+  if (mem == MCRT_DEVICE) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+  } else {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return MCRT_OK;
+}
+
+static mcrt_status upload_model_only(mcrt_ctx *ctx, hipStream_t st) {
+  fill_model(ctx, ctx->h_model, nullptr, 0);
+  HIPCHK(stage_copy(ctx, ctx->d_model, &ctx->h_model, sizeof(ModelDev), st));
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_reset(mcrt_ctx *ctx, void *stream) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device));
+  s = ensure_state(ctx, st);
+  if (s) return s;
+  s = ensure_ssca(ctx);
+  if (s) return s;
+  s = ensure_sed(ctx, ctx->ntheta);
+  if (s) return s;
+  s = zero_tallies(ctx, st);
+  if (s) return s;
+  return zero_epoch(ctx, st);
+}
+
+extern "C" mcrt_status mcrt_init_temperatures(mcrt_ctx *ctx, void *stream) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device));
+  s = ensure_state(ctx, st);
+  if (s) return s;
+  s = upload_model_only(ctx, st);
+  if (s) return s;
+  HIPCHK(launch_init_T(ctx->d_model, ctx->fp64, ctx->d_T, st));
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_set_temperatures(mcrt_ctx *ctx, const double *T, int mem, void *stream) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!ctx->has_grid || !ctx->has_dust) return fail(ctx, MCRT_ESTATE, "grid and dust must be set");
+  if (!T) return fail(ctx, MCRT_EINVAL, "T is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device));
+  mcrt_status s = ensure_state(ctx, st);
+  if (s) return s;
+  size_t bytes = ctx->ncell * (size_t)ctx->ns * 8;
+  HIPCHK(hipMemcpyAsync(ctx->d_T, T, bytes, mem == MCRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  if (mem != MCRT_DEVICE) HIPCHK(hipStreamSynchronize(st));
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+__global__ void k_d2f(const double *a, float *b, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) b[i] = (float)a[i];
+}
+__global__ void k_f2d(const float *a, double *b, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) b[i] = (double)a[i];
+}
+
+extern "C" mcrt_status mcrt_set_scattering(mcrt_ctx *ctx, const double *ssca, int mem, void *stream) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!ctx->has_grid || !ctx->has_dust) return fail(ctx, MCRT_ESTATE, "grid and dust must be set");
+  if (!ssca) return fail(ctx, MCRT_EINVAL, "ssca is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device));
+  mcrt_status s = ensure_ssca(ctx);
+  if (s) return s;
+  uint64_t m = (uint64_t)ctx->nview * ctx->nimg * ctx->ncell;
+  if (m == 0) return MCRT_OK;
+  if (ctx->fp64) {
+    HIPCHK(hipMemcpyAsync(ctx->d_ssca, ssca, m * 8, mem == MCRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  } else {
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc((void **)&tmp, m * 8));
+    HIPCHK(hipMemcpyAsync(tmp, ssca, m * 8, mem == MCRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_d2f, dim3(4096), dim3(256), 0, st, tmp, (float *)ctx->d_ssca, m);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    (void)hipFree(tmp);
+  }
+  if (mem != MCRT_DEVICE) HIPCHK(hipStreamSynchronize(st));
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_temperatures(mcrt_ctx *ctx, double *T_out, double *E_out, int mem,
+                                         void *stream) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!ctx->d_k) return fail(ctx, MCRT_ESTATE, "no tallies");
+  fill_model(ctx, ctx->h_model, nullptr, 0);
+  HIPCHK(stage_copy(ctx, ctx->d_model, &ctx->h_model, sizeof(ModelDev), st));
+  HIPCHK(launch_finalize_T(ctx->d_model, ctx->fp64, ctx->d_T, ctx->d_tmp, st));
+  size_t bytes = ctx->ncell * (size_t)ctx->ns * 8;
+  s = to_caller(ctx, T_out, ctx->d_T, bytes, mem, st);
+  if (s) return s;
+  s = to_caller(ctx, E_out, ctx->d_tmp, bytes, mem, st);
+  if (s) return s;
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_get_temperatures(mcrt_ctx *ctx, double *T_out, int mem, void *stream) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!ctx->d_T) return fail(ctx, MCRT_ESTATE, "no temperature field yet");
+  if (!T_out) return fail(ctx, MCRT_EINVAL, "T_out is NULL");
+  return to_caller(ctx, T_out, ctx->d_T, ctx->ncell * (size_t)ctx->ns * 8, mem, (hipStream_t)stream);
+}
+
+extern "C" mcrt_status mcrt_density(mcrt_ctx *ctx, void *rho_out, int mem, void *stream) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!ctx->has_grid) return fail(ctx, MCRT_ESTATE, "grid not set");
+  if (!rho_out) return fail(ctx, MCRT_EINVAL, "rho_out is NULL");
+  return to_caller(ctx, rho_out, ctx->d_rho, ctx->ncell * rsize(ctx), mem, (hipStream_t)stream);
+}
+
+extern "C" mcrt_status mcrt_tallies(mcrt_ctx *ctx, uint64_t *k_out, double *epath_out,
+                                    uint32_t *kpah_out, int mem, void *stream) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  if (!ctx->d_k) return fail(ctx, MCRT_ESTATE, "no tallies");
+  hipStream_t st = (hipStream_t)stream;
+  size_t b = ctx->ncell * (size_t)ctx->ns * 8;
+  s = to_caller(ctx, k_out, ctx->d_k, b, mem, st);
+  if (s) return s;
+  s = to_caller(ctx, epath_out, ctx->d_epath, b, mem, st);
+  if (s) return s;
+  return to_caller(ctx, kpah_out, ctx->d_kpah, ctx->ncell * 4, mem, st);
+}
+
+__global__ void k_sed_flux(const uint64_t *cnt, const double *w, int nl, int nt, double xi,
+                           double D2, double *out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl * nt) return;
+  int j = i % nl;
+  double dOmega = 4.0 * PI_D / (double)nt;
+  out[i] = (double)cnt[i] * xi / (dOmega * D2 * w[j]);
+}
+
+extern "C" mcrt_status mcrt_sed(mcrt_ctx *ctx, double *sed_out, uint64_t *counts_out, int mem,
+                                void *stream) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  if (!ctx->d_sed) return fail(ctx, MCRT_ESTATE, "no SED yet");
+  hipStream_t st = (hipStream_t)stream;
+  int n = ctx->ntheta * ctx->nl;
+  if (sed_out) {
+    if (ctx->sed_tmp_cap < (size_t)n * 8) {
+      HIPCHK(dev_alloc((void **)&ctx->d_sed_tmp, (size_t)n * 8));
+      ctx->sed_tmp_cap = (size_t)n * 8;
+    }
+    TabOff o = tab_offsets(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows);
+    hipLaunchKernelGGL(k_sed_flux, dim3((n + 255) / 256), dim3(256), 0, st, ctx->d_sed,
+                       ctx->d_tab + o.w, ctx->nl, ctx->ntheta, ctx->xi,
+                       ctx->distance * ctx->distance, ctx->d_sed_tmp);
+    HIPCHK(hipGetLastError());
+    s = to_caller(ctx, sed_out, ctx->d_sed_tmp, (size_t)n * 8, mem, st);
+    if (s) return s;
+  }
+  return to_caller(ctx, counts_out, ctx->d_sed, (size_t)n * 8, mem, st);
+}
+
+extern "C" mcrt_status mcrt_scattering(mcrt_ctx *ctx, double *ssca_out, int mem, void *stream) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t m = (uint64_t)ctx->nview * ctx->nimg * ctx->ncell;
+  if (m == 0 || !ssca_out) return MCRT_OK;
+  if (ctx->fp64) return to_caller(ctx, ssca_out, ctx->d_ssca, m * 8, mem, st);
+  double *tmp = nullptr;
+  HIPCHK(hipMalloc((void **)&tmp, m * 8));
+  hipLaunchKernelGGL(k_f2d, dim3(4096), dim3(256), 0, st, (const float *)ctx->d_ssca, tmp, m);
+  HIPCHK(hipGetLastError());
+  s = to_caller(ctx, ssca_out, tmp, m * 8, mem, st);
+  HIPCHK(hipStreamSynchronize(st));
+  (void)hipFree(tmp);
+  return s;
+}
+
+extern "C" mcrt_status mcrt_packet_records(mcrt_ctx *ctx, mcrt_packet_record *out, uint64_t n, int mem) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!out) return fail(ctx, MCRT_EINVAL, "out is NULL");
+  if (!ctx->d_rec || ctx->rec_n == 0) return fail(ctx, MCRT_ESTATE, "no records (run with record = 1)");
+  uint64_t m = n < ctx->rec_n ? n : ctx->rec_n;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(out, ctx->d_rec, m * sizeof(mcrt_packet_record),
+                   mem == MCRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return MCRT_OK;
+}
+
+// ------------------------------------------------------------- ray-tracer
+
+static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt, hipStream_t st,
+                              RtArgs &A) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  if (ctx->nview < 1 || ctx->nimg < 1) return fail(ctx, MCRT_ESTATE, "set_views before ray-tracing");
+  if (npx < 1 || npy < 1 || (uint64_t)npx * npy > (1ull << 28)) return fail(ctx, MCRT_EINVAL, "bad image size");
+  HIPCHK(hipSetDevice(ctx->device));
+  s = ensure_state(ctx, st);
+  if (s) return s;
+  s = ensure_ssca(ctx);
+  if (s) return s;
+  const int nq = ctx->nimg;
+  if (!ctx->S_ok) {
+    size_t need = (size_t)ctx->nview * ctx->ncell * nq * rsize(ctx);
+    if (need > ctx->S_cap) {
+      HIPCHK(dev_alloc(&ctx->d_S, need));
+      ctx->S_cap = need;
+    }
+    s = upload_model_only(ctx, st);
+    if (s) return s;
+    for (int v = 0; v < ctx->nview; ++v) HIPCHK(launch_build_S(ctx->d_model, v, ctx->fp64, ctx->d_S, st));
+    ctx->S_ok = true;
+  }
+  memset(&A, 0, sizeof A);
+  A.nx = ctx->nx; A.ny = ctx->ny; A.nz = ctx->nz; A.nimg = nq; A.npx = npx; A.npy = npy;
+  A.nview = ctx->nview; A.nsrc = ctx->nsrc;
+  for (int k = 0; k < 3; ++k) A.origin[k] = ctx->origin[k];
+  A.dcell = ctx->dcell;
+  A.ncell = ctx->ncell;
+  A.rho = rho_rt ? rho_rt : ctx->d_rho;
+  A.S = ctx->d_S;
+  TabOff o = tab_offsets(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows);
+  for (int q = 0; q < nq; ++q) {
+    int j = ctx->img_idx[q];
+    A.kext[q] = ctx->h_tab[o.kext + j];
+    for (int s2 = 0; s2 < ctx->nsrc; ++s2) A.lnu[s2][q] = ctx->src_lnu[s2 * ctx->nl + j];
+  }
+  for (int s2 = 0; s2 < ctx->nsrc; ++s2)
+    for (int k = 0; k < 3; ++k) A.srcpos[s2][k] = ctx->src_pos[3 * s2 + k];
+  A.D2 = ctx->distance * ctx->distance;
+  int n[3] = {ctx->nx, ctx->ny, ctx->nz};
+  double L = 0.0, ctr[3];
+  for (int k = 0; k < 3; ++k) {
+    ctr[k] = ctx->origin[k] + 0.5 * (double)n[k] * ctx->dcell;
+    if ((double)n[k] * ctx->dcell > L) L = (double)n[k] * ctx->dcell;
+  }
+  for (int v = 0; v < ctx->nview; ++v) {
+    RtView &V = A.v[v];
+    double th = ctx->views[2 * v] * PI_D / 180.0, ph = ctx->views[2 * v + 1] * PI_D / 180.0;
+    V.k[0] = std::sin(th) * std::cos(ph); V.k[1] = std::sin(th) * std::sin(ph); V.k[2] = std::cos(th);
+    V.ex[0] = std::cos(th) * std::cos(ph); V.ex[1] = std::cos(th) * std::sin(ph); V.ex[2] = -std::sin(th);
+    V.ey[0] = -std::sin(ph); V.ey[1] = std::cos(ph); V.ey[2] = 0.0;
+    for (int k = 0; k < 3; ++k) V.ctr[k] = ctr[k];
+    V.fov = std::sqrt(3.0) * L;
+    V.dpx = V.fov / (double)npx;
+    V.dpy = V.fov / (double)npy;
+    V.apix_d2 = V.dpx * V.dpy / A.D2;
+  }
+  HIPCHK(stage_copy(ctx, ctx->d_rt, &A, sizeof A, st));
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt,
+                                           void *img_out, double *sed_out, int mem, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  RtArgs A;
+  mcrt_status s = rt_prepare(ctx, npx, npy, rho_rt, st, A);
+  if (s) return s;
+  size_t ib = (size_t)ctx->nview * ctx->nimg * npx * npy * rsize(ctx);
+  void *img = img_out;
+  if (!img_out || mem != MCRT_DEVICE) {
+    if (ib > ctx->img_cap) {
+      HIPCHK(dev_alloc(&ctx->d_img_tmp, ib));
+      ctx->img_cap = ib;
+    }
+    img = ctx->d_img_tmp;
+  }
+  double *sed = nullptr;
+  size_t sb = (size_t)ctx->nview * ctx->nimg * 8;
+  if (sed_out) {
+    if (ctx->sed_tmp_cap < sb) {
+      HIPCHK(dev_alloc((void **)&ctx->d_sed_tmp, sb));
+      ctx->sed_tmp_cap = sb;
+    }
+    sed = (mem == MCRT_DEVICE) ? sed_out : ctx->d_sed_tmp;
+  }
+  HIPCHK(hipEventRecord(ctx->evf0, st));
+  HIPCHK(launch_rt_fwd(ctx->d_rt, A, ctx->fp64, img, sed, st));
+  HIPCHK(hipEventRecord(ctx->evf1, st));
+  ctx->have_f = true;
+  if (mem != MCRT_DEVICE) {
+    if (img_out) HIPCHK(hipMemcpyAsync(img_out, img, ib, hipMemcpyDeviceToHost, st));
+    if (sed_out) HIPCHK(hipMemcpyAsync(sed_out, sed, sb, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_raytrace_adjoint(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt,
+                                             const void *dL_dimg, const double *dL_dsed,
+                                             void *dL_drho, int mem, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (ctx && !dL_drho) return fail(ctx, MCRT_EINVAL, "dL_drho is NULL");
+  RtArgs A;
+  mcrt_status s = rt_prepare(ctx, npx, npy, rho_rt, st, A);
+  if (s) return s;
+  size_t ib = (size_t)ctx->nview * ctx->nimg * npx * npy * rsize(ctx);
+  size_t sb = (size_t)ctx->nview * ctx->nimg * 8;
+  size_t gb = ctx->ncell * rsize(ctx);
+  const void *wimg = dL_dimg;
+  const double *wsed = dL_dsed;
+  void *grad = dL_drho;
+  void *tmp_img = nullptr, *tmp_g = nullptr;
+  double *tmp_sed = nullptr;
+  if (mem != MCRT_DEVICE) {
+    if (dL_dimg) {
+      HIPCHK(hipMalloc(&tmp_img, ib));
+      HIPCHK(hipMemcpyAsync(tmp_img, dL_dimg, ib, hipMemcpyHostToDevice, st));
+      wimg = tmp_img;
+    }
+    if (dL_dsed) {
+      HIPCHK(hipMalloc((void **)&tmp_sed, sb));
+      HIPCHK(hipMemcpyAsync(tmp_sed, dL_dsed, sb, hipMemcpyHostToDevice, st));
+      wsed = tmp_sed;
+    }
+    HIPCHK(hipMalloc(&tmp_g, gb));
+    grad = tmp_g;
+  }
+  if (ctx->fp64) HIPCHK(fill<double>((double *)grad, 0.0, ctx->ncell, st));
+  else HIPCHK(fill<float>((float *)grad, 0.0f, ctx->ncell, st));
+  HIPCHK(hipEventRecord(ctx->eva0, st));
+  HIPCHK(launch_rt_adj(ctx->d_rt, A, ctx->fp64, wimg, wsed, grad, st));
+  HIPCHK(hipEventRecord(ctx->eva1, st));
+  ctx->have_a = true;
+  if (mem != MCRT_DEVICE) {
+    HIPCHK(hipMemcpyAsync(dL_drho, grad, gb, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (tmp_img) (void)hipFree(tmp_img);
+    if (tmp_sed) (void)hipFree(tmp_sed);
+    (void)hipFree(tmp_g);
+  }
+  return MCRT_OK;
+}
+
+static double event_ms(hipEvent_t a, hipEvent_t b) {
+  if (hipEventSynchronize(b) != hipSuccess) return -1.0;
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
+  return ms;
+}
+
+extern "C" mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_ms, double *rt_fwd_ms,
+                                         double *rt_adj_ms) {
+  if (!ctx) return MCRT_EINVAL;
+  if (transport_ms) *transport_ms = ctx->t_transport;
+  if (rt_fwd_ms) *rt_fwd_ms = ctx->have_f ? event_ms(ctx->evf0, ctx->evf1) : 0.0;
+  if (rt_adj_ms) *rt_adj_ms = ctx->have_a ? event_ms(ctx->eva0, ctx->eva1) : 0.0;
+  return MCRT_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
+                                      const uint64_t *n_packets, const uint64_t *seeds,
+                                      const mcrt_run_opts *opts, mcrt_run_stats *stats,
+                                      void *stream) {
+  if (!models || n_models < 1 || !models[0]) return MCRT_EINVAL;
+  mcrt_ctx *ctx = models[0];
+  if (!n_packets || !seeds) return fail(ctx, MCRT_EINVAL, "NULL n_packets/seeds");
+  mcrt_status s = check_opts(ctx, opts);
+  if (s) return s;
+  if (opts->mode == MCRT_BW_EPOCH || (opts->mode == MCRT_FROZEN && opts->n_iter != 1))
+    return fail(ctx, MCRT_EINVAL, "batch supports BW_TICKET and single-pass FROZEN");
+  if (opts->record) return fail(ctx, MCRT_EINVAL, "records are not kept in batch mode");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device));
+  std::vector<ModelDev> hm(n_models);
+  size_t lds = 0;
+  for (int m = 0; m < n_models; ++m) {
+    mcrt_ctx *c = models[m];
+    if (!c || c->device != ctx->device || c->fp64 != ctx->fp64)
+      return fail(ctx, MCRT_EINVAL, "model %d: same device and precision required", m);
+    s = prepare_run(c, opts, n_packets[m], st);
+    if (s) return fail(ctx, s, "model %d: %s", m, c->err.c_str());
+    fill_model(c, hm[m], opts, m);
+    hm[m].seed = seeds[m];
+    hm[m].first = 0;
+    hm[m].n = n_packets[m];
+    size_t b = transport_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->fp64);
+    if (b > lds) lds = b;
+  }
+  if (n_models > ctx->batch_cap) {
+    HIPCHK(dev_alloc((void **)&ctx->d_batch, sizeof(ModelDev) * n_models));
+    ctx->batch_cap = n_models;
+  }
+  if (sizeof(ModelDev) * n_models > STAGE_BYTES) return fail(ctx, MCRT_EINVAL, "too many models");
+  HIPCHK(stage_copy(ctx, ctx->d_batch, hm.data(), sizeof(ModelDev) * n_models, st));
+  int grid, block;
+  launch_shape(ctx, opts, grid, block);
+  // one graph: reset tallies and counters, the persistent transport, Eq. 4
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  mcrt_status cs = MCRT_OK;
+  for (int m = 0; m < n_models && cs == MCRT_OK; ++m) {
+    mcrt_ctx *c = models[m];
+    cs = zero_tallies(c, st);
+    if (cs == MCRT_OK && fill<uint64_t>(c->d_counter, 0ull, 1, st) != hipSuccess) cs = MCRT_EDEVICE;
+  }
+  hipError_t le = hipSuccess;
+  if (cs == MCRT_OK) le = launch_transport(ctx->d_batch, n_models, ctx->fp64, false, grid, block, lds, st);
+  for (int m = 0; m < n_models && cs == MCRT_OK && le == hipSuccess; ++m)
+    le = launch_finalize_T(ctx->d_batch + m, ctx->fp64, models[m]->d_T, nullptr, st);
+  hipError_t ce = hipStreamEndCapture(st, &graph);
+  if (cs != MCRT_OK || le != hipSuccess || ce != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(ctx, MCRT_EDEVICE, "graph capture failed: %s",
+                hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  HIPCHK(hipEventRecord(ctx->ev0, st));
+  HIPCHK(hipGraphLaunch(exec, st));
+  HIPCHK(hipEventRecord(ctx->ev1, st));
+  HIPCHK(hipStreamSynchronize(st));
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  ctx->t_transport = ms;
+  for (int m = 0; m < n_models; ++m) {
+    models[m]->S_ok = false;
+    if (stats) {
+      unsigned long long h[NSTAT];
+      mcrt_ctx *c = models[m];
+      HIPCHK(hipMemcpy(h, c->d_stats, sizeof h, hipMemcpyDeviceToHost));
+      mcrt_run_stats &o = stats[m];
+      o.packets = h[0]; o.escaped = h[1]; o.killed = h[2]; o.pah_stopped = h[3];
+      o.crossings = h[4]; o.scatters = h[5]; o.absorptions = h[6]; o.mrw_steps = h[7];
+      o.lucy_deposits = h[8]; o.clamped_T = h[9]; o.kernel_ms = ms;
+    }
+  }
+  return MCRT_OK;
+}

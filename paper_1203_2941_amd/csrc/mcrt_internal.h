@@ -1,0 +1,335 @@
+// mcrt_internal.h - device data layout and helpers of the HIP library.
+//
+// Everything here is internal to libmcrt (include/mcrt.h is the public ABI).
+// Units are cgs; both precisions walk the grid in centimetres with the
+// integer cell index authoritative, so the FP64 path follows the same
+// rounding sequence as a plain sequential evaluation of the method.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcrt {
+
+constexpr int MAX_NL = 256;
+constexpr int MAX_NS = 4;
+constexpr int MAX_SRC = 8;
+constexpr int MAX_VIEW = 16;
+constexpr int MAX_IMG = 16;
+constexpr int NT_TAB = 256;          // points of the ln(Phi) vs ln(T) table per species
+constexpr double T_TAB_MIN = 1.0;    // K
+constexpr double T_MAX = 1.0e5;      // K, upper end of the Eq. 4 search
+constexpr double T_FLOOR = 10.0;     // K, emission temperature of a cell with T = 0
+constexpr double H_PL = 6.62607015e-27;
+constexpr double C_LI = 2.99792458e10;
+constexpr double K_BO = 1.380649e-16;
+constexpr double PI_D = 3.14159265358979323846;
+
+enum { ST_ALIVE = 0, ST_ESCAPED = 1, ST_KILLED = 2, ST_PAH_STOP = 3 };
+enum { M_FROZEN = 0, M_BW_EPOCH = 1, M_BW_TICKET = 2 };
+enum { NSTAT = 10 };  // packets escaped killed pah crossings scatters absorptions mrw lucy clampedT
+
+// Offsets (in elements) of the packed per-model tables. The double table
+// serves FP64 arithmetic of both precisions (temperatures, diffusion solve,
+// source spectra); the R table holds what the packet walk reads per event
+// in the walk's precision.
+struct TabOff {
+  int w, hnu, a, kext, wk, wfk, kabs, frac, srcf, lnu, lum, pahw, pahe, logphi, srcpos, dtotal;
+  int r_kext, r_kabsm, r_alb, r_fsca, r_fabs, r_g, r_lucy, r_hnu, r_a, r_wk, r_total;
+};
+
+__host__ __device__ inline TabOff tab_offsets(int nl, int ns, int nsrc, int nrows) {
+  TabOff o;
+  int p = 0;
+  o.w = p; p += nl;
+  o.hnu = p; p += nl;
+  o.a = p; p += nl;
+  o.kext = p; p += nl;
+  o.wk = p; p += ns * nl;
+  o.wfk = p; p += ns * nl;
+  o.kabs = p; p += ns * nl;
+  o.frac = p; p += MAX_NS;
+  o.srcf = p; p += nsrc * nl;
+  o.lnu = p; p += nsrc * nl;
+  o.lum = p; p += MAX_SRC;
+  o.pahw = p; p += (nrows > 0 ? nrows : 1) * nl;
+  o.pahe = p; p += (nrows > 0 ? nrows : 1);
+  o.logphi = p; p += ns * NT_TAB;
+  o.srcpos = p; p += 3 * MAX_SRC;
+  o.dtotal = p;
+  int q = 0;
+  o.r_kext = q; q += nl;
+  o.r_kabsm = q; q += nl;
+  o.r_alb = q; q += nl;
+  o.r_fsca = q; q += ns * nl;
+  o.r_fabs = q; q += ns * nl;
+  o.r_g = q; q += ns * nl;
+  o.r_lucy = q; q += ns * nl;
+  o.r_hnu = q; q += nl;
+  o.r_a = q; q += nl;
+  o.r_wk = q; q += ns * nl;
+  o.r_total = q;
+  return o;
+}
+
+// One model as the kernels see it (a device array of these drives a launch).
+struct ModelDev {
+  int32_t nx, ny, nz, nl, ns, nsrc, pah, nrows, nview, nimg, ntheta, model_id;
+  int32_t mode, record, pass, iter;
+  double origin[3];
+  double dcell, V, xi, lucy_tau, mrw_tau, mrw_gamma, kext_max;
+  uint64_t max_int, first, n, id_base, rec_first, seed, ncell;
+  const void *rho;            // [cells] context precision
+  const double *tab;          // packed double table
+  const void *rtab;           // packed R table
+  const int32_t *imgmap;      // [nl] -> imaged index or -1
+  uint64_t *k;                // [ns][cells]
+  double *epath;              // [ns][cells]
+  double *T;                  // [ns][cells]
+  double *esnap;              // [ns][cells]
+  double *tt;                 // [ns][cells], < 0 = not yet computed this epoch
+  uint8_t *dirty;             // [cells]
+  uint32_t *kpah;             // [cells]
+  const uint64_t *kpah_prefix;// [cells] exclusive prefix of kpah (PAH pass)
+  uint64_t *sed;              // [ntheta][nl]
+  void *ssca;                 // [nview][nimg][cells] context precision
+  void *rec;                  // records [n]
+  uint64_t *counter;          // packet counter of the launch
+  unsigned long long *stats;  // [NSTAT]
+  double kv[MAX_VIEW][3];     // view directions toward the observer
+};
+
+// ---------------------------------------------------------------- RNG
+// Philox4x32-10 (Salmon et al. 2011); key = seed, counter = (draw block,
+// packet id low word, packet id bits 32-47 | iteration << 16,
+// model << 8 | stream tag). Draw d uses block d >> 2, word d & 3.
+__device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+struct Rng {
+  uint32_t k0, k1, c1, c2, c3, d, blk;
+  uint32_t b0, b1, b2, b3;
+};
+
+__device__ __forceinline__ void rng_init(Rng &r, uint64_t seed, uint64_t pid, uint32_t iter,
+                                         uint32_t model, uint32_t tag) {
+  r.k0 = (uint32_t)seed;
+  r.k1 = (uint32_t)(seed >> 32);
+  r.c1 = (uint32_t)pid;
+  r.c2 = ((uint32_t)(pid >> 32) & 0xFFFFu) | (iter << 16);
+  r.c3 = (model << 8) | (tag & 0xFFu);
+  r.d = 0;
+  r.blk = 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ uint32_t rng_u32(Rng &r) {
+  uint32_t b = r.d >> 2;
+  if (b != r.blk) {
+    uint32_t c0 = b, c1 = r.c1, c2 = r.c2, c3 = r.c3;
+    philox10(c0, c1, c2, c3, r.k0, r.k1);
+    r.b0 = c0; r.b1 = c1; r.b2 = c2; r.b3 = c3;
+    r.blk = b;
+  }
+  uint32_t w = r.d & 3u;
+  uint32_t x = (w == 0) ? r.b0 : (w == 1) ? r.b1 : (w == 2) ? r.b2 : r.b3;
+  r.d++;
+  return x;
+}
+
+// ((x >> 8) + 1/2) 2^-24: exact in both precisions, strictly inside (0, 1).
+template <typename R> __device__ __forceinline__ R rng_u(Rng &r) {
+  return ((R)(rng_u32(r) >> 8) + (R)0.5) * (R)(1.0 / 16777216.0);
+}
+
+// ---------------------------------------------------------------- math
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_cos(double x) { return cos(x); }
+__device__ __forceinline__ float m_cos(float x) { return cosf(x); }
+__device__ __forceinline__ double m_sin(double x) { return sin(x); }
+__device__ __forceinline__ float m_sin(float x) { return sinf(x); }
+__device__ __forceinline__ double m_floor(double x) { return floor(x); }
+__device__ __forceinline__ float m_floor(float x) { return floorf(x); }
+__device__ __forceinline__ double m_fabs(double x) { return fabs(x); }
+__device__ __forceinline__ float m_fabs(float x) { return fabsf(x); }
+template <typename R> __device__ __forceinline__ R m_inf() { return (R)__builtin_huge_val(); }
+// largest x of the Planck factor 1/(e^x - 1) kept in each precision
+template <typename R> __device__ __forceinline__ R x_cut();
+template <> __device__ __forceinline__ double x_cut<double>() { return 700.0; }
+template <> __device__ __forceinline__ float x_cut<float>() { return 80.0f; }
+
+__device__ __forceinline__ void upd_margin(double &mm, double v) {
+  if (v < mm) mm = v;
+}
+
+// Planck pieces (double): B = a/(e^x - 1), dB/dT = B (x/T)(1 + 1/(e^x - 1)),
+// x = h nu / kT; zero for x > 700 or T <= 0.
+__device__ __forceinline__ double planck_d(double hnu, double a, double T) {
+  if (!(T > 0.0)) return 0.0;
+  double x = hnu / (K_BO * T);
+  if (x > 700.0) return 0.0;
+  return a / expm1(x);
+}
+__device__ __forceinline__ double dplanck_d(double hnu, double a, double T) {
+  if (!(T > 0.0)) return 0.0;
+  double x = hnu / (K_BO * T);
+  if (x > 700.0) return 0.0;
+  double em = expm1(x);
+  double B = a / em;
+  return B * (x / T) * (1.0 + 1.0 / em);
+}
+
+// Phi_s(T) = sum_j w_j kabs_s,j B_j(T) (ascending frequency) and dPhi/dT.
+__device__ inline double phi_dphi(const double *wk, const double *hnu, const double *a, int nl,
+                                  double T, double *dphi) {
+  double s = 0.0, ds = 0.0;
+  double kT = K_BO * T;
+  for (int j = nl - 1; j >= 0; --j) {
+    double x = hnu[j] / kT;
+    if (x > 700.0) continue;
+    double em = expm1(x);
+    double B = a[j] / em;
+    s += wk[j] * B;
+    ds += wk[j] * (B * (x / T) * (1.0 + 1.0 / em));
+  }
+  *dphi = ds;
+  return s;
+}
+
+// Eq. 4 inverted in FP64: table bracket in (ln T, ln Phi), then safeguarded
+// Newton on ln Phi(ln T) until |d ln T| < 1e-14. rhs <= 0 -> 0; rhs at or
+// above Phi(T_MAX) -> T_MAX with *clamped set.
+__device__ inline double invert_T(const double *tab, const TabOff &o, int nl, int s, double rhs,
+                                  bool *clamped) {
+  if (!(rhs > 0.0)) return 0.0;
+  const double *lp = tab + o.logphi + s * NT_TAB;
+  const double *wk = tab + o.wk + s * nl;
+  const double *hnu = tab + o.hnu;
+  const double *a = tab + o.a;
+  const double lt0 = log(T_TAB_MIN), dlt = (log(T_MAX) - lt0) / (NT_TAB - 1);
+  double lr = log(rhs);
+  double dphi;
+  if (!(lr < lp[NT_TAB - 1])) {
+    double ph = phi_dphi(wk, hnu, a, nl, T_MAX, &dphi);
+    if (ph <= rhs) {
+      *clamped = true;
+      return T_MAX;
+    }
+  }
+  double ulo, uhi, u;
+  if (lr < lp[0]) {
+    ulo = -60.0;  // ~1e-26 K: Phi there underflows to 0 on any grid
+    uhi = lt0;
+    u = lt0 - 1.0;
+  } else {
+    int lo = 0, hi = NT_TAB - 1;
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (lp[mid] <= lr) lo = mid; else hi = mid;
+    }
+    ulo = lt0 + lo * dlt;
+    uhi = lt0 + hi * dlt;
+    double den = lp[hi] - lp[lo];
+    u = (den > 0.0 && lp[lo] > -1e300) ? ulo + (lr - lp[lo]) / den * dlt : 0.5 * (ulo + uhi);
+  }
+  for (int it = 0; it < 100; ++it) {
+    double T = exp(u);
+    double ph = phi_dphi(wk, hnu, a, nl, T, &dphi);
+    double un;
+    if (!(ph > 0.0)) {
+      ulo = u;
+      un = 0.5 * (ulo + uhi);
+    } else {
+      double g = log(ph) - lr;
+      if (g > 0.0) uhi = u; else ulo = u;
+      double slope = T * dphi / ph;
+      un = (slope > 0.0) ? u - g / slope : 0.5 * (ulo + uhi);
+      if (!(un > ulo && un < uhi)) un = 0.5 * (ulo + uhi);
+    }
+    double du = un - u;
+    u = un;
+    if (fabs(du) < 1e-14) break;
+  }
+  return exp(u);
+}
+
+// Survival in a sphere for diffusion from its centre, S = 2 sum (-1)^{n+1} y^{n^2}.
+__device__ inline double mrw_surv(double y) {
+  if (!(y > 0.0)) return 0.0;
+  if (y >= 1.0) return 1.0;
+  double ly = log(y), sum = 0.0;
+  for (int n = 1; n <= 10000; ++n) {
+    double term = exp((double)n * (double)n * ly);
+    sum += (n & 1) ? term : -term;
+    if (term < 1e-17 * fabs(sum)) break;
+  }
+  return 2.0 * sum;
+}
+
+__device__ inline double mrw_dsurv(double y) {
+  double ly = log(y), sum = 0.0;
+  for (int n = 1; n <= 10000; ++n) {
+    double nn = (double)n * (double)n;
+    double term = nn * exp((nn - 1.0) * ly);
+    sum += (n & 1) ? term : -term;
+    if (term < 1e-17 * fabs(sum)) break;
+  }
+  return 2.0 * sum;
+}
+
+// y in (0,1) with S(y) = u (FP64): Newton within a shrinking bracket.
+__device__ inline double mrw_solve(double u) {
+  double lo = 0.0, hi = 1.0, y = 0.5 * u;
+  if (!(y > 0.0)) y = 1e-300;
+  for (int it = 0; it < 200; ++it) {
+    double f = mrw_surv(y) - u;
+    if (f > 0.0) hi = y; else lo = y;
+    double df = mrw_dsurv(y);
+    double yn = (df > 0.0) ? y - f / df : 0.5 * (lo + hi);
+    if (!(yn > lo && yn < hi)) yn = 0.5 * (lo + hi);
+    if (fabs(yn - y) <= 1e-15 * y) {
+      y = yn;
+      break;
+    }
+    y = yn;
+  }
+  return y;
+}
+
+// Henyey-Greenstein inverse CDF of cos(beta) and phase function (Eq. 15).
+template <typename R> __device__ __forceinline__ R hg_mu(R g, R u) {
+  if (m_fabs(g) < (R)1e-6) return (R)2 * u - (R)1;
+  R q = ((R)1 - g * g) / ((R)1 - g + (R)2 * g * u);
+  R mu = ((R)1 + g * g - q * q) / ((R)2 * g);
+  if (mu > (R)1) mu = (R)1;
+  if (mu < (R)-1) mu = (R)-1;
+  return mu;
+}
+template <typename R> __device__ __forceinline__ R hg_phase(R g, R mu) {
+  R den = (R)1 + g * g - (R)2 * g * mu;
+  return ((R)1 - g * g) / ((R)4 * (R)PI_D * den * m_sqrt(den));
+}
+
+// Device fill (kept as a kernel so that graph captures record no memsets).
+template <typename T> __global__ void k_fill(T *p, T v, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+}  // namespace mcrt

@@ -1,0 +1,395 @@
+// mcrt_raytrace.hip - ray-tracer of sect. 4 (Eqs. 11-17) and its adjoint.
+//
+// One lane per pixel ray. Rays are parallel to -k (k toward the observer)
+// through a square field of side sqrt(3) x box edge and march front to back
+// with the same voxel walk as the transport. Every imaged wavelength of a
+// ray is carried in registers, so a cell crossing reads the density once
+// and one contiguous vector of source functions S[view][cell][0..n_img)
+// that is built per view before the march (emission plus scattered light,
+// both per unit extinction; constant in the traced density).
+// Intensities and transmittances accumulate in FP64 in both precisions.
+#include "mcrt_rtargs.h"
+
+namespace mcrt {
+
+template <typename R>
+__device__ __forceinline__ double plane_d(const RtArgs &A, double p0, double d, int c, int k) {
+  if (d > 0.0) return (A.origin[k] + (double)(c + 1) * A.dcell - p0) / d;
+  if (d < 0.0) return (A.origin[k] + (double)c * A.dcell - p0) / d;
+  return __builtin_huge_val();
+}
+
+// Entry of pixel ray (ix, iy) of view v into the box; false when it misses.
+__device__ inline bool ray_entry(const RtArgs &A, const RtView &V, int ix, int iy, double pe[3],
+                                 double dir[3], int c[3]) {
+  double xp = ((double)ix + 0.5) * V.dpx - 0.5 * V.fov;
+  double yp = ((double)iy + 0.5) * V.dpy - 0.5 * V.fov;
+  double r0[3];
+  int n[3] = {A.nx, A.ny, A.nz};
+  double tmin = -__builtin_huge_val(), tmax = __builtin_huge_val();
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r0[k] = V.ctr[k] + xp * V.ex[k] + yp * V.ey[k] + V.fov * V.k[k];
+    dir[k] = -V.k[k];
+    double lo = A.origin[k], hi = A.origin[k] + (double)n[k] * A.dcell;
+    if (dir[k] != 0.0) {
+      double t1 = (lo - r0[k]) / dir[k], t2 = (hi - r0[k]) / dir[k];
+      double a = t1 < t2 ? t1 : t2, b = t1 < t2 ? t2 : t1;
+      if (a > tmin) tmin = a;
+      if (b < tmax) tmax = b;
+    } else if (r0[k] < lo || r0[k] > hi) {
+      return false;
+    }
+  }
+  if (!(tmin < tmax)) return false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pe[k] = r0[k] + tmin * dir[k];
+    double q = (pe[k] - A.origin[k]) / A.dcell;
+    double f = floor(q);
+    int ci = (int)f;
+    if (q == f && dir[k] < 0.0) ci -= 1;
+    if (ci < 0) ci = 0;
+    if (ci >= n[k]) ci = n[k] - 1;
+    c[k] = ci;
+  }
+  return true;
+}
+
+// Voxel walk calling seg(cell, length) for every segment (FP64 geometry).
+template <typename F>
+__device__ __forceinline__ void walk(const RtArgs &A, const double p0[3], const double d[3],
+                                     int c0[3], F seg) {
+  int cx = c0[0], cy = c0[1], cz = c0[2];
+  if (cx < 0 || cx >= A.nx || cy < 0 || cy >= A.ny || cz < 0 || cz >= A.nz) return;
+  double tx = plane_d<double>(A, p0[0], d[0], cx, 0);
+  double ty = plane_d<double>(A, p0[1], d[1], cy, 1);
+  double tz = plane_d<double>(A, p0[2], d[2], cz, 2);
+  const int sx = d[0] > 0.0 ? 1 : -1, sy = d[1] > 0.0 ? 1 : -1, sz = d[2] > 0.0 ? 1 : -1;
+  double t = 0.0;
+  int64_t c = ((int64_t)cz * A.ny + cy) * A.nx + cx;
+  for (;;) {
+    int a = 0;
+    double tn = tx;
+    if (ty < tn) { a = 1; tn = ty; }
+    if (tz < tn) { a = 2; tn = tz; }
+    double ell = tn - t;
+    if (ell < 0.0) ell = 0.0;
+    seg(c, ell);
+    if (tn > t) t = tn;
+    if (a == 0) {
+      cx += sx;
+      if (cx < 0 || cx >= A.nx) return;
+      c += sx;
+      tx = plane_d<double>(A, p0[0], d[0], cx, 0);
+    } else if (a == 1) {
+      cy += sy;
+      if (cy < 0 || cy >= A.ny) return;
+      c += (int64_t)sy * A.nx;
+      ty = plane_d<double>(A, p0[1], d[1], cy, 1);
+    } else {
+      cz += sz;
+      if (cz < 0 || cz >= A.nz) return;
+      c += (int64_t)sz * A.nx * A.ny;
+      tz = plane_d<double>(A, p0[2], d[2], cz, 2);
+    }
+  }
+}
+
+// 1 - e^-x and e^-x of one segment in the walk precision.
+__device__ __forceinline__ void absorb_pair(double x, double &om, double &e) {
+  om = -expm1(-x);
+  e = exp(-x);
+}
+__device__ __forceinline__ void absorb_pair(float x, float &om, float &e) {
+  om = -expm1f(-x);
+  e = expf(-x);
+}
+
+// S[v][c][q] = sum_s f_s kabs_s B(T_s)/kext + Ssca/(V w rho kext).
+template <typename R>
+__global__ void k_build_S(const ModelDev *__restrict__ md, int v, R *S) {
+  const ModelDev &M = *md;
+  TabOff o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
+  const R *rho = (const R *)M.rho;
+  const R *ss = (const R *)M.ssca;
+  const int nq = M.nimg;
+  uint64_t n = M.ncell * (uint64_t)nq;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    uint64_t c = i / nq;
+    int q = (int)(i - c * nq);
+    int j = 0;
+    for (int jj = 0; jj < M.nl; ++jj)
+      if (M.imgmap[jj] == q) j = jj;
+    double em = 0.0;
+    for (int s = 0; s < M.ns; ++s) {
+      if (s == M.pah) continue;
+      em += M.tab[o.frac + s] * M.tab[o.kabs + s * M.nl + j] *
+            planck_d(M.tab[o.hnu + j], M.tab[o.a + j], M.T[(uint64_t)s * M.ncell + c]);
+    }
+    double ke = M.tab[o.kext + j];
+    double val = em / ke;
+    double r = (double)rho[c];
+    if (ss && r > 0.0)
+      val += (double)ss[((uint64_t)v * nq + q) * M.ncell + c] / (M.V * M.tab[o.w + j] * r * ke);
+    S[((uint64_t)v * M.ncell + c) * nq + q] = (R)val;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R *img) {
+  const RtArgs &A = *Ap;
+  const int v = blockIdx.y;
+  const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pix >= A.npx * A.npy) return;
+  const int ix = pix % A.npx, iy = pix / A.npx;
+  const RtView &V = A.v[v];
+  const int nq = A.nimg;
+  const R *rho = (const R *)A.rho;
+  const R *S = (const R *)A.S + (uint64_t)v * A.ncell * nq;
+  double I[MAX_IMG], tr[MAX_IMG];
+  R kx[MAX_IMG];
+#pragma unroll
+  for (int q = 0; q < MAX_IMG; ++q) {
+    I[q] = 0.0;
+    tr[q] = 1.0;
+    kx[q] = (R)A.kext[q];
+  }
+  double pe[3], dir[3];
+  int c[3];
+  if (ray_entry(A, V, ix, iy, pe, dir, c)) {
+    walk(A, pe, dir, c, [&](int64_t cell, double ell) {
+      R r = rho[cell];
+      if (!(r > (R)0)) return;
+      const R *sc = S + (uint64_t)cell * nq;
+      R el = (R)ell;
+#pragma unroll
+      for (int q = 0; q < MAX_IMG; ++q) {
+        if (q >= nq) break;
+        R dtau = r * kx[q] * el;
+        R om, e;
+        absorb_pair(dtau, om, e);
+        I[q] += tr[q] * (double)sc[q] * (double)om;
+        tr[q] *= (double)e;
+      }
+    });
+  }
+  const uint64_t plane = (uint64_t)A.npx * A.npy;
+#pragma unroll
+  for (int q = 0; q < MAX_IMG; ++q) {
+    if (q >= nq) break;
+    img[((uint64_t)v * nq + q) * plane + pix] = (R)(V.apix_d2 * I[q]);
+  }
+}
+
+// Attenuated point sources: one lane per (view, source, imaged wavelength).
+template <typename R>
+__global__ void k_rt_star(const RtArgs *__restrict__ Ap, R *img, double *sed) {
+  const RtArgs &A = *Ap;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int q = t % A.nimg, s = (t / A.nimg) % A.nsrc, v = t / (A.nimg * A.nsrc);
+  if (v >= A.nview) return;
+  const RtView &V = A.v[v];
+  const R *rho = (const R *)A.rho;
+  double p0[3] = {A.srcpos[s][0], A.srcpos[s][1], A.srcpos[s][2]};
+  int c[3];
+  for (int k = 0; k < 3; ++k) {
+    double qq = (p0[k] - A.origin[k]) / A.dcell;
+    double f = floor(qq);
+    int ci = (int)f;
+    if (qq == f && V.k[k] < 0.0) ci -= 1;
+    c[k] = ci;
+  }
+  double tau = 0.0;
+  walk(A, p0, V.k, c, [&](int64_t cell, double ell) { tau += (double)rho[cell] * A.kext[q] * ell; });
+  double F = A.lnu[s][q] / (4.0 * PI_D * A.D2) * exp(-tau);
+  double xp = 0.0, yp = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    xp += (p0[k] - V.ctr[k]) * V.ex[k];
+    yp += (p0[k] - V.ctr[k]) * V.ey[k];
+  }
+  int ix = (int)floor((xp + 0.5 * V.fov) / V.dpx), iy = (int)floor((yp + 0.5 * V.fov) / V.dpy);
+  if (ix >= 0 && ix < A.npx && iy >= 0 && iy < A.npy)
+    atomicAdd(&img[((uint64_t)v * A.nimg + q) * A.npx * A.npy + (uint64_t)iy * A.npx + ix], (R)F);
+  if (sed) atomicAdd(&sed[v * A.nimg + q], F);
+}
+
+// SED of the dust: one block per (view, wavelength), fixed-order tree sum.
+template <typename R>
+__global__ void k_rt_sed(const RtArgs *__restrict__ Ap, const R *img, double *sed) {
+  const RtArgs &A = *Ap;
+  const int vq = blockIdx.x;
+  const uint64_t plane = (uint64_t)A.npx * A.npy;
+  const R *p = img + (uint64_t)vq * plane;
+  double acc = 0.0;
+  for (uint64_t i = threadIdx.x; i < plane; i += blockDim.x) acc += (double)p[i];
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sed[vq] = red[0];
+}
+
+// Adjoint: first sweep gives I per wavelength, the second recomputes the
+// transmittance and the gathered intensity A_i in front of each cell:
+// dI/d(dtau_i) = T_<i S_i e^-dtau_i - (I - A_i), d(dtau_i)/d(rho_i) = kext l_i.
+template <typename R>
+__global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, const R *w_img,
+                                                const double *w_sed, R *drho) {
+  const RtArgs &A = *Ap;
+  const int v = blockIdx.y;
+  const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pix >= A.npx * A.npy) return;
+  const int ix = pix % A.npx, iy = pix / A.npx;
+  const RtView &V = A.v[v];
+  const int nq = A.nimg;
+  const R *rho = (const R *)A.rho;
+  const R *S = (const R *)A.S + (uint64_t)v * A.ncell * nq;
+  const uint64_t plane = (uint64_t)A.npx * A.npy;
+  double W[MAX_IMG], I[MAX_IMG], tr[MAX_IMG], acc[MAX_IMG];
+  R kx[MAX_IMG];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < MAX_IMG; ++q) {
+    W[q] = 0.0;
+    if (q < nq) {
+      W[q] = (w_img ? (double)w_img[((uint64_t)v * nq + q) * plane + pix] : 0.0) +
+             (w_sed ? w_sed[v * nq + q] : 0.0);
+      W[q] *= V.apix_d2;
+    }
+    any |= (W[q] != 0.0);
+    I[q] = 0.0;
+    tr[q] = 1.0;
+    acc[q] = 0.0;
+    kx[q] = (R)A.kext[q];
+  }
+  if (!any) return;
+  double pe[3], dir[3];
+  int c[3];
+  if (!ray_entry(A, V, ix, iy, pe, dir, c)) return;
+  walk(A, pe, dir, c, [&](int64_t cell, double ell) {
+    R r = rho[cell];
+    if (!(r > (R)0)) return;
+    const R *sc = S + (uint64_t)cell * nq;
+    R el = (R)ell;
+#pragma unroll
+    for (int q = 0; q < MAX_IMG; ++q) {
+      if (q >= nq) break;
+      R om, e;
+      absorb_pair(r * kx[q] * el, om, e);
+      I[q] += tr[q] * (double)sc[q] * (double)om;
+      tr[q] *= (double)e;
+    }
+  });
+#pragma unroll
+  for (int q = 0; q < MAX_IMG; ++q) tr[q] = 1.0;
+  walk(A, pe, dir, c, [&](int64_t cell, double ell) {
+    R r = rho[cell];
+    if (!(r > (R)0)) return;
+    const R *sc = S + (uint64_t)cell * nq;
+    R el = (R)ell;
+    double g = 0.0;
+#pragma unroll
+    for (int q = 0; q < MAX_IMG; ++q) {
+      if (q >= nq) break;
+      R om, e;
+      absorb_pair(r * kx[q] * el, om, e);
+      double Sq = (double)sc[q];
+      acc[q] += tr[q] * Sq * (double)om;
+      double dI = tr[q] * Sq * (double)e - (I[q] - acc[q]);
+      g += W[q] * A.kext[q] * ell * dI;
+      tr[q] *= (double)e;
+    }
+    if (g != 0.0) atomicAdd(&drho[cell], (R)g);
+  });
+}
+
+// Adjoint of the attenuated point-source term.
+template <typename R>
+__global__ void k_rt_star_adj(const RtArgs *__restrict__ Ap, const R *w_img, const double *w_sed,
+                              R *drho) {
+  const RtArgs &A = *Ap;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int q = t % A.nimg, s = (t / A.nimg) % A.nsrc, v = t / (A.nimg * A.nsrc);
+  if (v >= A.nview) return;
+  const RtView &V = A.v[v];
+  const R *rho = (const R *)A.rho;
+  double p0[3] = {A.srcpos[s][0], A.srcpos[s][1], A.srcpos[s][2]};
+  int c[3];
+  for (int k = 0; k < 3; ++k) {
+    double qq = (p0[k] - A.origin[k]) / A.dcell;
+    double f = floor(qq);
+    int ci = (int)f;
+    if (qq == f && V.k[k] < 0.0) ci -= 1;
+    c[k] = ci;
+  }
+  double xp = 0.0, yp = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    xp += (p0[k] - V.ctr[k]) * V.ex[k];
+    yp += (p0[k] - V.ctr[k]) * V.ey[k];
+  }
+  int ix = (int)floor((xp + 0.5 * V.fov) / V.dpx), iy = (int)floor((yp + 0.5 * V.fov) / V.dpy);
+  bool inimg = ix >= 0 && ix < A.npx && iy >= 0 && iy < A.npy;
+  double W = (w_sed ? w_sed[v * A.nimg + q] : 0.0) +
+             ((inimg && w_img) ? (double)w_img[((uint64_t)v * A.nimg + q) * A.npx * A.npy +
+                                               (uint64_t)iy * A.npx + ix]
+                               : 0.0);
+  if (W == 0.0) return;
+  double tau = 0.0;
+  walk(A, p0, V.k, c, [&](int64_t cell, double ell) { tau += (double)rho[cell] * A.kext[q] * ell; });
+  double F = A.lnu[s][q] / (4.0 * PI_D * A.D2) * exp(-tau);
+  walk(A, p0, V.k, c, [&](int64_t cell, double ell) {
+    atomicAdd(&drho[cell], (R)(-W * A.kext[q] * ell * F));
+  });
+}
+
+hipError_t launch_build_S(const ModelDev *d, int v, bool fp64, void *S, hipStream_t st) {
+  if (fp64) hipLaunchKernelGGL(k_build_S<double>, dim3(4096), dim3(256), 0, st, d, v, (double *)S);
+  else hipLaunchKernelGGL(k_build_S<float>, dim3(4096), dim3(256), 0, st, d, v, (float *)S);
+  return hipGetLastError();
+}
+
+hipError_t launch_rt_fwd(const RtArgs *dA, const RtArgs &hA, bool fp64, void *img, double *sed,
+                         hipStream_t st) {
+  dim3 grid((hA.npx * hA.npy + 255) / 256, hA.nview);
+  int nstar = hA.nview * hA.nsrc * hA.nimg;
+  if (fp64) {
+    hipLaunchKernelGGL(k_rt_fwd<double>, grid, dim3(256), 0, st, dA, (double *)img);
+    if (sed) hipLaunchKernelGGL(k_rt_sed<double>, dim3(hA.nview * hA.nimg), dim3(256), 0, st, dA,
+                                (const double *)img, sed);
+    if (nstar) hipLaunchKernelGGL(k_rt_star<double>, dim3((nstar + 63) / 64), dim3(64), 0, st, dA,
+                                  (double *)img, sed);
+  } else {
+    hipLaunchKernelGGL(k_rt_fwd<float>, grid, dim3(256), 0, st, dA, (float *)img);
+    if (sed) hipLaunchKernelGGL(k_rt_sed<float>, dim3(hA.nview * hA.nimg), dim3(256), 0, st, dA,
+                                (const float *)img, sed);
+    if (nstar) hipLaunchKernelGGL(k_rt_star<float>, dim3((nstar + 63) / 64), dim3(64), 0, st, dA,
+                                  (float *)img, sed);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rt_adj(const RtArgs *dA, const RtArgs &hA, bool fp64, const void *w_img,
+                         const double *w_sed, void *drho, hipStream_t st) {
+  dim3 grid((hA.npx * hA.npy + 255) / 256, hA.nview);
+  int nstar = hA.nview * hA.nsrc * hA.nimg;
+  if (fp64) {
+    hipLaunchKernelGGL(k_rt_adj<double>, grid, dim3(256), 0, st, dA, (const double *)w_img, w_sed,
+                       (double *)drho);
+    if (nstar) hipLaunchKernelGGL(k_rt_star_adj<double>, dim3((nstar + 63) / 64), dim3(64), 0, st,
+                                  dA, (const double *)w_img, w_sed, (double *)drho);
+  } else {
+    hipLaunchKernelGGL(k_rt_adj<float>, grid, dim3(256), 0, st, dA, (const float *)w_img, w_sed,
+                       (float *)drho);
+    if (nstar) hipLaunchKernelGGL(k_rt_star_adj<float>, dim3((nstar + 63) / 64), dim3(64), 0, st,
+                                  dA, (const float *)w_img, w_sed, (float *)drho);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mcrt

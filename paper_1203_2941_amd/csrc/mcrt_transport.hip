@@ -1,0 +1,794 @@
+// mcrt_transport.hip - Monte Carlo packet transport (sect. 2-3 of Heymann &
+// Siebenmorgen) as one persistent kernel for gfx950.
+//
+// Each block picks a model that still has packets (one model for
+// run_packets, many for run_batch), stages that model's opacity, Planck and
+// source tables in LDS, and its 64-wide waves refill lanes from the model's
+// packet counter with one atomic per wave. A lane runs its packet event by
+// event: emission (Eq. 1 packets, isotropic directions), optional modified
+// random walk (sect. 3.2), one flight of sampled optical depth through the
+// voxel grid (Eqs. 2-3) with Lucy deposits in thin cells (Eq. 9), then an
+// interaction: Henyey-Greenstein scattering (Eq. 15) or absorption with
+// re-emission by Eq. 5 (iterative scheme) or Eq. 10 (Bjorkman & Wood).
+// Escapes are counted into an LDS copy of the photon-counting SED.
+#include "mcrt_internal.h"
+
+namespace mcrt {
+
+template <typename R>
+struct Pkt {
+  R p[3], d[3];
+  int c[3];
+  int j, status;
+  uint64_t pid;
+  Rng rng;
+  uint32_t n_cross, n_scat, n_abs, n_mrw, n_lucy, n_int;
+  double mm;
+};
+
+template <typename R>
+struct Ctx {
+  const ModelDev *M;
+  TabOff o;
+  const double *dt;   // LDS double table
+  const R *rt;        // LDS R table
+  const int *imgmap;  // LDS
+  uint32_t *sed;      // LDS SED counts
+  const R *rho;
+  int64_t nc;
+  unsigned long long *st;  // LDS block counters [NSTAT]
+};
+
+__device__ __forceinline__ void stat_add(unsigned long long *st, int i, unsigned long long v) {
+  atomicAdd(&st[i], v);
+}
+
+template <typename R>
+__device__ __forceinline__ R plane_t(const ModelDev &M, R p0, R d, int c, int k) {
+  if (d > (R)0) return ((R)M.origin[k] + (R)(c + 1) * (R)M.dcell - p0) / d;
+  if (d < (R)0) return ((R)M.origin[k] + (R)c * (R)M.dcell - p0) / d;
+  return m_inf<R>();
+}
+
+template <typename R>
+__device__ __forceinline__ void start_cell(const ModelDev &M, const R p[3], const R d[3], int c[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    R q = (p[k] - (R)M.origin[k]) / (R)M.dcell;
+    R f = m_floor(q);
+    int ci = (int)f;
+    if (q == f && d[k] < (R)0) ci -= 1;
+    c[k] = ci;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void iso_dir(R uphi, R umu, R d[3]) {
+  R phi = (R)2 * (R)PI_D * uphi;
+  R mu = (R)1 - (R)2 * umu;
+  R t = (R)1 - mu * mu;
+  R s = m_sqrt(t > (R)0 ? t : (R)0);
+  d[0] = s * m_cos(phi);
+  d[1] = s * m_sin(phi);
+  d[2] = mu;
+}
+
+template <typename R>
+__device__ __forceinline__ void rotate_dir(R d[3], R mu, R phi) {
+  R t = (R)1 - mu * mu;
+  R st = m_sqrt(t > (R)0 ? t : (R)0);
+  R cp = m_cos(phi), sp = m_sin(phi);
+  R nx, ny, nz;
+  if (m_fabs(d[2]) > (R)1 - (R)1e-10) {
+    nx = st * cp;
+    ny = st * sp;
+    nz = (d[2] > (R)0) ? mu : -mu;
+  } else {
+    R s = m_sqrt((R)1 - d[2] * d[2]);
+    nx = st * (d[0] * d[2] * cp - d[1] * sp) / s + d[0] * mu;
+    ny = st * (d[1] * d[2] * cp + d[0] * sp) / s + d[1] * mu;
+    nz = -st * cp * s + d[2] * mu;
+  }
+  R nn = m_sqrt(nx * nx + ny * ny + nz * nz);
+  d[0] = nx / nn;
+  d[1] = ny / nn;
+  d[2] = nz / nn;
+}
+
+// Smallest index whose ascending running sum of f[q*stride] reaches u times
+// the total (f read from LDS).
+template <typename R, bool REC, typename T>
+__device__ __forceinline__ int pick_asc(const T *f, int stride, int n, R u, double &mm) {
+  R tot = (R)0;
+  for (int q = 0; q < n; ++q) tot += (R)f[q * stride];
+  R target = u * tot, c = (R)0;
+  for (int q = 0; q < n; ++q) {
+    R prev = c;
+    c += (R)f[q * stride];
+    if (c >= target) {
+      if (REC && tot > (R)0 && n > 1) {
+        upd_margin(mm, (double)((c - target) / tot));
+        upd_margin(mm, (double)((target - prev) / tot));
+      }
+      return q;
+    }
+  }
+  return n - 1;
+}
+
+// Inverse CDF over ascending frequency (descending index) of a spectrum
+// given by a functor; evaluated twice so that no per-lane array is needed.
+template <typename R, bool REC, typename F>
+__device__ __forceinline__ int pick_desc_fn(int n, R u, double &mm, F f) {
+  R tot = (R)0;
+  for (int j = n - 1; j >= 0; --j) tot += f(j);
+  R target = u * tot, c = (R)0;
+  for (int j = n - 1; j >= 0; --j) {
+    R prev = c;
+    c += f(j);
+    if (c >= target) {
+      if (REC && tot > (R)0) {
+        upd_margin(mm, (double)((c - target) / tot));
+        upd_margin(mm, (double)((target - prev) / tot));
+      }
+      return j;
+    }
+  }
+  return 0;
+}
+
+template <typename R>
+__device__ __forceinline__ bool is_thin(const Ctx<R> &X, R rho) {
+  const ModelDev &M = *X.M;
+  return M.lucy_tau > 0.0 && rho > (R)0 &&
+         rho * (R)M.kext_max * (R)M.dcell < (R)M.lucy_tau;
+}
+
+__device__ __forceinline__ double energy_of(const ModelDev &M, int64_t q) {
+  return (double)M.k[q] * M.xi + M.epath[q];
+}
+
+// Emission temperature of species s in cell c (see mcrt.h for the modes).
+template <typename R>
+__device__ double mode_T(Ctx<R> &X, int s, int64_t c, double rho) {
+  const ModelDev &M = *X.M;
+  int64_t q = (int64_t)s * X.nc + c;
+  if (M.mode == M_FROZEN) {
+    double T = M.T[q];
+    return (T > 0.0) ? T : T_FLOOR;
+  }
+  double frac = X.dt[X.o.frac + s];
+  bool cl = false;
+  double T;
+  if (M.mode == M_BW_EPOCH) {
+    T = M.tt[q];
+    if (T < 0.0) {
+      double rhs = (M.esnap[q] + M.xi) / (4.0 * PI_D * frac * rho * M.V);
+      T = invert_T(X.dt, X.o, M.nl, s, rhs, &cl);
+      M.tt[q] = T;  // every lane computes the same value from the snapshot
+    }
+  } else {
+    double e = (double)(*(volatile uint64_t *)&M.k[q]) * M.xi + *(volatile double *)&M.epath[q];
+    double rhs = (e + M.xi) / (4.0 * PI_D * frac * rho * M.V);
+    T = invert_T(X.dt, X.o, M.nl, s, rhs, &cl);
+  }
+  if (cl) stat_add(X.st, 9, 1ull);
+  return T;
+}
+
+// Lucy's estimator (Eq. 9) on one segment inside a thin cell.
+template <typename R>
+__device__ __forceinline__ void lucy_deposit(Ctx<R> &X, Pkt<R> &P, int64_t c, R rho, R ell) {
+  const ModelDev &M = *X.M;
+  int nl = M.nl, j = P.j;
+  R em = -m_expm1(-(rho * X.rt[X.o.r_kabsm + j] * ell));
+  for (int s = 0; s < M.ns; ++s) {
+    R f = X.rt[X.o.r_lucy + s * nl + j];
+    if (f == (R)0) continue;
+    atomicAdd(&M.epath[(int64_t)s * X.nc + c], (double)((R)M.xi * f * em));
+  }
+  M.dirty[c] = 1;
+  P.n_lucy++;
+}
+
+// One flight with optical depth tau_star. Returns true on escape.
+template <typename R, bool REC>
+__device__ bool fly(Ctx<R> &X, Pkt<R> &P, R tau_star) {
+  const ModelDev &M = *X.M;
+  const R p0x = P.p[0], p0y = P.p[1], p0z = P.p[2];
+  const R dx = P.d[0], dy = P.d[1], dz = P.d[2];
+  int cx = P.c[0], cy = P.c[1], cz = P.c[2];
+  R tx = plane_t<R>(M, p0x, dx, cx, 0);
+  R ty = plane_t<R>(M, p0y, dy, cy, 1);
+  R tz = plane_t<R>(M, p0z, dz, cz, 2);
+  const R kx = X.rt[X.o.r_kext + P.j];
+  const int sx = dx > (R)0 ? 1 : -1, sy = dy > (R)0 ? 1 : -1, sz = dz > (R)0 ? 1 : -1;
+  R t = (R)0, tau = (R)0;
+  int64_t c = ((int64_t)cz * M.ny + cy) * M.nx + cx;
+  for (;;) {
+    int a = 0;
+    R tn = tx;
+    if (ty < tn) { a = 1; tn = ty; }
+    if (tz < tn) { a = 2; tn = tz; }
+    if (REC) {
+      R t2 = (a == 0) ? (ty < tz ? ty : tz) : (a == 1) ? (tx < tz ? tx : tz) : (tx < ty ? tx : ty);
+      if (t2 < m_inf<R>() && t2 > (R)0) upd_margin(P.mm, (double)((t2 - tn) / t2));
+    }
+    R ell = tn - t;
+    if (ell < (R)0) ell = (R)0;
+    R rho = X.rho[c];
+    R dtau = rho * kx * ell;
+    bool thin = is_thin(X, rho);
+    if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tau_star) / tau_star));
+    if (tau + dtau > tau_star) {
+      R tint = t + (tau_star - tau) / (rho * kx);
+      if (thin) lucy_deposit(X, P, c, rho, tint - t);
+      P.p[0] = p0x + tint * dx;
+      P.p[1] = p0y + tint * dy;
+      P.p[2] = p0z + tint * dz;
+      P.c[0] = cx; P.c[1] = cy; P.c[2] = cz;
+      return false;
+    }
+    if (thin) lucy_deposit(X, P, c, rho, ell);
+    tau += dtau;
+    if (tn > t) t = tn;
+    P.n_cross++;
+    if (a == 0) {
+      cx += sx;
+      if (cx < 0 || cx >= M.nx) break;
+      c += sx;
+      tx = plane_t<R>(M, p0x, dx, cx, 0);
+    } else if (a == 1) {
+      cy += sy;
+      if (cy < 0 || cy >= M.ny) break;
+      c += (int64_t)sy * M.nx;
+      ty = plane_t<R>(M, p0y, dy, cy, 1);
+    } else {
+      cz += sz;
+      if (cz < 0 || cz >= M.nz) break;
+      c += (int64_t)sz * M.nx * M.ny;
+      tz = plane_t<R>(M, p0z, dz, cz, 2);
+    }
+  }
+  P.p[0] = p0x + t * dx;
+  P.p[1] = p0y + t * dy;
+  P.p[2] = p0z + t * dz;
+  P.c[0] = cx; P.c[1] = cy; P.c[2] = cz;
+  return true;
+}
+
+template <typename R>
+__device__ double rosseland(const Ctx<R> &X, double T) {
+  const ModelDev &M = *X.M;
+  double num = 0.0, den = 0.0;
+  for (int j = M.nl - 1; j >= 0; --j) {
+    double ke = X.dt[X.o.kext + j];
+    if (!(ke > 0.0)) return 0.0;
+    double db = X.dt[X.o.w + j] * dplanck_d(X.dt[X.o.hnu + j], X.dt[X.o.a + j], T);
+    num += db;
+    den += db / ke;
+  }
+  return (den > 0.0) ? num / den : 0.0;
+}
+
+template <typename R>
+__device__ double planck_mean(const Ctx<R> &X, int s, double T) {
+  const ModelDev &M = *X.M;
+  double num = 0.0, den = 0.0;
+  for (int j = M.nl - 1; j >= 0; --j) {
+    double b = X.dt[X.o.w + j] * planck_d(X.dt[X.o.hnu + j], X.dt[X.o.a + j], T);
+    num += b * X.dt[X.o.kabs + s * M.nl + j];
+    den += b;
+  }
+  return (den > 0.0) ? num / den : 0.0;
+}
+
+__device__ __forceinline__ int first_thermal(const ModelDev &M) {
+  for (int s = 0; s < M.ns; ++s)
+    if (s != M.pah) return s;
+  return 0;
+}
+
+// Modified random walk step (sect. 3.2): see the public header for the
+// trigger. Returns true when a step was taken.
+template <typename R, bool REC>
+__device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
+  const ModelDev &M = *X.M;
+  if (!(M.mrw_tau > 0.0)) return false;
+  int64_t c = ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0];
+  double rho = (double)X.rho[c];
+  if (!(rho > 0.0)) return false;
+  if (!(rho * M.kext_max * M.dcell > M.mrw_tau)) return false;
+  int s0 = first_thermal(M);
+  double T0 = mode_T(X, s0, c, rho);
+  double kr = rosseland(X, T0);
+  double taur = rho * kr * M.dcell;
+  if (REC) upd_margin(P.mm, fabs(taur - M.mrw_tau) / M.mrw_tau);
+  if (!(taur > M.mrw_tau)) return false;
+  double Rs = 1e300;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double pk = (double)P.p[k];
+    double lo = pk - (M.origin[k] + (double)P.c[k] * M.dcell);
+    double hi = (M.origin[k] + (double)(P.c[k] + 1) * M.dcell) - pk;
+    if (lo < Rs) Rs = lo;
+    if (hi < Rs) Rs = hi;
+  }
+  if (Rs < 0.0) Rs = 0.0;
+  double crit = rho * kr * Rs;
+  if (REC) upd_margin(P.mm, fabs(crit - M.mrw_gamma) / M.mrw_gamma);
+  if (!(crit >= M.mrw_gamma)) return false;
+  double ut = rng_u<double>(P.rng), ups = rng_u<double>(P.rng), ums = rng_u<double>(P.rng);
+  R ul = rng_u<R>(P.rng), uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+  double y = mrw_solve(ut);
+  double ell = -3.0 * rho * kr * Rs * Rs * log(y) / (PI_D * PI_D);
+  double ds[3];
+  {
+    double phi = 2.0 * PI_D * ups, mu = 1.0 - 2.0 * ums;
+    double s = sqrt(fmax(0.0, 1.0 - mu * mu));
+    ds[0] = s * cos(phi);
+    ds[1] = s * sin(phi);
+    ds[2] = mu;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P.p[k] = (R)((double)P.p[k] + Rs * ds[k]);
+  const int nl = M.nl;
+  double Ts[MAX_NS];
+  for (int s = 0; s < M.ns; ++s) {
+    Ts[s] = 0.0;
+    if (s == M.pah) continue;
+    Ts[s] = mode_T(X, s, c, rho);
+    double kp = planck_mean(X, s, Ts[s]);
+    atomicAdd(&M.epath[(int64_t)s * X.nc + c], M.xi * rho * X.dt[X.o.frac + s] * kp * ell);
+  }
+  M.dirty[c] = 1;
+  P.j = pick_desc_fn<double, REC>(nl, (double)ul, P.mm, [&](int j) {
+    double f = 0.0;
+    for (int s = 0; s < M.ns; ++s) {
+      if (s == M.pah) continue;
+      f += X.dt[X.o.wfk + s * nl + j] * planck_d(X.dt[X.o.hnu + j], X.dt[X.o.a + j], Ts[s]);
+    }
+    return f;
+  });
+  iso_dir<R>(uph, umu, P.d);
+  P.n_mrw++;
+  stat_add(X.st, 7, 1ull);
+  return true;
+}
+
+template <typename R>
+__device__ __forceinline__ int pah_row(const Ctx<R> &X, int64_t c) {
+  const ModelDev &M = *X.M;
+  double rho = (double)X.rho[c];
+  double q = (double)M.kpah[c] * M.xi / (4.0 * PI_D * X.dt[X.o.frac + M.pah] * rho * M.V);
+  int r = 0;
+  while (r < M.nrows - 1 && q >= X.dt[X.o.pahe + r]) r++;
+  return r;
+}
+
+template <typename R, bool REC>
+__device__ __forceinline__ int pick_pah(const Ctx<R> &X, int row, R u, double &mm) {
+  const double *pw = X.dt + X.o.pahw + row * X.M->nl;
+  return pick_desc_fn<double, REC>(X.M->nl, (double)u, mm, [&](int j) { return pw[j]; });
+}
+
+// Re-emission wavelength of species s at temperature T: Eq. 5 (FROZEN) or
+// Eq. 10 (Bjorkman & Wood), in the walk precision.
+template <typename R, bool REC>
+__device__ __forceinline__ int pick_thermal(const Ctx<R> &X, int s, double T, R u, double &mm) {
+  const ModelDev &M = *X.M;
+  const int nl = M.nl;
+  if (sizeof(R) == 8) {
+    const double *wk = X.dt + X.o.wk + s * nl;
+    const double *hnu = X.dt + X.o.hnu;
+    const double *a = X.dt + X.o.a;
+    if (M.mode == M_FROZEN)
+      return pick_desc_fn<double, REC>(nl, (double)u, mm,
+                                       [&](int j) { return wk[j] * planck_d(hnu[j], a[j], T); });
+    return pick_desc_fn<double, REC>(nl, (double)u, mm,
+                                     [&](int j) { return wk[j] * dplanck_d(hnu[j], a[j], T); });
+  } else {
+    const R *wk = X.rt + X.o.r_wk + s * nl;
+    const R *hnu = X.rt + X.o.r_hnu;
+    const R *a = X.rt + X.o.r_a;
+    const R kT = (R)(K_BO * T);
+    const R Tr = (R)T;
+    const R cut = x_cut<R>();
+    if (M.mode == M_FROZEN)
+      return pick_desc_fn<R, REC>(nl, u, mm, [&](int j) {
+        R x = hnu[j] / kT;
+        return x > cut ? (R)0 : wk[j] * (a[j] / m_expm1(x));
+      });
+    return pick_desc_fn<R, REC>(nl, u, mm, [&](int j) {
+      R x = hnu[j] / kT;
+      if (x > cut) return (R)0;
+      R em = m_expm1(x);
+      R B = a[j] / em;
+      return wk[j] * (B * (x / Tr) * ((R)1 + (R)1 / em));
+    });
+  }
+}
+
+template <typename R, bool REC>
+__device__ void finish(Ctx<R> &X, Pkt<R> &P) {
+  const ModelDev &M = *X.M;
+  stat_add(X.st, 4, P.n_cross);
+  if (P.n_lucy) stat_add(X.st, 8, P.n_lucy);
+  if (P.status == ST_ESCAPED) {
+    stat_add(X.st, 1, 1ull);
+    int nt = M.ntheta > 0 ? M.ntheta : 1;
+    R x = (P.d[2] + (R)1) * (R)0.5 * (R)nt;
+    int b = (int)m_floor(x);
+    if (b < 0) b = 0;
+    if (b >= nt) b = nt - 1;
+    if (REC && nt > 1) upd_margin(P.mm, (double)(m_fabs(x - m_floor(x + (R)0.5)) / (R)nt));
+    atomicAdd(&X.sed[b * M.nl + P.j], 1u);
+  } else if (P.status == ST_KILLED) {
+    stat_add(X.st, 2, 1ull);
+  } else if (P.status == ST_PAH_STOP) {
+    stat_add(X.st, 3, 1ull);
+  }
+  if (REC && M.rec) {
+    uint64_t slot = P.pid - M.id_base - M.rec_first;
+    uint64_t *r = (uint64_t *)M.rec + slot * 15;  // 120-byte mcrt_packet_record
+    double *rd = (double *)r;
+    r[0] = P.pid;
+    rd[1] = (double)P.p[0]; rd[2] = (double)P.p[1]; rd[3] = (double)P.p[2];
+    rd[4] = (double)P.d[0]; rd[5] = (double)P.d[1]; rd[6] = (double)P.d[2];
+    int32_t *ri = (int32_t *)(r + 7);
+    ri[0] = P.j;
+    ri[1] = P.status;
+    rd[8] = M.xi;
+    r[9] = P.n_cross; r[10] = P.n_scat; r[11] = P.n_abs; r[12] = P.n_mrw; r[13] = P.n_lucy;
+    rd[14] = P.mm;
+  }
+}
+
+// Start packet `idx` of the launch: source emission, or a PAH pass-2
+// packet born in the cell that owns it.
+template <typename R, bool REC>
+__device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
+  const ModelDev &M = *X.M;
+  const int nl = M.nl;
+  P.pid = M.id_base + M.first + idx;
+  rng_init(P.rng, M.seed, P.pid, (uint32_t)M.iter, (uint32_t)M.model_id, M.pass == 2 ? 3u : 0u);
+  P.status = ST_ALIVE;
+  P.n_cross = P.n_scat = P.n_abs = P.n_mrw = P.n_lucy = P.n_int = 0;
+  P.mm = 1e300;
+  stat_add(X.st, 0, 1ull);
+  if (M.pass == 2) {
+    // cell owning local packet index (first + idx) in the exclusive prefix of PAH counts
+    uint64_t li = M.first + idx;
+    int64_t lo = 0, hi = X.nc - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) >> 1;
+      if (M.kpah_prefix[mid] <= li) lo = mid; else hi = mid - 1;
+    }
+    int64_t c = lo;
+    int cc[3] = {(int)(c % M.nx), (int)((c / M.nx) % M.ny), (int)(c / ((int64_t)M.nx * M.ny))};
+    R u3[3];
+    u3[0] = rng_u<R>(P.rng);
+    u3[1] = rng_u<R>(P.rng);
+    u3[2] = rng_u<R>(P.rng);
+    R ul = rng_u<R>(P.rng), uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      P.c[k] = cc[k];
+      P.p[k] = (R)M.origin[k] + ((R)cc[k] + u3[k]) * (R)M.dcell;
+    }
+    P.j = pick_pah<R, REC>(X, pah_row(X, c), ul, P.mm);
+    iso_dir<R>(uph, umu, P.d);
+    return;
+  }
+  R uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+  R us = rng_u<R>(P.rng), ul = rng_u<R>(P.rng);
+  iso_dir<R>(uph, umu, P.d);
+  int s = 0;
+  if (M.nsrc > 1) s = pick_asc<double, REC>(X.dt + X.o.lum, 1, M.nsrc, (double)us, P.mm);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P.p[k] = (R)X.dt[X.o.srcpos + 3 * s + k];
+  const double *sf = X.dt + X.o.srcf + s * nl;
+  P.j = pick_desc_fn<double, REC>(nl, (double)ul, P.mm, [&](int j) { return sf[j]; });
+  start_cell<R>(M, P.p, P.d, P.c);
+  if (P.c[0] < 0 || P.c[0] >= M.nx || P.c[1] < 0 || P.c[1] >= M.ny || P.c[2] < 0 ||
+      P.c[2] >= M.nz)
+    P.status = ST_ESCAPED;
+}
+
+// One event cycle: MRW steps, a flight, an interaction.
+template <typename R, bool REC>
+__device__ void advance(Ctx<R> &X, Pkt<R> &P) {
+  const ModelDev &M = *X.M;
+  const int nl = M.nl, ns = M.ns;
+  while (mrw_step<R, REC>(X, P)) {
+    P.n_int++;
+    if (M.max_int > 0 && P.n_int >= M.max_int) {
+      P.status = ST_KILLED;
+      return;
+    }
+  }
+  R tau_star = -m_log(rng_u<R>(P.rng));
+  if (fly<R, REC>(X, P, tau_star)) {
+    P.status = ST_ESCAPED;
+    return;
+  }
+  int64_t c = ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0];
+  R ualb = rng_u<R>(P.rng), usp = rng_u<R>(P.rng);
+  const int j = P.j;
+  const R alb = X.rt[X.o.r_alb + j];
+  if (REC) upd_margin(P.mm, (double)m_fabs(ualb - alb));
+  if (ualb < alb) {
+    int s = pick_asc<R, REC>(X.rt + X.o.r_fsca + j, nl, ns, usp, P.mm);
+    R g = X.rt[X.o.r_g + s * nl + j];
+    R umu = rng_u<R>(P.rng), uph = rng_u<R>(P.rng);
+    R mu = hg_mu<R>(g, umu);
+    int q = X.imgmap[j];
+    if (q >= 0) {
+      for (int v = 0; v < M.nview; ++v) {
+        R cb = P.d[0] * (R)M.kv[v][0] + P.d[1] * (R)M.kv[v][1] + P.d[2] * (R)M.kv[v][2];
+        R add = (R)M.xi * hg_phase<R>(g, cb);
+        atomicAdd((R *)M.ssca + ((int64_t)v * M.nimg + q) * X.nc + c, add);
+      }
+    }
+    rotate_dir<R>(P.d, mu, (R)2 * (R)PI_D * uph);
+    P.n_scat++;
+    stat_add(X.st, 5, 1ull);
+  } else {
+    int s = pick_asc<R, REC>(X.rt + X.o.r_fabs + j, nl, ns, usp, P.mm);
+    P.n_abs++;
+    stat_add(X.st, 6, 1ull);
+    if (s == M.pah) {
+      if (M.pass != 2) {
+        atomicAdd(&M.kpah[c], 1u);
+        P.status = ST_PAH_STOP;
+        return;
+      }
+      R ul = rng_u<R>(P.rng), uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+      P.j = pick_pah<R, REC>(X, pah_row(X, c), ul, P.mm);
+      iso_dir<R>(uph, umu, P.d);
+    } else {
+      R rho = X.rho[c];
+      bool thin = is_thin(X, rho);
+      int64_t qk = (int64_t)s * X.nc + c;
+      double T;
+      if (M.mode == M_BW_TICKET) {
+        uint64_t kold = thin ? *(volatile uint64_t *)&M.k[qk]
+                             : (uint64_t)atomicAdd((unsigned long long *)&M.k[qk], 1ull);
+        double e = (double)kold * M.xi + *(volatile double *)&M.epath[qk];
+        double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s] * (double)rho * M.V);
+        bool cl = false;
+        T = invert_T(X.dt, X.o, nl, s, rhs, &cl);
+        if (cl) stat_add(X.st, 9, 1ull);
+      } else {
+        if (!thin) atomicAdd((unsigned long long *)&M.k[qk], 1ull);
+        T = mode_T(X, s, c, (double)rho);
+      }
+      M.dirty[c] = 1;
+      R ul = rng_u<R>(P.rng), uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+      P.j = pick_thermal<R, REC>(X, s, T, ul, P.mm);
+      iso_dir<R>(uph, umu, P.d);
+    }
+  }
+  P.n_int++;
+  if (M.max_int > 0 && P.n_int >= M.max_int) P.status = ST_KILLED;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  uint32_t lo = __shfl((int)(uint32_t)v, src), hi = __shfl((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Block-wide choice of the next model with packets left (-1 when none).
+__device__ int pick_model(const ModelDev *models, int nmodels) {
+  int start = blockIdx.x % nmodels;
+  for (int i = 0; i < nmodels; ++i) {
+    int m = (start + i) % nmodels;
+    const ModelDev &M = models[m];
+    if (*(volatile uint64_t *)M.counter < M.n) return m;
+  }
+  return -1;
+}
+
+template <typename R, bool REC>
+__global__ void __launch_bounds__(256) k_transport(const ModelDev *__restrict__ models,
+                                                    int nmodels) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int s_model;
+  __shared__ unsigned long long s_stat[NSTAT];
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (;;) {
+    if (threadIdx.x == 0) s_model = pick_model(models, nmodels);
+    __syncthreads();
+    const int m = __builtin_amdgcn_readfirstlane(s_model);
+    if (m < 0) break;
+    const ModelDev &M = models[m];
+    Ctx<R> X;
+    X.M = &M;
+    X.o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
+    X.nc = (int64_t)M.ncell;
+    X.rho = (const R *)M.rho;
+    double *dt = (double *)lds_raw;
+    R *rt = (R *)(dt + X.o.dtotal);
+    int *im = (int *)(rt + X.o.r_total + (X.o.r_total & 1));
+    uint32_t *sed = (uint32_t *)(im + M.nl + (M.nl & 1));
+    for (int i = threadIdx.x; i < X.o.dtotal; i += blockDim.x) dt[i] = M.tab[i];
+    for (int i = threadIdx.x; i < X.o.r_total; i += blockDim.x) rt[i] = ((const R *)M.rtab)[i];
+    for (int i = threadIdx.x; i < M.nl; i += blockDim.x) im[i] = M.imgmap[i];
+    const int nsed = (M.ntheta > 0 ? M.ntheta : 1) * M.nl;
+    for (int i = threadIdx.x; i < nsed; i += blockDim.x) sed[i] = 0u;
+    if (threadIdx.x < NSTAT) s_stat[threadIdx.x] = 0ull;
+    __syncthreads();
+    X.dt = dt;
+    X.rt = rt;
+    X.imgmap = im;
+    X.sed = sed;
+    X.st = s_stat;
+
+    Pkt<R> P;
+    bool active = false, exhausted = false;
+    for (;;) {
+      uint64_t need = __ballot(!active && !exhausted);
+      if (need) {
+        int leader = __ffsll((unsigned long long)need) - 1;
+        uint64_t base = 0;
+        if (lane == leader) base = atomicAdd((unsigned long long *)M.counter,
+                                             (unsigned long long)__popcll(need));
+        base = shfl64(base, leader);
+        if (!active && !exhausted) {
+          uint64_t idx = base + (uint64_t)__popcll(need & lt_mask);
+          if (idx < M.n) {
+            start_packet<R, REC>(X, P, idx);
+            if (P.status != ST_ALIVE) finish<R, REC>(X, P); else active = true;
+          } else {
+            exhausted = true;
+          }
+        }
+      }
+      if (!__any(active)) break;
+      if (active) {
+        advance<R, REC>(X, P);
+        if (P.status != ST_ALIVE) {
+          finish<R, REC>(X, P);
+          active = false;
+        }
+      }
+    }
+    // flush block SED and statistics
+    __syncthreads();
+    for (int i = threadIdx.x; i < nsed; i += blockDim.x)
+      if (sed[i]) atomicAdd((unsigned long long *)&M.sed[i], (unsigned long long)sed[i]);
+    if (threadIdx.x < NSTAT && s_stat[threadIdx.x])
+      atomicAdd(&M.stats[threadIdx.x], s_stat[threadIdx.x]);
+    __syncthreads();
+  }
+}
+
+// Lane-side layout size of the LDS tables for a model.
+size_t transport_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64) {
+  TabOff o = tab_offsets(nl, ns, nsrc, nrows);
+  size_t rs = fp64 ? 8 : 4;
+  size_t b = (size_t)o.dtotal * 8 + (size_t)(o.r_total + (o.r_total & 1)) * rs +
+             (size_t)(nl + (nl & 1)) * 4 + (size_t)(ntheta > 0 ? ntheta : 1) * nl * 4;
+  return b;
+}
+
+hipError_t launch_transport(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int grid,
+                            int block, size_t lds, hipStream_t st) {
+  if (fp64) {
+    if (rec)
+      hipLaunchKernelGGL((k_transport<double, true>), dim3(grid), dim3(block), lds, st, d_models, nmodels);
+    else
+      hipLaunchKernelGGL((k_transport<double, false>), dim3(grid), dim3(block), lds, st, d_models, nmodels);
+  } else {
+    if (rec)
+      hipLaunchKernelGGL((k_transport<float, true>), dim3(grid), dim3(block), lds, st, d_models, nmodels);
+    else
+      hipLaunchKernelGGL((k_transport<float, false>), dim3(grid), dim3(block), lds, st, d_models, nmodels);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- per-cell kernels
+
+// Start of a B&W epoch: cells touched since the last snapshot get their
+// energy re-read and lose the cached epoch temperature.
+__global__ void k_epoch_snapshot(const ModelDev *__restrict__ md) {
+  const ModelDev &M = *md;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < M.ncell; i += stride) {
+    if (!M.dirty[i]) continue;
+    for (int s = 0; s < M.ns; ++s) {
+      int64_t q = (int64_t)s * M.ncell + i;
+      double e = energy_of(M, q);
+      if (e != M.esnap[q] || M.tt[q] >= 0.0) {
+        M.esnap[q] = e;
+        M.tt[q] = -1.0;
+      }
+    }
+    M.dirty[i] = 0;
+  }
+}
+
+// Eq. 4 for every cell and thermal species; optionally also writes E.
+template <typename R>
+__global__ void k_finalize_T(const ModelDev *__restrict__ md, double *T, double *E) {
+  const ModelDev &M = *md;
+  TabOff o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
+  const R *rho = (const R *)M.rho;
+  uint64_t n = M.ncell * (uint64_t)M.ns;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    int s = (int)(i / M.ncell);
+    uint64_t c = i - (uint64_t)s * M.ncell;
+    double r = (double)rho[c];
+    double e = energy_of(M, i);
+    double frac = M.tab[o.frac + s];
+    double t = 0.0;
+    if (s != M.pah && r > 0.0 && frac > 0.0) {
+      bool cl = false;
+      t = invert_T(M.tab, o, M.nl, s, e / (4.0 * PI_D * frac * r * M.V), &cl);
+      if (cl) atomicAdd(&M.stats[9], 1ull);
+    }
+    T[i] = t;
+    if (E) E[i] = e;
+  }
+}
+
+// Thin-limit equilibrium temperature at every cell centre (first guess
+// of the iterative scheme): Phi_s(T) = sum_j w_j kabs_s,j J_j with
+// J_j = sum_src L_nu,j / (16 pi^2 r^2).
+template <typename R>
+__global__ void k_init_T(const ModelDev *__restrict__ md, double *T) {
+  const ModelDev &M = *md;
+  TabOff o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
+  const R *rho = (const R *)M.rho;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const int nl = M.nl;
+  for (; i < M.ncell; i += stride) {
+    int cc[3] = {(int)(i % M.nx), (int)((i / M.nx) % M.ny), (int)(i / ((uint64_t)M.nx * M.ny))};
+    double x[3];
+    for (int k = 0; k < 3; ++k) x[k] = M.origin[k] + ((double)cc[k] + 0.5) * M.dcell;
+    double r2[MAX_SRC];
+    for (int s = 0; s < M.nsrc; ++s) {
+      const double *ps = M.tab + o.srcpos + 3 * s;
+      double dx = x[0] - ps[0], dy = x[1] - ps[1], dz = x[2] - ps[2];
+      r2[s] = dx * dx + dy * dy + dz * dz;
+    }
+    for (int s = 0; s < M.ns; ++s) {
+      double t = 0.0;
+      if (s != M.pah && (double)rho[i] > 0.0) {
+        double rhs = 0.0;
+        for (int j = nl - 1; j >= 0; --j) {
+          double J = 0.0;
+          for (int q = 0; q < M.nsrc; ++q)
+            J += M.tab[o.lnu + q * nl + j] / (16.0 * PI_D * PI_D * r2[q]);
+          rhs += M.tab[o.wk + s * nl + j] * J;
+        }
+        bool cl = false;
+        t = invert_T(M.tab, o, nl, s, rhs, &cl);
+      }
+      T[(uint64_t)s * M.ncell + i] = t;
+    }
+  }
+}
+
+hipError_t launch_epoch_snapshot(const ModelDev *d, hipStream_t st) {
+  hipLaunchKernelGGL(k_epoch_snapshot, dim3(2048), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+hipError_t launch_finalize_T(const ModelDev *d, bool fp64, double *T, double *E, hipStream_t st) {
+  if (fp64) hipLaunchKernelGGL(k_finalize_T<double>, dim3(4096), dim3(256), 0, st, d, T, E);
+  else hipLaunchKernelGGL(k_finalize_T<float>, dim3(4096), dim3(256), 0, st, d, T, E);
+  return hipGetLastError();
+}
+hipError_t launch_init_T(const ModelDev *d, bool fp64, double *T, hipStream_t st) {
+  if (fp64) hipLaunchKernelGGL(k_init_T<double>, dim3(4096), dim3(256), 0, st, d, T);
+  else hipLaunchKernelGGL(k_init_T<float>, dim3(4096), dim3(256), 0, st, d, T);
+  return hipGetLastError();
+}
+
+}  // namespace mcrt

@@ -1,0 +1,203 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle: packet transport.
+
+FP64 path: per-packet escape point, direction, wavelength and weight within
+1e-6 relative and identical event counts; per-cell counts exact; energies and
+temperatures within 1e-4 relative (observed ~1e-12)."""
+import numpy as np
+import pytest
+
+import mcrt_inputs as mi
+from tests.pairing import compare_records, gpu_context
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def run_pair(orc, m, n=None, first=0, precision="fp64", **kw):
+    n = m.n_packets if n is None else n
+    o = orc.Oracle(m)
+    okw = {k: v for k, v in kw.items() if k in ("mode", "n_iter", "epoch", "lucy_tau", "mrw_tau",
+                                                  "mrw_gamma", "max_int", "n_total")}
+    o.run(first=first, n=n, record=True, **okw)
+    g = gpu_context(m, precision)
+    modes = {orc.FROZEN: "frozen", orc.BW_EPOCH: "bw_epoch"}
+    gkw = dict(mode=modes[kw.get("mode", orc.BW_EPOCH)], n_iter=kw.get("n_iter", 3),
+               epoch_packets=kw.get("epoch", 4096), lucy_tau=kw.get("lucy_tau", 1e-2),
+               mrw_tau=kw.get("mrw_tau", 0.0), mrw_gamma=kw.get("mrw_gamma", 2.0),
+               max_interactions=kw.get("max_int", 10_000_000), n_total=kw.get("n_total", m.n_packets),
+               record=True)
+    st = g.run_packets(first=first, n=n, seed=m.seed, **gkw)
+    return o, g, st
+
+
+def check_cells(o, g, rtol=1e-4):
+    k, ep, kp = g.tallies()
+    assert np.array_equal(k, o.k), "absorption counts differ"
+    assert np.array_equal(kp, o.kpah), "PAH counts differ"
+    scale = max(np.abs(o.epath).max(), 1e-300)
+    np.testing.assert_allclose(ep, o.epath, rtol=rtol, atol=1e-12 * scale)
+    fl, cnt = g.sed()
+    assert np.array_equal(cnt, o.sed), "SED counts differ"
+
+
+@pytest.mark.parametrize("mode", ["bw_epoch", "frozen"])
+def test_cube_fp64_per_packet(orc, mode):
+    """32^3 cube, 5800 K star, tau_V = 1, albedo 0.5, g = 0.5, 1e5 packets."""
+    m = mi.cube(n=32, n_packets=100_000)
+    o = orc.Oracle(m)
+    g = gpu_context(m)
+    if mode == "frozen":
+        o.init_T()
+        g.init_temperatures()
+        o.run(record=True, mode=orc.FROZEN, n_iter=2)
+        st = g.run_packets(0, m.n_packets, m.seed, mode="frozen", n_iter=2, record=True,
+                           n_total=m.n_packets)
+    else:
+        o.run(record=True, mode=orc.BW_EPOCH, epoch=4096)
+        st = g.run_packets(0, m.n_packets, m.seed, mode="bw_epoch", epoch_packets=4096,
+                           record=True, n_total=m.n_packets)
+    info = compare_records(g.records(m.n_packets), o.records, tol=1e-6, scale=-m.origin[0])
+    print(mode, info, flush=True)
+    check_cells(o, g)
+    To = o.finalize() if mode == "bw_epoch" else o.T
+    np.testing.assert_allclose(g.temperatures(), To, rtol=1e-4, atol=0)
+    for key in ("escaped", "killed", "scatters", "absorptions", "crossings"):
+        assert st[key] == o.stats[key] or mode == "frozen", key
+
+
+def test_init_temperatures(orc):
+    """Thin-limit first guess of the iterative scheme, cell by cell."""
+    m = mi.shell(n=24, n_packets=10)
+    o = orc.Oracle(m)
+    o.init_T()
+    g = gpu_context(m)
+    g.init_temperatures()
+    np.testing.assert_allclose(g.current_temperatures(), o.T, rtol=1e-11, atol=0)
+
+
+def test_resume_and_determinism(orc):
+    m = mi.cube(n=16, n_packets=20000, tau_v=2.0)
+    a = gpu_context(m)
+    a.run_packets(0, 20000, 0, mode="bw_epoch", epoch_packets=1000, n_total=20000)
+    b = gpu_context(m)
+    b.run_packets(0, 12000, 0, mode="bw_epoch", epoch_packets=1000, n_total=20000)
+    b.run_packets(12000, 8000, 0, mode="bw_epoch", epoch_packets=1000, n_total=20000)
+    ka, ea, _ = a.tallies()
+    kb, eb, _ = b.tallies()
+    assert np.array_equal(ka, kb)
+    np.testing.assert_allclose(ea, eb, rtol=1e-12)
+    assert np.array_equal(a.sed()[1], b.sed()[1])
+    # launch shape does not change the result
+    c = gpu_context(m)
+    c.run_packets(0, 20000, 0, mode="bw_epoch", epoch_packets=1000, n_total=20000, block_size=64,
+                  blocks_per_cu=1)
+    assert np.array_equal(ka, c.tallies()[0])
+
+
+def test_lucy_thin_cube(orc):
+    m = mi.cube(n=16, n_packets=30000, tau_v=1e-3)
+    o, g, st = run_pair(orc, m, mode=orc.BW_EPOCH, epoch=8192)
+    assert o.stats["lucy_deposits"] > 0
+    compare_records(g.records(m.n_packets), o.records, scale=-m.origin[0])
+    check_cells(o, g)
+
+
+def test_mrw_thick_cube(orc):
+    m = mi.cube(n=8, n_packets=150, tau_v=1e5, nl=12)
+    o, g, st = run_pair(orc, m, mode=orc.BW_EPOCH, epoch=100, mrw_tau=8.0, mrw_gamma=2.0)
+    assert o.stats["mrw_steps"] > 0 and st["mrw_steps"] == o.stats["mrw_steps"]
+    compare_records(g.records(m.n_packets), o.records, scale=-m.origin[0], allow_frac=0.02)
+    k, ep, _ = g.tallies()
+    np.testing.assert_allclose(ep.sum(), o.epath.sum(), rtol=1e-6)
+
+
+def test_interaction_cap(orc):
+    m = mi.cube(n=8, n_packets=3000, tau_v=5.0)
+    o, g, st = run_pair(orc, m, mode=orc.BW_EPOCH, max_int=3)
+    assert st["killed"] == o.stats["killed"] > 0
+    compare_records(g.records(m.n_packets), o.records, scale=-m.origin[0])
+
+
+def test_pah_two_stage(orc):
+    n = 16
+    m = mi.torus(n=n, n_clumps=30, n_packets=20000, nl=40)
+    o = orc.Oracle(m)
+    o.run(mode=orc.BW_EPOCH, epoch=5000, record=True)
+    g = gpu_context(m)
+    g.run_packets(0, m.n_packets, m.seed, mode="bw_epoch", epoch_packets=5000, record=True,
+                  n_total=m.n_packets)
+    compare_records(g.records(m.n_packets), o.records, scale=-m.origin[0])
+    npah = int(o.kpah.sum())
+    assert npah > 0
+    o.pah_pass(mode=orc.BW_EPOCH, epoch=5000, record=True)
+    st = g.run_pah(m.seed, mode="bw_epoch", epoch_packets=5000, record=True)
+    assert st["packets"] == npah
+    compare_records(g.records(npah), o.records, scale=-m.origin[0])
+    check_cells(o, g)
+
+
+def test_voxelize_torus_and_shell_match(orc):
+    """Torus cells are decided by exact FP64 comparisons: bit-identical.
+    Shell cell averages agree to rounding."""
+    m = mi.torus(n=48, n_clumps=300, n_packets=10)
+    g = gpu_context(m)
+    ref = orc.voxelize_torus(m.nx, m.ny, m.nz, m.origin, m.dcell, m.geometry)
+    assert np.array_equal(g.density(), ref.ravel())
+    g32 = gpu_context(m, "fp32")
+    assert np.array_equal(g32.density(), ref.ravel().astype(np.float32))
+    s = mi.shell(n=24, n_packets=10)
+    gs = gpu_context(s)
+    refs = orc.voxelize_shell(s.nx, s.ny, s.nz, s.origin, s.dcell, s.geometry)
+    np.testing.assert_allclose(gs.density(), refs.ravel(), rtol=1e-12, atol=0)
+
+
+def test_fp32_first_flight_and_aggregates(orc):
+    """FP32 walk: the first emission draws give the same direction and
+    wavelength; aggregates agree with the FP64 oracle within MC noise."""
+    m = mi.cube(n=32, n_packets=200_000, tau_v=1.0)
+    o = orc.Oracle(m)
+    o.run(mode=orc.BW_EPOCH, epoch=4096, record=True)
+    g = gpu_context(m, "fp32")
+    g.run_packets(0, m.n_packets, m.seed, mode="bw_epoch", epoch_packets=4096, record=True,
+                  n_total=m.n_packets)
+    rg = g.records(m.n_packets)
+    # packets with no interaction keep their emission direction
+    free = (o.records["n_scat"] + o.records["n_abs"] == 0) & (rg["n_scat"] + rg["n_abs"] == 0)
+    assert free.mean() > 0.2
+    np.testing.assert_allclose(rg["dir"][free], o.records["dir"][free], atol=2e-6)
+    assert np.mean(rg["j"][free] == o.records["j"][free]) > 0.9999
+    # SED per theta bin and wavelength: chi^2 of two independent-noise counts
+    so, sg = o.sed.astype(float), g.sed()[1].astype(float)
+    ok = (so + sg) > 50
+    chi = np.sum((so[ok] - sg[ok]) ** 2 / (so[ok] + sg[ok])) / ok.sum()
+    assert chi < 1.5
+    T = g.temperatures()[0]
+    To = o.finalize()[0]
+    k = o.k[0]
+    sel = k > 200
+    rel = np.abs(T[sel] / To[sel] - 1)
+    assert np.median(rel) < 0.01
+
+
+def test_ticket_mode_statistics(orc):
+    """Immediate B&W (GPU order) against the oracle's serial B&W."""
+    m = mi.cube(n=16, n_packets=100_000, tau_v=3.0)
+    o = orc.Oracle(m).run(mode=orc.BW_EPOCH, epoch=1)
+    g = gpu_context(m)
+    g.run_packets(0, m.n_packets, m.seed, mode="bw_ticket", n_total=m.n_packets)
+    To = o.finalize()[0]
+    T = g.temperatures()[0]
+    k = o.k[0]
+    sel = k > 300
+    assert sel.sum() > 50
+    z = (T[sel] / To[sel] - 1) / (np.sqrt(2.0 / k[sel]) / 5.5)
+    assert np.mean(np.abs(z) < 4) > 0.97
+    so, sg = o.sed.astype(float), g.sed()[1].astype(float)
+    ok = (so + sg) > 50
+    assert np.sum((so[ok] - sg[ok]) ** 2 / (so[ok] + sg[ok])) / ok.sum() < 1.5
