@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--npix", type=int, default=512)
     ap.add_argument("--cpu-sample", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one elementwise copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the method is not sharded here); use --gpus 1",
@@ -64,6 +66,14 @@ def main():
     import paper_1203_2941_amd as mc
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)  # reads and writes calib_copy_mib MiB each
+        torch.cuda.synchronize()
+        del a, b
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + written")
     N = args.packets
     m = mi.torus(n=args.grid, n_packets=N)
     views, idx = mi.image_views(n_views=8, n_img=16, nl=m.nl)

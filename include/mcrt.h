@@ -207,7 +207,9 @@ mcrt_status mcrt_raytrace_adjoint(mcrt_ctx *ctx, int npx, int npy, const void *r
  * with grid, dust and sources set) run packets 0..n_packets[m]-1 with
  * seeds[m] in one persistent launch captured in a HIP graph; blocks pick
  * models with work left and refill their lanes from per-model counters.
- * Modes FROZEN (n_iter = 1) and BW_TICKET. Tallies are reset first and
+ * Each model draws the same Philox streams as its own mcrt_run_packets with
+ * the same seed (seeds distinguish the models), so FROZEN batches reproduce
+ * per-model runs exactly. Modes FROZEN (n_iter = 1) and BW_TICKET. Tallies are reset first and
  * temperatures finalised (Eq. 4, FP64) inside the same graph. stats
  * (nullable) [n_models]. */
 mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models, const uint64_t *n_packets,

@@ -100,6 +100,16 @@ def lib():
     """The loaded libmcrt.so with argument types declared (raises if missing)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime with the same soname as the system
+        # one. Loading torch first makes libmcrt bind to that already-loaded
+        # runtime, so device pointers and streams from torch and the library's
+        # kernels share one runtime in the process.
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -c 'import __graft_entry__ as g; g.build()'`")

@@ -1,0 +1,74 @@
+"""Launch-shape autotuner for the persistent transport kernel.
+
+The queue depth of the persistent kernel is the number of lanes in flight,
+block_size x blocks_per_cu x CUs. The tuner times a packet subsample of the
+caller's models (one batched launch per candidate shape, same seeds) and
+keeps the shape with the highest packet rate. Results are cached per model
+signature in a JSON file.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+from typing import Dict, List, Sequence, Tuple
+
+from .context import Context, run_batch
+
+CANDIDATES: List[Tuple[int, int]] = [(64, 8), (128, 4), (128, 8), (256, 2), (256, 4), (256, 8)]
+CACHE = os.environ.get("MCRT_TUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "mcrt_autotune.json"))
+
+
+def signature(contexts: Sequence[Context], mode: str) -> str:
+    parts = [mode, str(len(contexts))]
+    for c in contexts:
+        parts.append(f"{c.nx}x{c.ny}x{c.nz}:{c.nl}:{c.ns}:{int(c.fp64)}")
+    return hashlib.sha1("|".join(parts).encode()).hexdigest()[:16]
+
+
+def _load() -> Dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: Dict) -> None:
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        with open(CACHE, "w") as f:
+            json.dump(d, f, indent=1)
+    except OSError:
+        pass
+
+
+def tune(contexts: Sequence[Context], n_packets: Sequence[int], seeds: Sequence[int],
+         sample_frac: float = 0.05, min_packets: int = 20000, candidates=None,
+         use_cache: bool = True, **opts) -> Dict:
+    """Best (block_size, blocks_per_cu) for a batch; returns a dict with the
+    choice and the measured rates of every candidate."""
+    mode = opts.get("mode", "bw_ticket")
+    key = signature(contexts, str(mode))
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        return cache[key]
+    cand = candidates or CANDIDATES
+    sub = [max(min_packets, int(n * sample_frac)) for n in n_packets]
+    rates = {}
+    for bs, bpc in cand:
+        t0 = time.perf_counter()
+        st = run_batch(contexts, sub, seeds, block_size=bs, blocks_per_cu=bpc, **opts)
+        dt = time.perf_counter() - t0
+        ms = st[0]["kernel_ms"] if st else dt * 1e3
+        rates[f"{bs}x{bpc}"] = sum(sub) / (ms / 1e3)
+    best = max(rates, key=rates.get)
+    bs, bpc = (int(x) for x in best.split("x"))
+    res = {"block_size": bs, "blocks_per_cu": bpc, "packets_per_s": rates[best], "rates": rates,
+           "sample_packets": int(sum(sub))}
+    if use_cache:
+        cache[key] = res
+        _store(cache)
+    return res

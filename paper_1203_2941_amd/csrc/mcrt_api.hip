@@ -94,6 +94,7 @@ struct mcrt_ctx {
   ModelDev h_model;
   double xi = 0.0;
   uint64_t n_total = 0;
+  double ssca_unit = 1.0;  // erg/s/sr per stored unit of the scattering sums
   // ray-tracer
   void *d_S = nullptr;
   size_t S_cap = 0;
@@ -106,6 +107,7 @@ struct mcrt_ctx {
   void *h_stage = nullptr;
   hipEvent_t ev_stage = nullptr, ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evf0 = nullptr, evf1 = nullptr, eva0 = nullptr, eva1 = nullptr;
+  hipStream_t cap_stream = nullptr;  // graph capture (the caller's stream may be the legacy one)
   bool have_f = false, have_a = false;
   double t_transport = 0.0;
   size_t sed_tmp_cap = 0;
@@ -193,6 +195,7 @@ extern "C" mcrt_status mcrt_create(mcrt_ctx **out, int device, int precision) {
       hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->evf0) != hipSuccess ||
       hipEventCreate(&ctx->evf1) != hipSuccess || hipEventCreate(&ctx->eva0) != hipSuccess ||
       hipEventCreate(&ctx->eva1) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void **)&ctx->d_counter, sizeof(uint64_t)) != hipSuccess ||
       hipMalloc((void **)&ctx->d_stats, sizeof(unsigned long long) * NSTAT) != hipSuccess ||
       hipMalloc((void **)&ctx->d_model, sizeof(ModelDev)) != hipSuccess ||
@@ -220,6 +223,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   hipEvent_t evs[] = {ctx->evf0, ctx->evf1, ctx->eva0, ctx->eva1};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
@@ -735,6 +739,7 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.mrw_tau = o ? o->mrw_tau : 0.0;
   M.mrw_gamma = o ? o->mrw_gamma : 2.0;
   M.kext_max = ctx->kext_max;
+  M.ssca_unit = ctx->ssca_unit;
   M.max_int = o ? o->max_interactions : 0;
   M.ncell = ctx->ncell;
   M.rho = ctx->d_rho;
@@ -815,6 +820,28 @@ static mcrt_status read_stats(mcrt_ctx *ctx, mcrt_run_stats *stats, hipStream_t 
   return MCRT_OK;
 }
 
+template <typename T>
+__global__ void k_scale(T *p, double f, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = (T)((double)p[i] * f);
+}
+
+// Scattering sums are stored in units of the packet energy of the run that
+// accumulates them; a change of unit rescales what is already stored.
+static mcrt_status set_ssca_unit(mcrt_ctx *ctx, double unit, hipStream_t st) {
+  if (!(unit > 0.0) || unit == ctx->ssca_unit) return MCRT_OK;
+  uint64_t m = (uint64_t)ctx->nview * ctx->nimg * ctx->ncell;
+  if (ctx->d_ssca && m) {
+    double f = ctx->ssca_unit / unit;
+    if (ctx->fp64) hipLaunchKernelGGL(k_scale<double>, dim3(4096), dim3(256), 0, st, (double *)ctx->d_ssca, f, m);
+    else hipLaunchKernelGGL(k_scale<float>, dim3(4096), dim3(256), 0, st, (float *)ctx->d_ssca, f, m);
+    HIPCHK(hipGetLastError());
+  }
+  ctx->ssca_unit = unit;
+  return MCRT_OK;
+}
+
 static mcrt_status prepare_run(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n, hipStream_t st) {
   mcrt_status s = ready(ctx);
   if (s) return s;
@@ -835,6 +862,8 @@ static mcrt_status prepare_run(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n
   if (nt == 0) return fail(ctx, MCRT_EINVAL, "n_total is 0");
   ctx->n_total = nt;
   ctx->xi = ctx->ltot / (double)nt;
+  s = set_ssca_unit(ctx, ctx->xi, st);
+  if (s) return s;
   HIPCHK(fill<unsigned long long>(ctx->d_stats, 0ull, NSTAT, st));
   return MCRT_OK;
 }
@@ -1069,18 +1098,29 @@ extern "C" mcrt_status mcrt_set_scattering(mcrt_ctx *ctx, const double *ssca, in
   if (s) return s;
   uint64_t m = (uint64_t)ctx->nview * ctx->nimg * ctx->ncell;
   if (m == 0) return MCRT_OK;
-  if (ctx->fp64) {
-    HIPCHK(hipMemcpyAsync(ctx->d_ssca, ssca, m * 8, mem == MCRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-  } else {
-    double *tmp = nullptr;
-    HIPCHK(hipMalloc((void **)&tmp, m * 8));
-    HIPCHK(hipMemcpyAsync(tmp, ssca, m * 8, mem == MCRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_d2f, dim3(4096), dim3(256), 0, st, tmp, (float *)ctx->d_ssca, m);
-    HIPCHK(hipGetLastError());
+  std::vector<double> h(m);
+  if (mem == MCRT_DEVICE) {
+    HIPCHK(hipMemcpyAsync(h.data(), ssca, m * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    (void)hipFree(tmp);
+  } else {
+    memcpy(h.data(), ssca, m * 8);
   }
-  if (mem != MCRT_DEVICE) HIPCHK(hipStreamSynchronize(st));
+  double mx = 0.0;
+  for (uint64_t i = 0; i < m; ++i) {
+    if (!finite_nonneg(h[i])) return fail(ctx, MCRT_EINVAL, "scattering sums must be finite and >= 0");
+    if (h[i] > mx) mx = h[i];
+  }
+  // store in units that keep the largest value near 2^20
+  double unit = mx > 0.0 ? mx / 1048576.0 : 1.0;
+  if (ctx->fp64) {
+    for (auto &v : h) v /= unit;
+    HIPCHK(hipMemcpy(ctx->d_ssca, h.data(), m * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(m);
+    for (uint64_t i = 0; i < m; ++i) f[i] = (float)(h[i] / unit);
+    HIPCHK(hipMemcpy(ctx->d_ssca, f.data(), m * 4, hipMemcpyHostToDevice));
+  }
+  ctx->ssca_unit = unit;
   ctx->S_ok = false;
   return MCRT_OK;
 }
@@ -1170,10 +1210,15 @@ extern "C" mcrt_status mcrt_scattering(mcrt_ctx *ctx, double *ssca_out, int mem,
   hipStream_t st = (hipStream_t)stream;
   uint64_t m = (uint64_t)ctx->nview * ctx->nimg * ctx->ncell;
   if (m == 0 || !ssca_out) return MCRT_OK;
-  if (ctx->fp64) return to_caller(ctx, ssca_out, ctx->d_ssca, m * 8, mem, st);
   double *tmp = nullptr;
   HIPCHK(hipMalloc((void **)&tmp, m * 8));
-  hipLaunchKernelGGL(k_f2d, dim3(4096), dim3(256), 0, st, (const float *)ctx->d_ssca, tmp, m);
+  if (ctx->fp64) {
+    HIPCHK(hipMemcpyAsync(tmp, ctx->d_ssca, m * 8, hipMemcpyDeviceToDevice, st));
+  } else {
+    hipLaunchKernelGGL(k_f2d, dim3(4096), dim3(256), 0, st, (const float *)ctx->d_ssca, tmp, m);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_scale<double>, dim3(4096), dim3(256), 0, st, tmp, ctx->ssca_unit, m);
   HIPCHK(hipGetLastError());
   s = to_caller(ctx, ssca_out, tmp, m * 8, mem, st);
   HIPCHK(hipStreamSynchronize(st));
@@ -1378,13 +1423,14 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
       return fail(ctx, MCRT_EINVAL, "model %d: same device and precision required", m);
     s = prepare_run(c, opts, n_packets[m], st);
     if (s) return fail(ctx, s, "model %d: %s", m, c->err.c_str());
-    fill_model(c, hm[m], opts, m);
+    fill_model(c, hm[m], opts, 0);  // same streams as the model's own run_packets
     hm[m].seed = seeds[m];
     hm[m].first = 0;
     hm[m].n = n_packets[m];
     size_t b = transport_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->fp64);
     if (b > lds) lds = b;
   }
+  if (lds > ctx->lds_max) return fail(ctx, MCRT_EINVAL, "batch tables need %zu bytes of LDS (limit %zu)", lds, ctx->lds_max);
   if (n_models > ctx->batch_cap) {
     HIPCHK(dev_alloc((void **)&ctx->d_batch, sizeof(ModelDev) * n_models));
     ctx->batch_cap = n_models;
@@ -1393,21 +1439,23 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   HIPCHK(stage_copy(ctx, ctx->d_batch, hm.data(), sizeof(ModelDev) * n_models, st));
   int grid, block;
   launch_shape(ctx, opts, grid, block);
-  // one graph: reset tallies and counters, the persistent transport, Eq. 4
+  // one graph: reset tallies and counters, the persistent transport, Eq. 4.
+  // Captured on the library's own stream, launched on the caller's.
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  hipStream_t cs_ = ctx->cap_stream;
+  HIPCHK(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
   mcrt_status cs = MCRT_OK;
   for (int m = 0; m < n_models && cs == MCRT_OK; ++m) {
     mcrt_ctx *c = models[m];
-    cs = zero_tallies(c, st);
-    if (cs == MCRT_OK && fill<uint64_t>(c->d_counter, 0ull, 1, st) != hipSuccess) cs = MCRT_EDEVICE;
+    cs = zero_tallies(c, cs_);
+    if (cs == MCRT_OK && fill<uint64_t>(c->d_counter, 0ull, 1, cs_) != hipSuccess) cs = MCRT_EDEVICE;
   }
   hipError_t le = hipSuccess;
-  if (cs == MCRT_OK) le = launch_transport(ctx->d_batch, n_models, ctx->fp64, false, grid, block, lds, st);
+  if (cs == MCRT_OK) le = launch_transport(ctx->d_batch, n_models, ctx->fp64, false, grid, block, lds, cs_);
   for (int m = 0; m < n_models && cs == MCRT_OK && le == hipSuccess; ++m)
-    le = launch_finalize_T(ctx->d_batch + m, ctx->fp64, models[m]->d_T, nullptr, st);
-  hipError_t ce = hipStreamEndCapture(st, &graph);
+    le = launch_finalize_T(ctx->d_batch + m, ctx->fp64, models[m]->d_T, nullptr, cs_);
+  hipError_t ce = hipStreamEndCapture(cs_, &graph);
   if (cs != MCRT_OK || le != hipSuccess || ce != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     return fail(ctx, MCRT_EDEVICE, "graph capture failed: %s",

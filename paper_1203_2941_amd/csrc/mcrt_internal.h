@@ -77,6 +77,7 @@ struct ModelDev {
   int32_t mode, record, pass, iter;
   double origin[3];
   double dcell, V, xi, lucy_tau, mrw_tau, mrw_gamma, kext_max;
+  double ssca_unit;           // scattering sums are stored in these units (erg/s/sr)
   uint64_t max_int, first, n, id_base, rec_first, seed, ncell;
   const void *rho;            // [cells] context precision
   const double *tab;          // packed double table
@@ -145,7 +146,9 @@ __device__ __forceinline__ uint32_t rng_u32(Rng &r) {
   return x;
 }
 
-// ((x >> 8) + 1/2) 2^-24: exact in both precisions, strictly inside (0, 1).
+// ((x >> 8) + 1/2) 2^-24, strictly inside (0, 1). It has 25 significant bits:
+// exact in FP64; rounded to nearest in FP32 (draws that set directions or
+// pick source wavelengths are taken in FP64 in both precisions).
 template <typename R> __device__ __forceinline__ R rng_u(Rng &r) {
   return ((R)(rng_u32(r) >> 8) + (R)0.5) * (R)(1.0 / 16777216.0);
 }

@@ -133,7 +133,8 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, int v, R *S) {
     double val = em / ke;
     double r = (double)rho[c];
     if (ss && r > 0.0)
-      val += (double)ss[((uint64_t)v * nq + q) * M.ncell + c] / (M.V * M.tab[o.w + j] * r * ke);
+      val += (double)ss[((uint64_t)v * nq + q) * M.ncell + c] * M.ssca_unit /
+             (M.V * M.tab[o.w + j] * r * ke);
     S[((uint64_t)v * M.ncell + c) * nq + q] = (R)val;
   }
 }

@@ -37,17 +37,31 @@ struct Ctx {
   const R *rho;
   int64_t nc;
   unsigned long long *st;  // LDS block counters [NSTAT]
+  R rho_thin;              // FP32 walk: lucy_tau / (max kext dcell), 0 when Lucy is off
 };
 
 __device__ __forceinline__ void stat_add(unsigned long long *st, int i, unsigned long long v) {
   atomicAdd(&st[i], v);
 }
 
+// Distance along d from p0 to the exit plane of cell c on axis k. The FP64
+// walk divides (the same rounding as a plain evaluation); the FP32 walk
+// multiplies by a per-flight reciprocal.
 template <typename R>
 __device__ __forceinline__ R plane_t(const ModelDev &M, R p0, R d, int c, int k) {
   if (d > (R)0) return ((R)M.origin[k] + (R)(c + 1) * (R)M.dcell - p0) / d;
   if (d < (R)0) return ((R)M.origin[k] + (R)c * (R)M.dcell - p0) / d;
   return m_inf<R>();
+}
+template <typename R>
+__device__ __forceinline__ R plane_r(const ModelDev &M, R p0, R d, R inv, int c, int k) {
+  if constexpr (sizeof(R) == 8) {
+    return plane_t<R>(M, p0, d, c, k);
+  } else {
+    if (d > (R)0) return ((R)M.origin[k] + (R)(c + 1) * (R)M.dcell - p0) * inv;
+    if (d < (R)0) return ((R)M.origin[k] + (R)c * (R)M.dcell - p0) * inv;
+    return m_inf<R>();
+  }
 }
 
 template <typename R>
@@ -62,15 +76,16 @@ __device__ __forceinline__ void start_cell(const ModelDev &M, const R p[3], cons
   }
 }
 
+// Isotropic direction, evaluated in FP64 in both precisions (sqrt(1 - mu^2)
+// cancels near the poles in FP32) and rounded to the walk type.
 template <typename R>
-__device__ __forceinline__ void iso_dir(R uphi, R umu, R d[3]) {
-  R phi = (R)2 * (R)PI_D * uphi;
-  R mu = (R)1 - (R)2 * umu;
-  R t = (R)1 - mu * mu;
-  R s = m_sqrt(t > (R)0 ? t : (R)0);
-  d[0] = s * m_cos(phi);
-  d[1] = s * m_sin(phi);
-  d[2] = mu;
+__device__ __forceinline__ void iso_dir(double uphi, double umu, R d[3]) {
+  double phi = 2.0 * PI_D * uphi;
+  double mu = 1.0 - 2.0 * umu;
+  double s = sqrt(fmax(0.0, 1.0 - mu * mu));
+  d[0] = (R)(s * cos(phi));
+  d[1] = (R)(s * sin(phi));
+  d[2] = (R)mu;
 }
 
 template <typename R>
@@ -137,11 +152,16 @@ __device__ __forceinline__ int pick_desc_fn(int n, R u, double &mm, F f) {
   return 0;
 }
 
+// Lucy's thin-cell test rho max(kext) dcell < lucy_tau; the FP32 walk
+// compares rho with the equivalent density threshold.
 template <typename R>
 __device__ __forceinline__ bool is_thin(const Ctx<R> &X, R rho) {
   const ModelDev &M = *X.M;
-  return M.lucy_tau > 0.0 && rho > (R)0 &&
-         rho * (R)M.kext_max * (R)M.dcell < (R)M.lucy_tau;
+  if constexpr (sizeof(R) == 8) {
+    return M.lucy_tau > 0.0 && rho > (R)0 && rho * (R)M.kext_max * (R)M.dcell < (R)M.lucy_tau;
+  } else {
+    return rho > (R)0 && rho < X.rho_thin;
+  }
 }
 
 __device__ __forceinline__ double energy_of(const ModelDev &M, int64_t q) {
@@ -198,9 +218,10 @@ __device__ bool fly(Ctx<R> &X, Pkt<R> &P, R tau_star) {
   const R p0x = P.p[0], p0y = P.p[1], p0z = P.p[2];
   const R dx = P.d[0], dy = P.d[1], dz = P.d[2];
   int cx = P.c[0], cy = P.c[1], cz = P.c[2];
-  R tx = plane_t<R>(M, p0x, dx, cx, 0);
-  R ty = plane_t<R>(M, p0y, dy, cy, 1);
-  R tz = plane_t<R>(M, p0z, dz, cz, 2);
+  const R ix = (R)1 / dx, iy = (R)1 / dy, iz = (R)1 / dz;
+  R tx = plane_r<R>(M, p0x, dx, ix, cx, 0);
+  R ty = plane_r<R>(M, p0y, dy, iy, cy, 1);
+  R tz = plane_r<R>(M, p0z, dz, iz, cz, 2);
   const R kx = X.rt[X.o.r_kext + P.j];
   const int sx = dx > (R)0 ? 1 : -1, sy = dy > (R)0 ? 1 : -1, sz = dz > (R)0 ? 1 : -1;
   R t = (R)0, tau = (R)0;
@@ -237,17 +258,17 @@ __device__ bool fly(Ctx<R> &X, Pkt<R> &P, R tau_star) {
       cx += sx;
       if (cx < 0 || cx >= M.nx) break;
       c += sx;
-      tx = plane_t<R>(M, p0x, dx, cx, 0);
+      tx = plane_r<R>(M, p0x, dx, ix, cx, 0);
     } else if (a == 1) {
       cy += sy;
       if (cy < 0 || cy >= M.ny) break;
       c += (int64_t)sy * M.nx;
-      ty = plane_t<R>(M, p0y, dy, cy, 1);
+      ty = plane_r<R>(M, p0y, dy, iy, cy, 1);
     } else {
       cz += sz;
       if (cz < 0 || cz >= M.nz) break;
       c += (int64_t)sz * M.nx * M.ny;
-      tz = plane_t<R>(M, p0z, dz, cz, 2);
+      tz = plane_r<R>(M, p0z, dz, iz, cz, 2);
     }
   }
   P.p[0] = p0x + t * dx;
@@ -319,7 +340,7 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
   if (REC) upd_margin(P.mm, fabs(crit - M.mrw_gamma) / M.mrw_gamma);
   if (!(crit >= M.mrw_gamma)) return false;
   double ut = rng_u<double>(P.rng), ups = rng_u<double>(P.rng), ums = rng_u<double>(P.rng);
-  R ul = rng_u<R>(P.rng), uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+  double ul = rng_u<double>(P.rng), uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
   double y = mrw_solve(ut);
   double ell = -3.0 * rho * kr * Rs * Rs * log(y) / (PI_D * PI_D);
   double ds[3];
@@ -342,7 +363,7 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
     atomicAdd(&M.epath[(int64_t)s * X.nc + c], M.xi * rho * X.dt[X.o.frac + s] * kp * ell);
   }
   M.dirty[c] = 1;
-  P.j = pick_desc_fn<double, REC>(nl, (double)ul, P.mm, [&](int j) {
+  P.j = pick_desc_fn<double, REC>(nl, ul, P.mm, [&](int j) {
     double f = 0.0;
     for (int s = 0; s < M.ns; ++s) {
       if (s == M.pah) continue;
@@ -367,9 +388,9 @@ __device__ __forceinline__ int pah_row(const Ctx<R> &X, int64_t c) {
 }
 
 template <typename R, bool REC>
-__device__ __forceinline__ int pick_pah(const Ctx<R> &X, int row, R u, double &mm) {
+__device__ __forceinline__ int pick_pah(const Ctx<R> &X, int row, double u, double &mm) {
   const double *pw = X.dt + X.o.pahw + row * X.M->nl;
-  return pick_desc_fn<double, REC>(X.M->nl, (double)u, mm, [&](int j) { return pw[j]; });
+  return pick_desc_fn<double, REC>(X.M->nl, u, mm, [&](int j) { return pw[j]; });
 }
 
 // Re-emission wavelength of species s at temperature T: Eq. 5 (FROZEN) or
@@ -470,7 +491,7 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
     u3[0] = rng_u<R>(P.rng);
     u3[1] = rng_u<R>(P.rng);
     u3[2] = rng_u<R>(P.rng);
-    R ul = rng_u<R>(P.rng), uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+    double ul = rng_u<double>(P.rng), uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       P.c[k] = cc[k];
@@ -480,15 +501,15 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
     iso_dir<R>(uph, umu, P.d);
     return;
   }
-  R uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
-  R us = rng_u<R>(P.rng), ul = rng_u<R>(P.rng);
+  double uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
+  double us = rng_u<double>(P.rng), ul = rng_u<double>(P.rng);
   iso_dir<R>(uph, umu, P.d);
   int s = 0;
-  if (M.nsrc > 1) s = pick_asc<double, REC>(X.dt + X.o.lum, 1, M.nsrc, (double)us, P.mm);
+  if (M.nsrc > 1) s = pick_asc<double, REC>(X.dt + X.o.lum, 1, M.nsrc, us, P.mm);
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.p[k] = (R)X.dt[X.o.srcpos + 3 * s + k];
   const double *sf = X.dt + X.o.srcf + s * nl;
-  P.j = pick_desc_fn<double, REC>(nl, (double)ul, P.mm, [&](int j) { return sf[j]; });
+  P.j = pick_desc_fn<double, REC>(nl, ul, P.mm, [&](int j) { return sf[j]; });
   start_cell<R>(M, P.p, P.d, P.c);
   if (P.c[0] < 0 || P.c[0] >= M.nx || P.c[1] < 0 || P.c[1] >= M.ny || P.c[2] < 0 ||
       P.c[2] >= M.nz)
@@ -526,7 +547,8 @@ __device__ void advance(Ctx<R> &X, Pkt<R> &P) {
     if (q >= 0) {
       for (int v = 0; v < M.nview; ++v) {
         R cb = P.d[0] * (R)M.kv[v][0] + P.d[1] * (R)M.kv[v][1] + P.d[2] * (R)M.kv[v][2];
-        R add = (R)M.xi * hg_phase<R>(g, cb);
+        // sums kept in units of ssca_unit (the packet energy): erg/s sums overflow FP32
+        R add = (R)(M.xi / M.ssca_unit) * hg_phase<R>(g, cb);
         atomicAdd((R *)M.ssca + ((int64_t)v * M.nimg + q) * X.nc + c, add);
       }
     }
@@ -543,7 +565,7 @@ __device__ void advance(Ctx<R> &X, Pkt<R> &P) {
         P.status = ST_PAH_STOP;
         return;
       }
-      R ul = rng_u<R>(P.rng), uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+      double ul = rng_u<double>(P.rng), uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
       P.j = pick_pah<R, REC>(X, pah_row(X, c), ul, P.mm);
       iso_dir<R>(uph, umu, P.d);
     } else {
@@ -564,7 +586,8 @@ __device__ void advance(Ctx<R> &X, Pkt<R> &P) {
         T = mode_T(X, s, c, (double)rho);
       }
       M.dirty[c] = 1;
-      R ul = rng_u<R>(P.rng), uph = rng_u<R>(P.rng), umu = rng_u<R>(P.rng);
+      R ul = rng_u<R>(P.rng);
+      double uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
       P.j = pick_thermal<R, REC>(X, s, T, ul, P.mm);
       iso_dir<R>(uph, umu, P.d);
     }
@@ -608,6 +631,7 @@ __global__ void __launch_bounds__(256) k_transport(const ModelDev *__restrict__ 
     X.o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
     X.nc = (int64_t)M.ncell;
     X.rho = (const R *)M.rho;
+    X.rho_thin = (M.lucy_tau > 0.0) ? (R)(M.lucy_tau / (M.kext_max * M.dcell)) : (R)0;
     double *dt = (double *)lds_raw;
     R *rt = (R *)(dt + X.o.dtotal);
     int *im = (int *)(rt + X.o.r_total + (X.o.r_total & 1));

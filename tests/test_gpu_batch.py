@@ -1,0 +1,78 @@
+"""Batched persistent launch (one HIP graph over many uneven models)
+against per-model launches, and the launch-shape autotuner."""
+import numpy as np
+import pytest
+
+import mcrt_inputs as mi
+from tests.pairing import gpu_context
+
+pytestmark = pytest.mark.gpu
+
+
+def models():
+    specs = [dict(n=24, n_clumps=60, nl=40), dict(n=32, n_clumps=200, nl=64),
+             dict(n=16, n_clumps=20, nl=100)]
+    return [mi.torus(n_packets=20000 + 5000 * i, seed=i, geo_seed=100 + i, **s)
+            for i, s in enumerate(specs)]
+
+
+def test_batch_equals_individual_runs():
+    """FROZEN single pass with the thin-limit temperatures: integer tallies
+    are order independent, so the batched graph must reproduce every
+    model's per-model launch exactly; repeated graph launches with eager
+    work in between give the same result each time."""
+    import paper_1203_2941_amd as mc
+    ms = models()
+    ref = []
+    for i, m in enumerate(ms):
+        g = gpu_context(m)
+        g.init_temperatures()
+        g.run_packets(0, m.n_packets, m.seed, mode="frozen", n_iter=1, n_total=m.n_packets)
+        ref.append((g.tallies(), g.sed()[1], g.temperatures()))
+    ctxs = [gpu_context(m) for m in ms]
+    for c in ctxs:
+        c.init_temperatures()
+    for rep in range(3):
+        # the frozen pass overwrites T with its Eq. 4 result: restore the guess
+        for c in ctxs:
+            c.init_temperatures()
+        st = mc.run_batch(ctxs, [m.n_packets for m in ms], [m.seed for m in ms],
+                          mode="frozen", n_iter=1)
+        for i, (c, m) in enumerate(zip(ctxs, ms)):
+            (k, ep, kp), sed, T = ref[i]
+            k2, ep2, kp2 = c.tallies()
+            assert np.array_equal(k, k2), (rep, i)
+            assert np.array_equal(kp, kp2), (rep, i)
+            np.testing.assert_allclose(ep2, ep, rtol=1e-10, atol=0)
+            assert np.array_equal(c.sed()[1], sed)
+            assert st[i]["packets"] == m.n_packets
+            # Eq. 4 runs inside the graph: same temperatures as the eager path
+            np.testing.assert_allclose(c.current_temperatures(), T, rtol=1e-12, atol=0)
+        # eager work between graph launches
+        gpu_context(ms[0]).run_packets(0, 1000, 7, mode="bw_ticket", n_total=1000)
+
+
+def test_batch_ticket_conserves_packets():
+    import paper_1203_2941_amd as mc
+    ms = models()
+    ctxs = [gpu_context(m, "fp32") for m in ms]
+    st = mc.run_batch(ctxs, [m.n_packets for m in ms], [m.seed for m in ms], mode="bw_ticket",
+                      mrw_tau=50.0)
+    for s, m, c in zip(st, ms, ctxs):
+        assert s["escaped"] + s["killed"] + s["pah_stopped"] == m.n_packets
+        assert int(c.sed()[1].sum()) == s["escaped"]
+        T = c.current_temperatures()
+        assert np.all(np.isfinite(T)) and T.max() > 0
+
+
+def test_autotuner_picks_a_candidate(tmp_path, monkeypatch):
+    from paper_1203_2941_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    ms = models()
+    ctxs = [gpu_context(m, "fp32") for m in ms]
+    res = autotune.tune(ctxs, [m.n_packets for m in ms], [m.seed for m in ms],
+                        candidates=[(128, 4), (256, 4)], mode="bw_ticket")
+    assert (res["block_size"], res["blocks_per_cu"]) in [(128, 4), (256, 4)]
+    assert res["packets_per_s"] > 0
+    again = autotune.tune(ctxs, [m.n_packets for m in ms], [m.seed for m in ms], mode="bw_ticket")
+    assert again == res  # served from the cache

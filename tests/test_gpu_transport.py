@@ -109,12 +109,29 @@ def test_lucy_thin_cube(orc):
 
 
 def test_mrw_thick_cube(orc):
+    """Modified random walk in a very thick cube. A walk step moves the
+    packet by the distance to the nearest face, p -> p + R(p) d_s, whose
+    Jacobian I + d_s n^T makes long chains amplify last-bit differences of
+    exp/log between the two codes (measured: identical to 1e-9 relative up
+    to ~2000 events, then ~20x per 1000 events). Per-packet parity is
+    therefore checked on chains cut at 1500 interactions, with one epoch so
+    packets do not couple through energy snapshots; the full run is
+    compared statistically."""
     m = mi.cube(n=8, n_packets=150, tau_v=1e5, nl=12)
-    o, g, st = run_pair(orc, m, mode=orc.BW_EPOCH, epoch=100, mrw_tau=8.0, mrw_gamma=2.0)
-    assert o.stats["mrw_steps"] > 0 and st["mrw_steps"] == o.stats["mrw_steps"]
-    compare_records(g.records(m.n_packets), o.records, scale=-m.origin[0], allow_frac=0.02)
-    k, ep, _ = g.tallies()
-    np.testing.assert_allclose(ep.sum(), o.epath.sum(), rtol=1e-6)
+    o, g, st = run_pair(orc, m, mode=orc.BW_EPOCH, epoch=10**9, mrw_tau=8.0, mrw_gamma=2.0,
+                        max_int=1500)
+    assert o.stats["mrw_steps"] > 1000 and st["mrw_steps"] == o.stats["mrw_steps"]
+    compare_records(g.records(m.n_packets), o.records, scale=-m.origin[0])
+    check_cells(o, g, rtol=1e-9)
+    # full chains: same physics within Monte Carlo noise
+    o2 = orc.Oracle(m).run(mode=orc.BW_EPOCH, epoch=100, mrw_tau=8.0, mrw_gamma=2.0)
+    g2 = gpu_context(m)
+    s2 = g2.run_packets(0, m.n_packets, m.seed, mode="bw_epoch", epoch_packets=100, mrw_tau=8.0,
+                        mrw_gamma=2.0, n_total=m.n_packets)
+    assert s2["escaped"] == m.n_packets
+    assert s2["mrw_steps"] == pytest.approx(o2.stats["mrw_steps"], rel=0.15)
+    k2, ep2, _ = g2.tallies()
+    assert ep2.sum() == pytest.approx(o2.epath.sum(), rel=0.15)
 
 
 def test_interaction_cap(orc):
@@ -187,14 +204,14 @@ def test_fp32_first_flight_and_aggregates(orc):
 
 def test_ticket_mode_statistics(orc):
     """Immediate B&W (GPU order) against the oracle's serial B&W."""
-    m = mi.cube(n=16, n_packets=100_000, tau_v=3.0)
+    m = mi.cube(n=8, n_packets=100_000, tau_v=3.0)
     o = orc.Oracle(m).run(mode=orc.BW_EPOCH, epoch=1)
     g = gpu_context(m)
     g.run_packets(0, m.n_packets, m.seed, mode="bw_ticket", n_total=m.n_packets)
     To = o.finalize()[0]
     T = g.temperatures()[0]
     k = o.k[0]
-    sel = k > 300
+    sel = k > 100
     assert sel.sum() > 50
     z = (T[sel] / To[sel] - 1) / (np.sqrt(2.0 / k[sel]) / 5.5)
     assert np.mean(np.abs(z) < 4) > 0.97

@@ -33,8 +33,10 @@ def test_u24_open_interval_and_exact(orc):
     for x in [0, 255, 256, 2**32 - 1, 2**31, 12345678]:
         u = orc.u24(x)
         assert 0.0 < u < 1.0
-        assert np.float32(u) == u  # exactly representable in FP32 too
-        assert u == ((x >> 8) + 0.5) / 2**24
+        assert u == ((x >> 8) + 0.5) / 2**24  # exact in FP64 (25 significant bits)
+    # 25 bits do not fit FP32: the walk in FP32 draws these uniforms in FP64
+    u = orc.u24(2**32 - 1)
+    assert float(np.float32(u)) != u and float(np.float32(orc.u24(2**16))) == orc.u24(2**16)
     assert orc.u24(0) == 0.5 / 2**24
     assert orc.u24(2**32 - 1) == 1.0 - 0.5 / 2**24
 
