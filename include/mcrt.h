@@ -165,6 +165,13 @@ mcrt_status mcrt_run_pah(mcrt_ctx *ctx, uint64_t seed, const mcrt_run_opts *opts
  * [ns][cells] FP64 (PAH species and empty cells 0); E_out (nullable)
  * absorbed power [ns][cells] FP64 erg/s. */
 mcrt_status mcrt_temperatures(mcrt_ctx *ctx, double *T_out, double *E_out, int mem, void *stream);
+/* Eq. 4 on the device for n given right-hand sides rhs = E/(4 pi f rho V)
+ * (erg/s/g per species mass, host arrays): T_out[i] for species `species`.
+ * method 0: bracketed Newton to 1e-14 in ln T (used by Eq. 4 finalisation
+ * and epoch temperatures); 1: cubic Hermite table of ln T(ln Phi) (used at
+ * every absorption of BW_TICKET), about 1e-10 relative. */
+mcrt_status mcrt_invert_temperature(mcrt_ctx *ctx, int species, uint64_t n, const double *rhs,
+                                    double *T_out, int method);
 /* Copy of the context's temperature field [ns][cells] FP64 as it stands
  * (initial guess, values set by the caller, or the last Eq. 4 result);
  * unlike mcrt_temperatures nothing is recomputed. */

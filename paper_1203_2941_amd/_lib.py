@@ -74,6 +74,7 @@ SIGNATURES = {
     "mcrt_temperatures": (C.c_int, [_ctxp, _vp, _vp, C.c_int, _vp]),
     "mcrt_tallies": (C.c_int, [_ctxp, _vp, _vp, _vp, C.c_int, _vp]),
     "mcrt_get_temperatures": (C.c_int, [_ctxp, _vp, C.c_int, _vp]),
+    "mcrt_invert_temperature": (C.c_int, [_ctxp, C.c_int, C.c_uint64, _vp, _vp, C.c_int]),
     "mcrt_density": (C.c_int, [_ctxp, _vp, C.c_int, _vp]),
     "mcrt_sed": (C.c_int, [_ctxp, _vp, _vp, C.c_int, _vp]),
     "mcrt_scattering": (C.c_int, [_ctxp, _vp, C.c_int, _vp]),

@@ -212,6 +212,13 @@ class Context:
                                              L.HOST, None))
         return (T, E) if with_energy else T
 
+    def invert_temperature(self, species, rhs, method=0):
+        r = _f64(rhs).ravel()
+        T = np.zeros_like(r)
+        self._chk(self.lib.mcrt_invert_temperature(self.h, species, r.size, C.c_void_p(r.ctypes.data),
+                                                   C.c_void_p(T.ctypes.data), method))
+        return T
+
     def current_temperatures(self):
         T = np.zeros((self.ns, self.ncells))
         self._chk(self.lib.mcrt_get_temperatures(self.h, C.c_void_p(T.ctypes.data), L.HOST, None))

@@ -72,6 +72,7 @@ struct mcrt_ctx {
   double *d_tab = nullptr;
   void *d_rtab = nullptr;
   int32_t *d_imgmap = nullptr;
+  double *d_herm = nullptr;
   size_t tab_cap = 0, rtab_cap = 0;
   bool tables_ok = false;
   // state
@@ -212,7 +213,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  void *ps[] = {ctx->d_rho, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_k, ctx->d_epath,
+  void *ps[] = {ctx->d_rho, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_k, ctx->d_epath,
                 ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
                 ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_counter, ctx->d_stats,
                 ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
@@ -393,6 +394,52 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
       r[o.r_wk + s * nl + j] = t[o.wk + s * nl + j];
     }
   }
+  // Hermite table of ln T(ln Phi) per species (see invert_T_fast)
+  const int HS = 3 + 2 * NH_TAB;
+  std::vector<double> herm((size_t)ns * HS, 0.0);
+  for (int s = 0; s < ns; ++s) {
+    const double *wk = &t[o.wk + s * nl];
+    auto phi = [&](double T, double *dphi) {
+      double sum = 0.0, ds = 0.0;
+      for (int j = nl - 1; j >= 0; --j) {
+        double x = H_PL * nu[j] / (K_BO * T);
+        if (x > 700.0) continue;
+        double em = std::expm1(x);
+        double B = t[o.a + j] / em;
+        sum += wk[j] * B;
+        ds += wk[j] * (B * (x / T) * (1.0 + 1.0 / em));
+      }
+      *dphi = ds;
+      return sum;
+    };
+    double d0, d1;
+    double p0 = phi(T_HERM_MIN, &d0), p1 = phi(T_MAX, &d1);
+    double *hh = &herm[(size_t)s * HS];
+    if (!(p0 > 0.0) || !(p1 > p0)) {
+      hh[0] = 0.0; hh[1] = 1.0; hh[2] = 0.0;  // empty table: always the Newton path
+      continue;
+    }
+    double u0 = std::log(p0), u1 = std::log(p1), du = (u1 - u0) / (NH_TAB - 1);
+    hh[0] = u0; hh[1] = du; hh[2] = NH_TAB;
+    double T = T_HERM_MIN;
+    for (int k = 0; k < NH_TAB; ++k) {
+      double target = u0 + k * du;
+      if (k == NH_TAB - 1) T = T_MAX;
+      // Newton on ln Phi(ln T) from the previous node (monotone, smooth)
+      for (int it = 0; it < 60 && k > 0 && k < NH_TAB - 1; ++it) {
+        double dp, p = phi(T, &dp);
+        double g = std::log(p) - target;
+        double step = g / (T * dp / p);
+        double Tn = T * std::exp(-step);
+        if (!(Tn > 0.0)) break;
+        T = Tn;
+        if (std::fabs(step) < 1e-15) break;
+      }
+      double dp, p = phi(T, &dp);
+      hh[3 + 2 * k] = std::log(T);
+      hh[4 + 2 * k] = p / (T * dp);  // d ln T / d ln Phi
+    }
+  }
   std::vector<int32_t> im(nl, -1);
   for (int q = 0; q < ctx->nimg; ++q) im[ctx->img_idx[q]] = q;
   mcrt_ctx *c = ctx;
@@ -406,6 +453,8 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
     ctx->rtab_cap = rb;
   }
   HIPCHK(dev_alloc((void **)&ctx->d_imgmap, (size_t)nl * 4));
+  HIPCHK(dev_alloc((void **)&ctx->d_herm, herm.size() * 8));
+  HIPCHK(hipMemcpy(ctx->d_herm, herm.data(), herm.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(ctx->d_tab, t.data(), tb, hipMemcpyHostToDevice));
   if (ctx->fp64) {
     HIPCHK(hipMemcpy(ctx->d_rtab, r.data(), rb, hipMemcpyHostToDevice));
@@ -746,6 +795,7 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.tab = ctx->d_tab;
   M.rtab = ctx->d_rtab;
   M.imgmap = ctx->d_imgmap;
+  M.herm = ctx->d_herm;
   M.k = ctx->d_k; M.epath = ctx->d_epath; M.T = ctx->d_T; M.esnap = ctx->d_esnap; M.tt = ctx->d_tt;
   M.dirty = ctx->d_dirty; M.kpah = ctx->d_kpah; M.kpah_prefix = ctx->d_prefix;
   M.sed = ctx->d_sed;
@@ -1141,6 +1191,38 @@ extern "C" mcrt_status mcrt_temperatures(mcrt_ctx *ctx, double *T_out, double *E
   s = to_caller(ctx, E_out, ctx->d_tmp, bytes, mem, st);
   if (s) return s;
   ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+__global__ void k_invert(const double *tab, const double *herm, int nl, int ns, int nsrc, int nrows,
+                         int s, uint64_t n, const double *rhs, double *T, int method) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  TabOff o = tab_offsets(nl, ns, nsrc, nrows);
+  bool cl = false;
+  T[i] = method == 1 ? invert_T_fast(herm, tab, o, nl, s, rhs[i], &cl)
+                     : invert_T(tab, o, nl, s, rhs[i], &cl);
+}
+
+extern "C" mcrt_status mcrt_invert_temperature(mcrt_ctx *ctx, int species, uint64_t n,
+                                               const double *rhs, double *T_out, int method) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  if (species < 0 || species >= ctx->ns) return fail(ctx, MCRT_EINVAL, "bad species");
+  if (!rhs || !T_out) return fail(ctx, MCRT_EINVAL, "NULL array");
+  if (method != 0 && method != 1) return fail(ctx, MCRT_EINVAL, "method must be 0 or 1");
+  if (n == 0) return MCRT_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  double *d = nullptr;
+  HIPCHK(hipMalloc((void **)&d, n * 16));
+  HIPCHK(hipMemcpy(d, rhs, n * 8, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_invert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, ctx->d_tab,
+                     ctx->d_herm, ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows, species, n, d, d + n,
+                     method);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(T_out, d + n, n * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(ctx, MCRT_EDEVICE, "invert: %s", hipGetErrorString(e));
   return MCRT_OK;
 }
 

@@ -190,7 +190,7 @@ __device__ double mode_T(Ctx<R> &X, int s, int64_t c, double rho) {
   } else {
     double e = (double)(*(volatile uint64_t *)&M.k[q]) * M.xi + *(volatile double *)&M.epath[q];
     double rhs = (e + M.xi) / (4.0 * PI_D * frac * rho * M.V);
-    T = invert_T(X.dt, X.o, M.nl, s, rhs, &cl);
+    T = invert_T_fast(M.herm, X.dt, X.o, M.nl, s, rhs, &cl);
   }
   if (cl) stat_add(X.st, 9, 1ull);
   return T;
@@ -211,9 +211,17 @@ __device__ __forceinline__ void lucy_deposit(Ctx<R> &X, Pkt<R> &P, int64_t c, R 
   P.n_lucy++;
 }
 
+// Density gathers issued ahead per flight: the voxel path does not depend
+// on the density, only where the flight stops does, so each lane walks K
+// cells ahead, issues K independent loads, then consumes the segments in
+// order (same arithmetic and order as a one-cell-at-a-time walk).
+template <typename R> struct Ahead { static constexpr int K = 4; };
+template <> struct Ahead<double> { static constexpr int K = 2; };
+
 // One flight with optical depth tau_star. Returns true on escape.
 template <typename R, bool REC>
 __device__ bool fly(Ctx<R> &X, Pkt<R> &P, R tau_star) {
+  constexpr int K = Ahead<R>::K;
   const ModelDev &M = *X.M;
   const R p0x = P.p[0], p0y = P.p[1], p0z = P.p[2];
   const R dx = P.d[0], dy = P.d[1], dz = P.d[2];
@@ -224,52 +232,74 @@ __device__ bool fly(Ctx<R> &X, Pkt<R> &P, R tau_star) {
   R tz = plane_r<R>(M, p0z, dz, iz, cz, 2);
   const R kx = X.rt[X.o.r_kext + P.j];
   const int sx = dx > (R)0 ? 1 : -1, sy = dy > (R)0 ? 1 : -1, sz = dz > (R)0 ? 1 : -1;
+  const int64_t nxy = (int64_t)M.nx * M.ny;
   R t = (R)0, tau = (R)0;
   int64_t c = ((int64_t)cz * M.ny + cy) * M.nx + cx;
+  bool out = false;
   for (;;) {
-    int a = 0;
-    R tn = tx;
-    if (ty < tn) { a = 1; tn = ty; }
-    if (tz < tn) { a = 2; tn = tz; }
-    if (REC) {
-      R t2 = (a == 0) ? (ty < tz ? ty : tz) : (a == 1) ? (tx < tz ? tx : tz) : (tx < ty ? tx : ty);
-      if (t2 < m_inf<R>() && t2 > (R)0) upd_margin(P.mm, (double)((t2 - tn) / t2));
+    int64_t cs[K];
+    R ts[K], ls[K], rh[K];
+    int ns = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!out) {
+        int a = 0;
+        R tn = tx;
+        if (ty < tn) { a = 1; tn = ty; }
+        if (tz < tn) { a = 2; tn = tz; }
+        if (REC) {
+          R t2 = (a == 0) ? (ty < tz ? ty : tz) : (a == 1) ? (tx < tz ? tx : tz) : (tx < ty ? tx : ty);
+          if (t2 < m_inf<R>() && t2 > (R)0) upd_margin(P.mm, (double)((t2 - tn) / t2));
+        }
+        R ell = tn - t;
+        if (ell < (R)0) ell = (R)0;
+        cs[k] = c;
+        ts[k] = t;
+        ls[k] = ell;
+        ns = k + 1;
+        if (tn > t) t = tn;
+        if (a == 0) {
+          cx += sx;
+          if (cx < 0 || cx >= M.nx) out = true;
+          else { c += sx; tx = plane_r<R>(M, p0x, dx, ix, cx, 0); }
+        } else if (a == 1) {
+          cy += sy;
+          if (cy < 0 || cy >= M.ny) out = true;
+          else { c += (int64_t)sy * M.nx; ty = plane_r<R>(M, p0y, dy, iy, cy, 1); }
+        } else {
+          cz += sz;
+          if (cz < 0 || cz >= M.nz) out = true;
+          else { c += (int64_t)sz * nxy; tz = plane_r<R>(M, p0z, dz, iz, cz, 2); }
+        }
+      }
     }
-    R ell = tn - t;
-    if (ell < (R)0) ell = (R)0;
-    R rho = X.rho[c];
-    R dtau = rho * kx * ell;
-    bool thin = is_thin(X, rho);
-    if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tau_star) / tau_star));
-    if (tau + dtau > tau_star) {
-      R tint = t + (tau_star - tau) / (rho * kx);
-      if (thin) lucy_deposit(X, P, c, rho, tint - t);
-      P.p[0] = p0x + tint * dx;
-      P.p[1] = p0y + tint * dy;
-      P.p[2] = p0z + tint * dz;
-      P.c[0] = cx; P.c[1] = cy; P.c[2] = cz;
-      return false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) rh[k] = (k < ns) ? X.rho[cs[k]] : (R)0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k < ns) {
+        R rho = rh[k];
+        R dtau = rho * kx * ls[k];
+        bool thin = is_thin(X, rho);
+        if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tau_star) / tau_star));
+        if (tau + dtau > tau_star) {
+          R tint = ts[k] + (tau_star - tau) / (rho * kx);
+          if (thin) lucy_deposit(X, P, cs[k], rho, tint - ts[k]);
+          P.p[0] = p0x + tint * dx;
+          P.p[1] = p0y + tint * dy;
+          P.p[2] = p0z + tint * dz;
+          const int64_t ck = cs[k];
+          P.c[2] = (int)(ck / nxy);
+          P.c[1] = (int)((ck / M.nx) % M.ny);
+          P.c[0] = (int)(ck % M.nx);
+          return false;
+        }
+        if (thin) lucy_deposit(X, P, cs[k], rho, ls[k]);
+        tau += dtau;
+        P.n_cross++;
+      }
     }
-    if (thin) lucy_deposit(X, P, c, rho, ell);
-    tau += dtau;
-    if (tn > t) t = tn;
-    P.n_cross++;
-    if (a == 0) {
-      cx += sx;
-      if (cx < 0 || cx >= M.nx) break;
-      c += sx;
-      tx = plane_r<R>(M, p0x, dx, ix, cx, 0);
-    } else if (a == 1) {
-      cy += sy;
-      if (cy < 0 || cy >= M.ny) break;
-      c += (int64_t)sy * M.nx;
-      ty = plane_r<R>(M, p0y, dy, iy, cy, 1);
-    } else {
-      cz += sz;
-      if (cz < 0 || cz >= M.nz) break;
-      c += (int64_t)sz * M.nx * M.ny;
-      tz = plane_r<R>(M, p0z, dz, iz, cz, 2);
-    }
+    if (out) break;
   }
   P.p[0] = p0x + t * dx;
   P.p[1] = p0y + t * dy;
@@ -579,7 +609,7 @@ __device__ void advance(Ctx<R> &X, Pkt<R> &P) {
         double e = (double)kold * M.xi + *(volatile double *)&M.epath[qk];
         double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s] * (double)rho * M.V);
         bool cl = false;
-        T = invert_T(X.dt, X.o, nl, s, rhs, &cl);
+        T = invert_T_fast(M.herm, X.dt, X.o, nl, s, rhs, &cl);
         if (cl) stat_add(X.st, 9, 1ull);
       } else {
         if (!thin) atomicAdd((unsigned long long *)&M.k[qk], 1ull);

@@ -81,6 +81,25 @@ def test_init_temperatures(orc):
     np.testing.assert_allclose(g.current_temperatures(), o.T, rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("method,tol", [(0, 1e-12), (1, 1e-9)])
+def test_eq4_inversion_matches_oracle(orc, method, tol):
+    """Device Eq. 4 (Newton, and the Hermite table used at every immediate
+    B&W absorption) against the oracle's bisection, 3 K .. 3e4 K."""
+    m = mi.torus(n=8, n_clumps=5, n_packets=10)
+    o = orc.Oracle(m)
+    g = gpu_context(m)
+    for s in (0, 1):
+        Ts = np.geomspace(3.5, 3e4, 400)
+        rhs = np.array([o.phi(s, t) for t in Ts])
+        got = g.invert_temperature(s, rhs, method)
+        ref = np.array([o.invert_T(s, r) for r in rhs])
+        np.testing.assert_allclose(got, ref, rtol=tol)
+        np.testing.assert_allclose(got, Ts, rtol=max(tol, 1e-11))
+    # outside the table both fall back or clamp like the oracle
+    lo = g.invert_temperature(0, np.array([o.phi(0, 1.5), 0.0, o.phi(0, 2e5)]), method)
+    assert lo[0] == pytest.approx(1.5, rel=1e-9) and lo[1] == 0.0 and lo[2] == 1e5
+
+
 def test_resume_and_determinism(orc):
     m = mi.cube(n=16, n_packets=20000, tau_v=2.0)
     a = gpu_context(m)

@@ -1,0 +1,47 @@
+"""Host-side logic that needs no GPU: autotuner signature and cache,
+bench's one-GPU contract, option validation in the binding."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+class FakeCtx:
+    def __init__(self, n, nl, ns, fp64=False):
+        self.nx = self.ny = self.nz = n
+        self.nl, self.ns, self.fp64 = nl, ns, fp64
+
+
+def test_autotune_signature_and_cache(tmp_path, monkeypatch):
+    from paper_1203_2941_amd import autotune
+    a = [FakeCtx(64, 40, 3), FakeCtx(128, 100, 3)]
+    b = [FakeCtx(64, 40, 3), FakeCtx(128, 100, 3)]
+    c = [FakeCtx(64, 41, 3), FakeCtx(128, 100, 3)]
+    assert autotune.signature(a, "bw_ticket") == autotune.signature(b, "bw_ticket")
+    assert autotune.signature(a, "bw_ticket") != autotune.signature(c, "bw_ticket")
+    assert autotune.signature(a, "bw_ticket") != autotune.signature(a, "frozen")
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "t.json"))
+    key = autotune.signature(a, "bw_ticket")
+    hit = {"block_size": 128, "blocks_per_cu": 4, "packets_per_s": 1.0, "rates": {}, "sample_packets": 1}
+    (tmp_path / "t.json").write_text(json.dumps({key: hit}))
+    # a cached entry is returned without touching the GPU
+    assert autotune.tune(a, [1, 1], [0, 1], mode="bw_ticket") == hit
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_run_opts_modes():
+    from paper_1203_2941_amd import context, _lib
+    o = context.run_opts(mode="bw_epoch", epoch_packets=7, record=True)
+    assert o.mode == _lib.BW_EPOCH and o.epoch_packets == 7 and o.record == 1
+    with pytest.raises(KeyError):
+        context.run_opts(mode="nonsense")
