@@ -27,7 +27,7 @@ hipError_t launch_transport(const ModelDev *d_models, int nmodels, bool fp64, bo
 hipError_t launch_epoch_snapshot(const ModelDev *d, hipStream_t st);
 hipError_t launch_finalize_T(const ModelDev *d, bool fp64, double *T, double *E, hipStream_t st);
 hipError_t launch_init_T(const ModelDev *d, bool fp64, double *T, hipStream_t st);
-hipError_t launch_build_S(const ModelDev *d, int v, bool fp64, void *S, hipStream_t st);
+hipError_t launch_build_S(const ModelDev *d, bool fp64, void *S, hipStream_t st);
 hipError_t launch_vox_torus(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
                             int ncl, const double *dC, double r_clump, double rho_cl,
                             double rho_int, double r_in, double r_out, double s1, void *rho,
@@ -377,6 +377,34 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
       for (int j = nl - 1; j >= 0; --j) ph += t[o.wk + s * nl + j] * h_planck(nu[j], T);
       t[o.logphi + s * NT_TAB + k] = std::log(ph);  // -inf where Phi underflows
     }
+  // per-interval upper bound of the mixture Rosseland mean on the ln T grid
+  {
+    auto kross = [&](double T) {
+      double num = 0.0, den = 0.0;
+      for (int j = nl - 1; j >= 0; --j) {
+        if (!(kext[j] > 0.0)) return 0.0;
+        double x = H_PL * nu[j] / (K_BO * T);
+        if (x > 700.0) continue;
+        double em = std::expm1(x);
+        double B = t[o.a + j] / em;
+        double db = w[j] * (B * (x / T) * (1.0 + 1.0 / em));
+        num += db;
+        den += db / kext[j];
+      }
+      return den > 0.0 ? num / den : 0.0;
+    };
+    double gmax = 0.0;
+    for (int k = 0; k < NT_TAB - 1; ++k) {
+      double mx = 0.0;
+      for (int q = 0; q <= 8; ++q) {
+        double v = kross(std::exp(lt0 + (k + q / 8.0) * dlt));
+        if (v > mx) mx = v;
+      }
+      t[o.krmax + k] = 1.02 * mx;
+      if (mx > gmax) gmax = mx;
+    }
+    t[o.krmax + NT_TAB - 1] = ctx->kext_max;  // outside the grid: the hard bound
+  }
   // walk-precision table
   std::vector<double> r(o.r_total, 0.0);
   for (int j = 0; j < nl; ++j) {
@@ -796,6 +824,7 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.rtab = ctx->d_rtab;
   M.imgmap = ctx->d_imgmap;
   M.herm = ctx->d_herm;
+  for (int q = 0; q < ctx->nimg; ++q) M.img_j[q] = ctx->img_idx[q];
   M.k = ctx->d_k; M.epath = ctx->d_epath; M.T = ctx->d_T; M.esnap = ctx->d_esnap; M.tt = ctx->d_tt;
   M.dirty = ctx->d_dirty; M.kpah = ctx->d_kpah; M.kpah_prefix = ctx->d_prefix;
   M.sed = ctx->d_sed;
@@ -1341,7 +1370,7 @@ static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_r
     }
     s = upload_model_only(ctx, st);
     if (s) return s;
-    for (int v = 0; v < ctx->nview; ++v) HIPCHK(launch_build_S(ctx->d_model, v, ctx->fp64, ctx->d_S, st));
+    HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, ctx->d_S, st));
     ctx->S_ok = true;
   }
   memset(&A, 0, sizeof A);

@@ -35,7 +35,7 @@ enum { NSTAT = 10 };  // packets escaped killed pah crossings scatters absorptio
 // source spectra); the R table holds what the packet walk reads per event
 // in the walk's precision.
 struct TabOff {
-  int w, hnu, a, kext, wk, wfk, kabs, frac, srcf, lnu, lum, pahw, pahe, logphi, srcpos, dtotal;
+  int w, hnu, a, kext, wk, wfk, kabs, frac, srcf, lnu, lum, pahw, pahe, logphi, krmax, srcpos, dtotal;
   int r_kext, r_kabsm, r_alb, r_fsca, r_fabs, r_g, r_lucy, r_hnu, r_a, r_wk, r_total;
 };
 
@@ -56,6 +56,7 @@ __host__ __device__ inline TabOff tab_offsets(int nl, int ns, int nsrc, int nrow
   o.pahw = p; p += (nrows > 0 ? nrows : 1) * nl;
   o.pahe = p; p += (nrows > 0 ? nrows : 1);
   o.logphi = p; p += ns * NT_TAB;
+  o.krmax = p; p += NT_TAB;
   o.srcpos = p; p += 3 * MAX_SRC;
   o.dtotal = p;
   int q = 0;
@@ -86,6 +87,7 @@ struct ModelDev {
   const void *rtab;           // packed R table
   const int32_t *imgmap;      // [nl] -> imaged index or -1
   const double *herm;         // [ns][3 + 2*NH_TAB]: u0, du, n, then (ln T, dlnT/dlnPhi) per node
+  int32_t img_j[MAX_IMG];     // wavelength index of each imaged wavelength
   uint64_t *k;                // [ns][cells]
   double *epath;              // [ns][cells]
   double *T;                  // [ns][cells]
@@ -221,7 +223,7 @@ __device__ inline double phi_dphi(const double *wk, const double *hnu, const dou
 // Newton on ln Phi(ln T) until |d ln T| < 1e-14. rhs <= 0 -> 0; rhs at or
 // above Phi(T_MAX) -> T_MAX with *clamped set.
 __device__ inline double invert_T(const double *tab, const TabOff &o, int nl, int s, double rhs,
-                                  bool *clamped) {
+                                  bool *clamped, double u_start = 0.0, bool have_start = false) {
   if (!(rhs > 0.0)) return 0.0;
   const double *lp = tab + o.logphi + s * NT_TAB;
   const double *wk = tab + o.wk + s * nl;
@@ -252,6 +254,7 @@ __device__ inline double invert_T(const double *tab, const TabOff &o, int nl, in
     uhi = lt0 + hi * dlt;
     double den = lp[hi] - lp[lo];
     u = (den > 0.0 && lp[lo] > -1e300) ? ulo + (lr - lp[lo]) / den * dlt : 0.5 * (ulo + uhi);
+    if (have_start && u_start > ulo && u_start < uhi) u = u_start;
   }
   for (int it = 0; it < 100; ++it) {
     double T = exp(u);
@@ -278,6 +281,28 @@ __device__ inline double invert_T(const double *tab, const TabOff &o, int nl, in
 // ln Phi grid whose node values and slopes are exact (host FP64). Interval
 // error ~ du^4/384 |y''''| (about 1e-10 relative in T for 2048 nodes); falls
 // back to the Newton solve outside the table.
+__device__ inline bool herm_lnT(const double *herm, int s, double rhs, double *lnT) {
+  const double *h = herm + (size_t)s * (3 + 2 * NH_TAB);
+  double x = (log(rhs) - h[0]) / h[1];
+  int n = (int)h[2];
+  if (!(x >= 0.0) || !(x < (double)(n - 1))) return false;
+  int k = (int)x;
+  double t = x - (double)k, t2 = t * t, t3 = t2 * t;
+  const double *p = h + 3 + 2 * k;
+  *lnT = (2.0 * t3 - 3.0 * t2 + 1.0) * p[0] + (t3 - 2.0 * t2 + t) * h[1] * p[1] +
+         (-2.0 * t3 + 3.0 * t2) * p[2] + (t3 - t2) * h[1] * p[3];
+  return true;
+}
+
+// Eq. 4 in FP64 to 1e-14, Newton started from the Hermite estimate.
+__device__ inline double invert_T_exact(const double *herm, const double *tab, const TabOff &o,
+                                        int nl, int s, double rhs, bool *clamped) {
+  if (!(rhs > 0.0)) return 0.0;
+  double u0;
+  bool ok = herm && herm_lnT(herm, s, rhs, &u0);
+  return invert_T(tab, o, nl, s, rhs, clamped, u0, ok);
+}
+
 __device__ inline double invert_T_fast(const double *herm, const double *tab, const TabOff &o,
                                        int nl, int s, double rhs, bool *clamped) {
   if (!(rhs > 0.0)) return 0.0;

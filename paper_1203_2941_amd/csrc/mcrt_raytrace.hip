@@ -106,36 +106,55 @@ __device__ __forceinline__ void absorb_pair(float x, float &om, float &e) {
   e = expf(-x);
 }
 
-// S[v][c][q] = sum_s f_s kabs_s B(T_s)/kext + Ssca/(V w rho kext).
+// S[v][c][q] = sum_s f_s kabs_s B(T_s)/kext + Ssca/(V w rho kext): one lane
+// per cell evaluates the view-independent emission once and writes the
+// 16-wide source vector of every view.
 template <typename R>
-__global__ void k_build_S(const ModelDev *__restrict__ md, int v, R *S) {
+__global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
   const ModelDev &M = *md;
   TabOff o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
   const R *rho = (const R *)M.rho;
   const R *ss = (const R *)M.ssca;
   const int nq = M.nimg;
-  uint64_t n = M.ncell * (uint64_t)nq;
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) {
-    uint64_t c = i / nq;
-    int q = (int)(i - c * nq);
-    int j = 0;
-    for (int jj = 0; jj < M.nl; ++jj)
-      if (M.imgmap[jj] == q) j = jj;
-    double em = 0.0;
+  for (; c < M.ncell; c += stride) {
+    double T[MAX_NS];
+    bool hot = false;
     for (int s = 0; s < M.ns; ++s) {
-      if (s == M.pah) continue;
-      em += M.tab[o.frac + s] * M.tab[o.kabs + s * M.nl + j] *
-            planck_d(M.tab[o.hnu + j], M.tab[o.a + j], M.T[(uint64_t)s * M.ncell + c]);
+      T[s] = (s == M.pah) ? 0.0 : M.T[(uint64_t)s * M.ncell + c];
+      hot |= T[s] > 0.0;
     }
-    double ke = M.tab[o.kext + j];
-    double val = em / ke;
     double r = (double)rho[c];
-    if (ss && r > 0.0)
-      val += (double)ss[((uint64_t)v * nq + q) * M.ncell + c] * M.ssca_unit /
-             (M.V * M.tab[o.w + j] * r * ke);
-    S[((uint64_t)v * M.ncell + c) * nq + q] = (R)val;
+    double em[MAX_IMG];
+#pragma unroll
+    for (int q = 0; q < MAX_IMG; ++q) {
+      em[q] = 0.0;
+      if (q < nq && hot) {
+        int j = M.img_j[q];
+        double e = 0.0;
+        for (int s = 0; s < M.ns; ++s) {
+          if (s == M.pah) continue;
+          e += M.tab[o.frac + s] * M.tab[o.kabs + s * M.nl + j] *
+               planck_d(M.tab[o.hnu + j], M.tab[o.a + j], T[s]);
+        }
+        em[q] = e / M.tab[o.kext + j];
+      }
+    }
+    for (int v = 0; v < M.nview; ++v) {
+      R *out = S + ((uint64_t)v * M.ncell + c) * nq;
+#pragma unroll
+      for (int q = 0; q < MAX_IMG; ++q) {
+        if (q >= nq) break;
+        double val = em[q];
+        if (ss && r > 0.0) {
+          int j = M.img_j[q];
+          val += (double)ss[((uint64_t)v * nq + q) * M.ncell + c] * M.ssca_unit /
+                 (M.V * M.tab[o.w + j] * r * M.tab[o.kext + j]);
+        }
+        out[q] = (R)val;
+      }
+    }
   }
 }
 
@@ -349,9 +368,9 @@ __global__ void k_rt_star_adj(const RtArgs *__restrict__ Ap, const R *w_img, con
   });
 }
 
-hipError_t launch_build_S(const ModelDev *d, int v, bool fp64, void *S, hipStream_t st) {
-  if (fp64) hipLaunchKernelGGL(k_build_S<double>, dim3(4096), dim3(256), 0, st, d, v, (double *)S);
-  else hipLaunchKernelGGL(k_build_S<float>, dim3(4096), dim3(256), 0, st, d, v, (float *)S);
+hipError_t launch_build_S(const ModelDev *d, bool fp64, void *S, hipStream_t st) {
+  if (fp64) hipLaunchKernelGGL(k_build_S<double>, dim3(8192), dim3(256), 0, st, d, (double *)S);
+  else hipLaunchKernelGGL(k_build_S<float>, dim3(8192), dim3(256), 0, st, d, (float *)S);
   return hipGetLastError();
 }
 

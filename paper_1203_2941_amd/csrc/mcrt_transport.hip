@@ -184,7 +184,7 @@ __device__ double mode_T(Ctx<R> &X, int s, int64_t c, double rho) {
     T = M.tt[q];
     if (T < 0.0) {
       double rhs = (M.esnap[q] + M.xi) / (4.0 * PI_D * frac * rho * M.V);
-      T = invert_T(X.dt, X.o, M.nl, s, rhs, &cl);
+      T = invert_T_exact(M.herm, X.dt, X.o, M.nl, s, rhs, &cl);
       M.tt[q] = T;  // every lane computes the same value from the snapshot
     }
   } else {
@@ -218,94 +218,113 @@ __device__ __forceinline__ void lucy_deposit(Ctx<R> &X, Pkt<R> &P, int64_t c, R 
 template <typename R> struct Ahead { static constexpr int K = 4; };
 template <> struct Ahead<double> { static constexpr int K = 2; };
 
-// One flight with optical depth tau_star. Returns true on escape.
+// State of a flight in progress (kept per lane across event cycles).
+template <typename R>
+struct Flight {
+  R tx, ty, tz, t, tau, tstar, kx, ix, iy, iz;
+  int64_t c;
+  int cx, cy, cz;
+  bool out;
+};
+
+template <typename R>
+__device__ __forceinline__ void flight_setup(const Ctx<R> &X, const Pkt<R> &P, Flight<R> &F,
+                                             R tau_star) {
+  const ModelDev &M = *X.M;
+  F.cx = P.c[0]; F.cy = P.c[1]; F.cz = P.c[2];
+  F.ix = (R)1 / P.d[0]; F.iy = (R)1 / P.d[1]; F.iz = (R)1 / P.d[2];
+  F.tx = plane_r<R>(M, P.p[0], P.d[0], F.ix, F.cx, 0);
+  F.ty = plane_r<R>(M, P.p[1], P.d[1], F.iy, F.cy, 1);
+  F.tz = plane_r<R>(M, P.p[2], P.d[2], F.iz, F.cz, 2);
+  F.kx = X.rt[X.o.r_kext + P.j];
+  F.t = (R)0;
+  F.tau = (R)0;
+  F.tstar = tau_star;
+  F.c = ((int64_t)F.cz * M.ny + F.cy) * M.nx + F.cx;
+  F.out = false;
+}
+
+// One batch of up to K cell crossings of the flight in F, starting at the
+// flight origin P.p. Returns 0 to continue, 1 at an interaction (P.p and
+// P.c set to the interaction point), 2 on escape (P.p at the exit point).
 template <typename R, bool REC>
-__device__ bool fly(Ctx<R> &X, Pkt<R> &P, R tau_star) {
+__device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   constexpr int K = Ahead<R>::K;
   const ModelDev &M = *X.M;
   const R p0x = P.p[0], p0y = P.p[1], p0z = P.p[2];
   const R dx = P.d[0], dy = P.d[1], dz = P.d[2];
-  int cx = P.c[0], cy = P.c[1], cz = P.c[2];
-  const R ix = (R)1 / dx, iy = (R)1 / dy, iz = (R)1 / dz;
-  R tx = plane_r<R>(M, p0x, dx, ix, cx, 0);
-  R ty = plane_r<R>(M, p0y, dy, iy, cy, 1);
-  R tz = plane_r<R>(M, p0z, dz, iz, cz, 2);
-  const R kx = X.rt[X.o.r_kext + P.j];
   const int sx = dx > (R)0 ? 1 : -1, sy = dy > (R)0 ? 1 : -1, sz = dz > (R)0 ? 1 : -1;
   const int64_t nxy = (int64_t)M.nx * M.ny;
-  R t = (R)0, tau = (R)0;
-  int64_t c = ((int64_t)cz * M.ny + cy) * M.nx + cx;
-  bool out = false;
-  for (;;) {
-    int64_t cs[K];
-    R ts[K], ls[K], rh[K];
-    int ns = 0;
+  const R kx = F.kx, tau_star = F.tstar;
+  int64_t cs[K];
+  R ts[K], ls[K], rh[K];
+  int ns = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (!out) {
-        int a = 0;
-        R tn = tx;
-        if (ty < tn) { a = 1; tn = ty; }
-        if (tz < tn) { a = 2; tn = tz; }
-        if (REC) {
-          R t2 = (a == 0) ? (ty < tz ? ty : tz) : (a == 1) ? (tx < tz ? tx : tz) : (tx < ty ? tx : ty);
-          if (t2 < m_inf<R>() && t2 > (R)0) upd_margin(P.mm, (double)((t2 - tn) / t2));
-        }
-        R ell = tn - t;
-        if (ell < (R)0) ell = (R)0;
-        cs[k] = c;
-        ts[k] = t;
-        ls[k] = ell;
-        ns = k + 1;
-        if (tn > t) t = tn;
-        if (a == 0) {
-          cx += sx;
-          if (cx < 0 || cx >= M.nx) out = true;
-          else { c += sx; tx = plane_r<R>(M, p0x, dx, ix, cx, 0); }
-        } else if (a == 1) {
-          cy += sy;
-          if (cy < 0 || cy >= M.ny) out = true;
-          else { c += (int64_t)sy * M.nx; ty = plane_r<R>(M, p0y, dy, iy, cy, 1); }
-        } else {
-          cz += sz;
-          if (cz < 0 || cz >= M.nz) out = true;
-          else { c += (int64_t)sz * nxy; tz = plane_r<R>(M, p0z, dz, iz, cz, 2); }
-        }
+  for (int k = 0; k < K; ++k) {
+    if (!F.out) {
+      int a = 0;
+      R tn = F.tx;
+      if (F.ty < tn) { a = 1; tn = F.ty; }
+      if (F.tz < tn) { a = 2; tn = F.tz; }
+      if (REC) {
+        R t2 = (a == 0) ? (F.ty < F.tz ? F.ty : F.tz) : (a == 1) ? (F.tx < F.tz ? F.tx : F.tz)
+                                                               : (F.tx < F.ty ? F.tx : F.ty);
+        if (t2 < m_inf<R>() && t2 > (R)0) upd_margin(P.mm, (double)((t2 - tn) / t2));
+      }
+      R ell = tn - F.t;
+      if (ell < (R)0) ell = (R)0;
+      cs[k] = F.c;
+      ts[k] = F.t;
+      ls[k] = ell;
+      ns = k + 1;
+      if (tn > F.t) F.t = tn;
+      if (a == 0) {
+        F.cx += sx;
+        if (F.cx < 0 || F.cx >= M.nx) F.out = true;
+        else { F.c += sx; F.tx = plane_r<R>(M, p0x, dx, F.ix, F.cx, 0); }
+      } else if (a == 1) {
+        F.cy += sy;
+        if (F.cy < 0 || F.cy >= M.ny) F.out = true;
+        else { F.c += (int64_t)sy * M.nx; F.ty = plane_r<R>(M, p0y, dy, F.iy, F.cy, 1); }
+      } else {
+        F.cz += sz;
+        if (F.cz < 0 || F.cz >= M.nz) F.out = true;
+        else { F.c += (int64_t)sz * nxy; F.tz = plane_r<R>(M, p0z, dz, F.iz, F.cz, 2); }
       }
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) rh[k] = (k < ns) ? X.rho[cs[k]] : (R)0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k < ns) {
-        R rho = rh[k];
-        R dtau = rho * kx * ls[k];
-        bool thin = is_thin(X, rho);
-        if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tau_star) / tau_star));
-        if (tau + dtau > tau_star) {
-          R tint = ts[k] + (tau_star - tau) / (rho * kx);
-          if (thin) lucy_deposit(X, P, cs[k], rho, tint - ts[k]);
-          P.p[0] = p0x + tint * dx;
-          P.p[1] = p0y + tint * dy;
-          P.p[2] = p0z + tint * dz;
-          const int64_t ck = cs[k];
-          P.c[2] = (int)(ck / nxy);
-          P.c[1] = (int)((ck / M.nx) % M.ny);
-          P.c[0] = (int)(ck % M.nx);
-          return false;
-        }
-        if (thin) lucy_deposit(X, P, cs[k], rho, ls[k]);
-        tau += dtau;
-        P.n_cross++;
-      }
-    }
-    if (out) break;
   }
-  P.p[0] = p0x + t * dx;
-  P.p[1] = p0y + t * dy;
-  P.p[2] = p0z + t * dz;
-  P.c[0] = cx; P.c[1] = cy; P.c[2] = cz;
-  return true;
+#pragma unroll
+  for (int k = 0; k < K; ++k) rh[k] = (k < ns) ? X.rho[cs[k]] : (R)0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (k < ns) {
+      R rho = rh[k];
+      R dtau = rho * kx * ls[k];
+      bool thin = is_thin(X, rho);
+      if (REC) upd_margin(P.mm, (double)(m_fabs(F.tau + dtau - tau_star) / tau_star));
+      if (F.tau + dtau > tau_star) {
+        R tint = ts[k] + (tau_star - F.tau) / (rho * kx);
+        if (thin) lucy_deposit(X, P, cs[k], rho, tint - ts[k]);
+        P.p[0] = p0x + tint * dx;
+        P.p[1] = p0y + tint * dy;
+        P.p[2] = p0z + tint * dz;
+        const int64_t ck = cs[k];
+        P.c[2] = (int)(ck / nxy);
+        P.c[1] = (int)((ck / M.nx) % M.ny);
+        P.c[0] = (int)(ck % M.nx);
+        return 1;
+      }
+      if (thin) lucy_deposit(X, P, cs[k], rho, ls[k]);
+      F.tau += dtau;
+      P.n_cross++;
+    }
+  }
+  if (!F.out) return 0;
+  P.p[0] = p0x + F.t * dx;
+  P.p[1] = p0y + F.t * dy;
+  P.p[2] = p0z + F.t * dz;
+  P.c[0] = F.cx; P.c[1] = F.cy; P.c[2] = F.cz;
+  return 2;
 }
 
 template <typename R>
@@ -352,6 +371,14 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
   if (!(rho * M.kext_max * M.dcell > M.mrw_tau)) return false;
   int s0 = first_thermal(M);
   double T0 = mode_T(X, s0, c, rho);
+  if (!REC) {
+    // rigorous upper bound of kappa_R(T) on its table interval: skip the
+    // exact mean when even the bound cannot reach the threshold
+    const double lt0 = log(T_TAB_MIN), dlt = (log(T_MAX) - lt0) / (NT_TAB - 1);
+    double xk = (log(T0) - lt0) / dlt;
+    int k = (xk >= 0.0 && xk < (double)(NT_TAB - 1)) ? (int)xk : NT_TAB - 1;
+    if (!(rho * X.dt[X.o.krmax + k] * M.dcell > M.mrw_tau)) return false;
+  }
   double kr = rosseland(X, T0);
   double taur = rho * kr * M.dcell;
   if (REC) upd_margin(P.mm, fabs(taur - M.mrw_tau) / M.mrw_tau);
@@ -445,15 +472,17 @@ __device__ __forceinline__ int pick_thermal(const Ctx<R> &X, int s, double T, R 
     const R kT = (R)(K_BO * T);
     const R Tr = (R)T;
     const R cut = x_cut<R>();
+    // e^x - 1 from the hardware exponential, with a 3-term series below 0.03
+    auto em1 = [](R x) { return x < (R)0.03 ? x * ((R)1 + x * ((R)0.5 + x * (R)(1.0 / 6.0))) : __expf(x) - (R)1; };
     if (M.mode == M_FROZEN)
       return pick_desc_fn<R, REC>(nl, u, mm, [&](int j) {
         R x = hnu[j] / kT;
-        return x > cut ? (R)0 : wk[j] * (a[j] / m_expm1(x));
+        return x > cut ? (R)0 : wk[j] * (a[j] / em1(x));
       });
     return pick_desc_fn<R, REC>(nl, u, mm, [&](int j) {
       R x = hnu[j] / kT;
       if (x > cut) return (R)0;
-      R em = m_expm1(x);
+      R em = em1(x);
       R B = a[j] / em;
       return wk[j] * (B * (x / Tr) * ((R)1 + (R)1 / em));
     });
@@ -546,23 +575,29 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
     P.status = ST_ESCAPED;
 }
 
-// One event cycle: MRW steps, a flight, an interaction.
+// Start of a flight: modified random walk steps while they apply, then the
+// optical depth of the flight. Returns false when the packet is killed.
 template <typename R, bool REC>
-__device__ void advance(Ctx<R> &X, Pkt<R> &P) {
+__device__ bool flight_start(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   const ModelDev &M = *X.M;
-  const int nl = M.nl, ns = M.ns;
   while (mrw_step<R, REC>(X, P)) {
     P.n_int++;
     if (M.max_int > 0 && P.n_int >= M.max_int) {
       P.status = ST_KILLED;
-      return;
+      return false;
     }
   }
   R tau_star = -m_log(rng_u<R>(P.rng));
-  if (fly<R, REC>(X, P, tau_star)) {
-    P.status = ST_ESCAPED;
-    return;
-  }
+  flight_setup<R>(X, P, F, tau_star);
+  return true;
+}
+
+// Interaction at P.p in cell P.c: albedo split, HG scattering with its
+// event sums, or absorption with re-emission (or a PAH stop).
+template <typename R, bool REC>
+__device__ void interact(Ctx<R> &X, Pkt<R> &P) {
+  const ModelDev &M = *X.M;
+  const int nl = M.nl, ns = M.ns;
   int64_t c = ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0];
   R ualb = rng_u<R>(P.rng), usp = rng_u<R>(P.rng);
   const int j = P.j;
@@ -680,32 +715,46 @@ __global__ void __launch_bounds__(256) k_transport(const ModelDev *__restrict__ 
     X.st = s_stat;
 
     Pkt<R> P;
-    bool active = false, exhausted = false;
+    Flight<R> F;
+    // lane states: 0 needs a packet, 1 flight start, 2 in flight, 3 interaction, 4 no work left
+    int state = 0;
     for (;;) {
-      uint64_t need = __ballot(!active && !exhausted);
+      uint64_t need = __ballot(state == 0);
       if (need) {
         int leader = __ffsll((unsigned long long)need) - 1;
         uint64_t base = 0;
         if (lane == leader) base = atomicAdd((unsigned long long *)M.counter,
                                              (unsigned long long)__popcll(need));
         base = shfl64(base, leader);
-        if (!active && !exhausted) {
+        if (state == 0) {
           uint64_t idx = base + (uint64_t)__popcll(need & lt_mask);
           if (idx < M.n) {
             start_packet<R, REC>(X, P, idx);
-            if (P.status != ST_ALIVE) finish<R, REC>(X, P); else active = true;
+            if (P.status != ST_ALIVE) finish<R, REC>(X, P); else state = 1;
           } else {
-            exhausted = true;
+            state = 4;
           }
         }
       }
-      if (!__any(active)) break;
-      if (active) {
-        advance<R, REC>(X, P);
-        if (P.status != ST_ALIVE) {
-          finish<R, REC>(X, P);
-          active = false;
+      if (!__any(state != 4)) break;
+      // interactions wait until half the wave has one, or nothing else can run
+      const uint64_t mi = __ballot(state == 3);
+      const uint64_t mf = __ballot(state == 1 || state == 2);
+      if (mi && (__popcll(mi) >= 32 || mf == 0)) {
+        if (state == 3) {
+          interact<R, REC>(X, P);
+          if (P.status != ST_ALIVE) { finish<R, REC>(X, P); state = 0; }
+          else state = 1;
         }
+      }
+      if (state == 1) {
+        if (flight_start<R, REC>(X, P, F)) state = 2;
+        else { finish<R, REC>(X, P); state = 0; }
+      }
+      if (state == 2) {
+        int r = flight_batch<R, REC>(X, P, F);
+        if (r == 1) state = 3;
+        else if (r == 2) { P.status = ST_ESCAPED; finish<R, REC>(X, P); state = 0; }
       }
     }
     // flush block SED and statistics
@@ -783,7 +832,9 @@ __global__ void k_finalize_T(const ModelDev *__restrict__ md, double *T, double 
     double t = 0.0;
     if (s != M.pah && r > 0.0 && frac > 0.0) {
       bool cl = false;
-      t = invert_T(M.tab, o, M.nl, s, e / (4.0 * PI_D * frac * r * M.V), &cl);
+      double rhs = e / (4.0 * PI_D * frac * r * M.V);
+      t = (sizeof(R) == 8) ? invert_T_exact(M.herm, M.tab, o, M.nl, s, rhs, &cl)
+                           : invert_T_fast(M.herm, M.tab, o, M.nl, s, rhs, &cl);
       if (cl) atomicAdd(&M.stats[9], 1ull);
     }
     T[i] = t;
