@@ -28,6 +28,8 @@ hipError_t launch_epoch_snapshot(const ModelDev *d, hipStream_t st);
 hipError_t launch_finalize_T(const ModelDev *d, bool fp64, double *T, double *E, hipStream_t st);
 hipError_t launch_init_T(const ModelDev *d, bool fp64, double *T, hipStream_t st);
 hipError_t launch_build_S(const ModelDev *d, bool fp64, void *S, hipStream_t st);
+hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, int nz, int nbx,
+                        int nby, hipStream_t st);
 hipError_t launch_vox_torus(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
                             int ncl, const double *dC, double r_clump, double rho_cl,
                             double rho_int, double r_in, double r_out, double s1, void *rho,
@@ -53,6 +55,8 @@ struct mcrt_ctx {
   double origin[3] = {0, 0, 0}, dcell = 0;
   uint64_t ncell = 0;
   void *d_rho = nullptr;
+  void *d_rho_b = nullptr;  // density in 4x4x4 bricks for the walk
+  int nbx = 0, nby = 0, nbz = 0;
   // dust
   bool has_dust = false;
   int nl = 0, ns = 0, pah = -1, nrows = 0;
@@ -100,6 +104,9 @@ struct mcrt_ctx {
   void *d_S = nullptr;
   size_t S_cap = 0;
   bool S_ok = false;
+  // tallies changed by a run outside B&W epochs, which keeps no dirty flags:
+  // the next epoch snapshot must then cover every cell
+  bool snap_stale = false;
   RtArgs *d_rt = nullptr;
   void *d_img_tmp = nullptr;
   size_t img_cap = 0;
@@ -213,7 +220,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  void *ps[] = {ctx->d_rho, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_k, ctx->d_epath,
+  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_k, ctx->d_epath,
                 ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
                 ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_counter, ctx->d_stats,
                 ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
@@ -306,6 +313,7 @@ static mcrt_status zero_epoch(mcrt_ctx *ctx, hipStream_t st) {
   HIPCHK(fill<double>(ctx->d_esnap, 0.0, n, st));
   HIPCHK(fill<double>(ctx->d_tt, -1.0, n, st));
   HIPCHK(fill<uint8_t>(ctx->d_dirty, (uint8_t)0, ctx->ncell, st));
+  ctx->snap_stale = false;
   return MCRT_OK;
 }
 
@@ -499,6 +507,21 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
 
 // ------------------------------------------------------------------- set
 
+// Bricked copy of the density read by the walk; rebuilt whenever the
+// density changes.
+static mcrt_status build_brick(mcrt_ctx *ctx) {
+  ctx->nbx = (ctx->nx + 3) / 4;
+  ctx->nby = (ctx->ny + 3) / 4;
+  ctx->nbz = (ctx->nz + 3) / 4;
+  const uint64_t nb = (uint64_t)ctx->nbx * ctx->nby * ctx->nbz * 64;
+  HIPCHK(dev_alloc(&ctx->d_rho_b, nb * rsize(ctx)));
+  HIPCHK(hipMemset(ctx->d_rho_b, 0, nb * rsize(ctx)));
+  HIPCHK(launch_brick(ctx->fp64, ctx->d_rho, ctx->d_rho_b, ctx->nx, ctx->ny, ctx->nz, ctx->nbx,
+                      ctx->nby, 0));
+  HIPCHK(hipDeviceSynchronize());
+  return MCRT_OK;
+}
+
 static bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
 extern "C" mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
@@ -534,6 +557,10 @@ extern "C" mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, cons
   for (int k = 0; k < 3; ++k) ctx->origin[k] = origin[k];
   ctx->dcell = dcell;
   ctx->ncell = n;
+  {
+    mcrt_status sb = build_brick(ctx);
+    if (sb) return sb;
+  }
   ctx->has_grid = true;
   ctx->S_ok = false;
   if (ctx->has_dust) {
@@ -564,6 +591,8 @@ static mcrt_status grid_geom(mcrt_ctx *ctx, int nx, int ny, int nz, const double
 }
 
 static mcrt_status grid_done(mcrt_ctx *ctx) {
+  mcrt_status sb = build_brick(ctx);
+  if (sb) return sb;
   ctx->has_grid = true;
   ctx->S_ok = false;
   if (ctx->has_dust) {
@@ -820,6 +849,8 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.max_int = o ? o->max_interactions : 0;
   M.ncell = ctx->ncell;
   M.rho = ctx->d_rho;
+  M.rho_b = ctx->d_rho_b;
+  M.nbx = ctx->nbx; M.nby = ctx->nby; M.nbz = ctx->nbz;
   M.tab = ctx->d_tab;
   M.rtab = ctx->d_rtab;
   M.imgmap = ctx->d_imgmap;
@@ -880,6 +911,7 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, hipSt
   if (lds > ctx->lds_max)
     return fail(ctx, MCRT_EINVAL, "tables need %zu bytes of LDS (limit %zu): fewer wavelengths, species or SED bins", lds, ctx->lds_max);
   HIPCHK(launch_transport(ctx->d_model, 1, ctx->fp64, o->record != 0, grid, block, lds, st));
+  if (o->mode != MCRT_BW_EPOCH) ctx->snap_stale = true;
   return MCRT_OK;
 }
 
@@ -1002,6 +1034,10 @@ extern "C" mcrt_status mcrt_run_packets(mcrt_ctx *ctx, uint64_t first, uint64_t 
       while (a < end) {
         uint64_t b = (a / P + 1) * P;
         if (b > end) b = end;
+        if (ctx->snap_stale) {
+          HIPCHK(fill<uint8_t>(ctx->d_dirty, (uint8_t)1, ctx->ncell, st));
+          ctx->snap_stale = false;
+        }
         HIPCHK(launch_epoch_snapshot(ctx->d_model, st));
         s = set_range(ctx, a, b - a, st);
         if (s) return s;
@@ -1071,6 +1107,10 @@ extern "C" mcrt_status mcrt_run_pah(mcrt_ctx *ctx, uint64_t seed, const mcrt_run
       for (uint64_t a = 0; a < total;) {
         uint64_t b = (a / P + 1) * P;
         if (b > total) b = total;
+        if (ctx->snap_stale) {
+          HIPCHK(fill<uint8_t>(ctx->d_dirty, (uint8_t)1, ctx->ncell, st));
+          ctx->snap_stale = false;
+        }
         HIPCHK(launch_epoch_snapshot(ctx->d_model, st));
         s = set_range(ctx, a, b - a, st);
         if (s) return s;
@@ -1564,6 +1604,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   }
   hipError_t le = hipSuccess;
   if (cs == MCRT_OK) le = launch_transport(ctx->d_batch, n_models, ctx->fp64, false, grid, block, lds, cs_);
+  for (int m = 0; m < n_models; ++m) models[m]->snap_stale = true;
   for (int m = 0; m < n_models && cs == MCRT_OK && le == hipSuccess; ++m)
     le = launch_finalize_T(ctx->d_batch + m, ctx->fp64, models[m]->d_T, nullptr, cs_);
   hipError_t ce = hipStreamEndCapture(cs_, &graph);

@@ -83,6 +83,8 @@ struct ModelDev {
   double ssca_unit;           // scattering sums are stored in these units (erg/s/sr)
   uint64_t max_int, first, n, id_base, rec_first, seed, ncell;
   const void *rho;            // [cells] context precision
+  const void *rho_b;          // the same density in 4x4x4 bricks (brick_index), read by the walk
+  int32_t nbx, nby, nbz;      // bricks per axis
   const double *tab;          // packed double table
   const void *rtab;           // packed R table
   const int32_t *imgmap;      // [nl] -> imaged index or -1
@@ -103,6 +105,17 @@ struct ModelDev {
   unsigned long long *stats;  // [NSTAT]
   double kv[MAX_VIEW][3];     // view directions toward the observer
 };
+
+// ---------------------------------------------------------------- bricks
+// The voxel walk reads the density from a copy stored in 4x4x4 bricks of 64
+// cells (256 B in FP32), x fastest inside a brick and bricks x-fastest. A
+// step to a neighbouring cell stays in its brick three times in four, so
+// the gathers of one packet share cache lines far more often than in the
+// x-fastest layout, where every y or z step lands on a new line.
+__host__ __device__ __forceinline__ int64_t brick_index(int cx, int cy, int cz, int nbx, int nby) {
+  return ((((int64_t)(cz >> 2) * nby + (cy >> 2)) * nbx + (cx >> 2)) << 6) +
+         (((cz & 3) << 4) | ((cy & 3) << 2) | (cx & 3));
+}
 
 // ---------------------------------------------------------------- RNG
 // Philox4x32-10 (Salmon et al. 2011); key = seed, counter = (draw block,
@@ -145,8 +158,11 @@ __device__ __forceinline__ uint32_t rng_u32(Rng &r) {
     r.b0 = c0; r.b1 = c1; r.b2 = c2; r.b3 = c3;
     r.blk = b;
   }
-  uint32_t w = r.d & 3u;
-  uint32_t x = (w == 0) ? r.b0 : (w == 1) ? r.b1 : (w == 2) ? r.b2 : r.b3;
+  // word d & 3 of the block, chosen with masks: a select chain between the
+  // members would be turned into an indexed load and move r to scratch
+  const uint32_t w = r.d & 3u;
+  const uint32_t x = (r.b0 & (0u - (uint32_t)(w == 0u))) | (r.b1 & (0u - (uint32_t)(w == 1u))) |
+                     (r.b2 & (0u - (uint32_t)(w == 2u))) | (r.b3 & (0u - (uint32_t)(w == 3u)));
   r.d++;
   return x;
 }
@@ -156,6 +172,19 @@ __device__ __forceinline__ uint32_t rng_u32(Rng &r) {
 // pick source wavelengths are taken in FP64 in both precisions).
 template <typename R> __device__ __forceinline__ R rng_u(Rng &r) {
   return ((R)(rng_u32(r) >> 8) + (R)0.5) * (R)(1.0 / 16777216.0);
+}
+
+// ------------------------------------------------ global-memory access
+// Device buffers reached through ModelDev are generic pointers to the
+// compiler, which would emit flat_* instructions; flat loads also count
+// against LDS waits. These helpers access them as global memory.
+#define MCRT_AS_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ T gld(const T *p) {
+  return *(const MCRT_AS_GLOBAL T *)p;
+}
+template <typename T> __device__ __forceinline__ T gatomic_add(T *p, T v) {
+  return __hip_atomic_fetch_add((MCRT_AS_GLOBAL T *)p, v, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- math
@@ -221,22 +250,27 @@ __device__ inline double phi_dphi(const double *wk, const double *hnu, const dou
 
 // Eq. 4 inverted in FP64: table bracket in (ln T, ln Phi), then safeguarded
 // Newton on ln Phi(ln T) until |d ln T| < 1e-14. rhs <= 0 -> 0; rhs at or
-// above Phi(T_MAX) -> T_MAX with *clamped set.
-__device__ inline double invert_T(const double *tab, const TabOff &o, int nl, int s, double rhs,
-                                  bool *clamped, double u_start = 0.0, bool have_start = false) {
-  if (!(rhs > 0.0)) return 0.0;
-  const double *lp = tab + o.logphi + s * NT_TAB;
-  const double *wk = tab + o.wk + s * nl;
-  const double *hnu = tab + o.hnu;
-  const double *a = tab + o.a;
+// above Phi(T_MAX) -> T_MAX, flagged as clamped. Kept out of line: its
+// FP64 loops would otherwise add their registers to every caller.
+struct TInv {
+  double T;
+  int clamped;
+};
+
+static __device__ __noinline__ TInv invert_T_core(const double *lp, const double *wk,
+                                                  const double *hnu, const double *a, int nl,
+                                                  double rhs, double u_start, int have_start) {
+  TInv r{0.0, 0};
+  if (!(rhs > 0.0)) return r;
   const double lt0 = log(T_TAB_MIN), dlt = (log(T_MAX) - lt0) / (NT_TAB - 1);
   double lr = log(rhs);
   double dphi;
   if (!(lr < lp[NT_TAB - 1])) {
     double ph = phi_dphi(wk, hnu, a, nl, T_MAX, &dphi);
     if (ph <= rhs) {
-      *clamped = true;
-      return T_MAX;
+      r.T = T_MAX;
+      r.clamped = 1;
+      return r;
     }
   }
   double ulo, uhi, u;
@@ -274,7 +308,17 @@ __device__ inline double invert_T(const double *tab, const TabOff &o, int nl, in
     u = un;
     if (fabs(du) < 1e-14) break;
   }
-  return exp(u);
+  r.T = exp(u);
+  return r;
+}
+
+__device__ inline double invert_T(const double *tab, const TabOff &o, int nl, int s, double rhs,
+                                  bool *clamped, double u_start = 0.0, bool have_start = false) {
+  if (!(rhs > 0.0)) return 0.0;
+  TInv r = invert_T_core(tab + o.logphi + s * NT_TAB, tab + o.wk + s * nl, tab + o.hnu,
+                         tab + o.a, nl, rhs, u_start, have_start ? 1 : 0);
+  if (r.clamped) *clamped = true;
+  return r.T;
 }
 
 // Eq. 4 by table: ln T as a cubic Hermite function of ln Phi on a uniform
@@ -343,7 +387,7 @@ __device__ inline double mrw_dsurv(double y) {
 }
 
 // y in (0,1) with S(y) = u (FP64): Newton within a shrinking bracket.
-__device__ inline double mrw_solve(double u) {
+static __device__ __noinline__ double mrw_solve(double u) {
   double lo = 0.0, hi = 1.0, y = 0.5 * u;
   if (!(y > 0.0)) y = 1e-300;
   for (int it = 0; it < 200; ++it) {

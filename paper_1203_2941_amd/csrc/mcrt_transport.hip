@@ -20,6 +20,7 @@ struct Pkt {
   R p[3], d[3];
   int c[3];
   int j, status;
+  R rho;  // density of cell c after a flight that ends in an interaction
   uint64_t pid;
   Rng rng;
   uint32_t n_cross, n_scat, n_abs, n_mrw, n_lucy, n_int;
@@ -38,30 +39,14 @@ struct Ctx {
   int64_t nc;
   unsigned long long *st;  // LDS block counters [NSTAT]
   R rho_thin;              // FP32 walk: lucy_tau / (max kext dcell), 0 when Lucy is off
+  R og[3], dc;             // grid origin and cell size in the walk precision
+  int nx, ny, nz;
+  const R *rho_b;          // bricked density (brick_index)
+  int nbx, nby;
 };
 
 __device__ __forceinline__ void stat_add(unsigned long long *st, int i, unsigned long long v) {
   atomicAdd(&st[i], v);
-}
-
-// Distance along d from p0 to the exit plane of cell c on axis k. The FP64
-// walk divides (the same rounding as a plain evaluation); the FP32 walk
-// multiplies by a per-flight reciprocal.
-template <typename R>
-__device__ __forceinline__ R plane_t(const ModelDev &M, R p0, R d, int c, int k) {
-  if (d > (R)0) return ((R)M.origin[k] + (R)(c + 1) * (R)M.dcell - p0) / d;
-  if (d < (R)0) return ((R)M.origin[k] + (R)c * (R)M.dcell - p0) / d;
-  return m_inf<R>();
-}
-template <typename R>
-__device__ __forceinline__ R plane_r(const ModelDev &M, R p0, R d, R inv, int c, int k) {
-  if constexpr (sizeof(R) == 8) {
-    return plane_t<R>(M, p0, d, c, k);
-  } else {
-    if (d > (R)0) return ((R)M.origin[k] + (R)(c + 1) * (R)M.dcell - p0) * inv;
-    if (d < (R)0) return ((R)M.origin[k] + (R)c * (R)M.dcell - p0) * inv;
-    return m_inf<R>();
-  }
 }
 
 template <typename R>
@@ -132,14 +117,39 @@ __device__ __forceinline__ int pick_asc(const T *f, int stride, int n, R u, doub
 }
 
 // Inverse CDF over ascending frequency (descending index) of a spectrum
-// given by a functor; evaluated twice so that no per-lane array is needed.
+// given by a functor: the first j (from n-1 down) whose running sum reaches
+// u times the total, 0 if none does. The running sums are the plain
+// sequential ones. A first pass records them at the start of each of NB
+// chunks; the second pass re-walks only the chunk that holds the answer,
+// from its recorded start, so it adds the same terms in the same order.
+// Lanes then differ by at most one chunk of work instead of a whole pass.
 template <typename R, bool REC, typename F>
 __device__ __forceinline__ int pick_desc_fn(int n, R u, double &mm, F f) {
-  R tot = (R)0;
-  for (int j = n - 1; j >= 0; --j) tot += f(j);
-  R target = u * tot, c = (R)0;
-  for (int j = n - 1; j >= 0; --j) {
-    R prev = c;
+  constexpr int NB = 8;
+  const int ch = (n + NB - 1) / NB;
+  R cb[NB + 1];
+  R c = (R)0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    cb[b] = c;
+    const int hi = n - 1 - b * ch;
+    const int lo = hi - ch + 1 > 0 ? hi - ch + 1 : 0;
+    for (int j = hi; j >= lo; --j) c += f(j);
+  }
+  cb[NB] = c;
+  const R tot = c, target = u * tot;
+  // first chunk whose end sum reaches the target (the last one otherwise)
+  int bs = NB - 1;
+  R c0 = cb[NB - 1];
+#pragma unroll
+  for (int b = NB - 2; b >= 0; --b) {
+    if (cb[b + 1] >= target) { bs = b; c0 = cb[b]; }
+  }
+  const int hi = n - 1 - bs * ch;
+  const int lo = hi - ch + 1 > 0 ? hi - ch + 1 : 0;
+  c = c0;
+  for (int j = hi; j >= lo; --j) {
+    const R prev = c;
     c += f(j);
     if (c >= target) {
       if (REC && tot > (R)0) {
@@ -205,9 +215,9 @@ __device__ __forceinline__ void lucy_deposit(Ctx<R> &X, Pkt<R> &P, int64_t c, R 
   for (int s = 0; s < M.ns; ++s) {
     R f = X.rt[X.o.r_lucy + s * nl + j];
     if (f == (R)0) continue;
-    atomicAdd(&M.epath[(int64_t)s * X.nc + c], (double)((R)M.xi * f * em));
+    gatomic_add(&M.epath[(int64_t)s * X.nc + c], (double)((R)M.xi * f * em));
   }
-  M.dirty[c] = 1;
+  if (M.mode == M_BW_EPOCH) M.dirty[c] = 1;
   P.n_lucy++;
 }
 
@@ -215,142 +225,225 @@ __device__ __forceinline__ void lucy_deposit(Ctx<R> &X, Pkt<R> &P, int64_t c, R 
 // on the density, only where the flight stops does, so each lane walks K
 // cells ahead, issues K independent loads, then consumes the segments in
 // order (same arithmetic and order as a one-cell-at-a-time walk).
-template <typename R> struct Ahead { static constexpr int K = 4; };
+template <typename R> struct Ahead { static constexpr int K = 8; };
 template <> struct Ahead<double> { static constexpr int K = 2; };
 
-// State of a flight in progress (kept per lane across event cycles).
+// State of a flight in progress (kept per lane across event cycles). The
+// distance from the flight origin p0 to the next face on axis a is worked
+// out afresh from that face's index e_a (an exact integer held in R) at
+// every crossing, never accumulated:
+//   FP64: ((origin_a + e_a dcell) - p0_a) / d_a   (as a plain evaluation)
+//   FP32: fma(e_a, dcell, origin_a - p0_a) * (1 / d_a)
+// An axis with d_a = 0 keeps distance +inf and is never stepped.
 template <typename R>
 struct Flight {
-  R tx, ty, tz, t, tau, tstar, kx, ix, iy, iz;
-  int64_t c;
+  R tx, ty, tz;  // distance to the next face per axis
+  R ex, ey, ez;  // index of that face
+  R qx, qy, qz;  // FP32: origin - p0 (unused in FP64)
+  R ix, iy, iz;  // FP32: 1 / d; FP64: d
+  R t, tau, tstar, kx;
   int cx, cy, cz;
   bool out;
 };
 
 template <typename R>
+__device__ __forceinline__ R face_t(const Ctx<R> &X, R e, R q, R og, R p0, R id) {
+  if constexpr (sizeof(R) == 8) return ((og + e * X.dc) - p0) / id;
+  else return __builtin_fmaf(e, X.dc, q) * id;
+}
+
+template <typename R>
+__device__ __forceinline__ void setup_axis(const Ctx<R> &X, int c, R p, R d, R og, R &e, R &q,
+                                           R &id, R &t) {
+  e = (R)(c + (d > (R)0 ? 1 : 0));
+  q = og - p;
+  id = (sizeof(R) == 8) ? d : (R)1 / d;
+  t = (d != (R)0) ? face_t<R>(X, e, q, og, p, id) : m_inf<R>();
+}
+
+template <typename R>
 __device__ __forceinline__ void flight_setup(const Ctx<R> &X, const Pkt<R> &P, Flight<R> &F,
                                              R tau_star) {
-  const ModelDev &M = *X.M;
   F.cx = P.c[0]; F.cy = P.c[1]; F.cz = P.c[2];
-  F.ix = (R)1 / P.d[0]; F.iy = (R)1 / P.d[1]; F.iz = (R)1 / P.d[2];
-  F.tx = plane_r<R>(M, P.p[0], P.d[0], F.ix, F.cx, 0);
-  F.ty = plane_r<R>(M, P.p[1], P.d[1], F.iy, F.cy, 1);
-  F.tz = plane_r<R>(M, P.p[2], P.d[2], F.iz, F.cz, 2);
+  setup_axis<R>(X, P.c[0], P.p[0], P.d[0], X.og[0], F.ex, F.qx, F.ix, F.tx);
+  setup_axis<R>(X, P.c[1], P.p[1], P.d[1], X.og[1], F.ey, F.qy, F.iy, F.ty);
+  setup_axis<R>(X, P.c[2], P.p[2], P.d[2], X.og[2], F.ez, F.qz, F.iz, F.tz);
   F.kx = X.rt[X.o.r_kext + P.j];
   F.t = (R)0;
   F.tau = (R)0;
   F.tstar = tau_star;
-  F.c = ((int64_t)F.cz * M.ny + F.cy) * M.nx + F.cx;
   F.out = false;
 }
 
 // One batch of up to K cell crossings of the flight in F, starting at the
-// flight origin P.p. Returns 0 to continue, 1 at an interaction (P.p and
-// P.c set to the interaction point), 2 on escape (P.p at the exit point).
+// flight origin P.p. Returns 0 to continue, 1 at an interaction (P.p, P.c
+// and P.rho set to the interaction point and its cell), 2 on escape (P.p
+// at the exit point). Each crossing leaves by the nearest face, ties going
+// to x, then y, then z; the step is written with selects so that lanes
+// leaving by different axes do not diverge.
 template <typename R, bool REC>
 __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   constexpr int K = Ahead<R>::K;
-  const ModelDev &M = *X.M;
   const R p0x = P.p[0], p0y = P.p[1], p0z = P.p[2];
   const R dx = P.d[0], dy = P.d[1], dz = P.d[2];
   const int sx = dx > (R)0 ? 1 : -1, sy = dy > (R)0 ? 1 : -1, sz = dz > (R)0 ? 1 : -1;
-  const int64_t nxy = (int64_t)M.nx * M.ny;
-  const R kx = F.kx, tau_star = F.tstar;
+  // the flight state is worked on in locals (selects between struct members
+  // would otherwise become address arithmetic and push the struct to scratch)
+  R tx = F.tx, ty = F.ty, tz = F.tz, ex = F.ex, ey = F.ey, ez = F.ez;
+  const R qx = F.qx, qy = F.qy, qz = F.qz, ix = F.ix, iy = F.iy, iz = F.iz;
+  const R ogx = X.og[0], ogy = X.og[1], ogz = X.og[2];
+  R t = F.t, tau = F.tau;
+  const R tau_star = F.tstar, kx = F.kx;
+  int cx = F.cx, cy = F.cy, cz = F.cz;
+  bool out = F.out;
   int64_t cs[K];
   R ts[K], ls[K], rh[K];
+  uint32_t mv = 0;  // exit axis of step k in bits 2k..2k+1
   int ns = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    if (!F.out) {
-      int a = 0;
-      R tn = F.tx;
-      if (F.ty < tn) { a = 1; tn = F.ty; }
-      if (F.tz < tn) { a = 2; tn = F.tz; }
+    if (!out) {
+      const bool b1 = ty < tx;
+      const R t01 = b1 ? ty : tx;
+      const bool b2 = tz < t01;
+      const R tn = b2 ? tz : t01;
       if (REC) {
-        R t2 = (a == 0) ? (F.ty < F.tz ? F.ty : F.tz) : (a == 1) ? (F.tx < F.tz ? F.tx : F.tz)
-                                                               : (F.tx < F.ty ? F.tx : F.ty);
+        R t2 = b2 ? (b1 ? (tx < ty ? tx : ty) : (ty < tx ? ty : tx))
+                  : (b1 ? (tx < tz ? tx : tz) : (ty < tz ? ty : tz));
         if (t2 < m_inf<R>() && t2 > (R)0) upd_margin(P.mm, (double)((t2 - tn) / t2));
       }
-      R ell = tn - F.t;
+      R ell = tn - t;
       if (ell < (R)0) ell = (R)0;
-      cs[k] = F.c;
-      ts[k] = F.t;
+      cs[k] = brick_index(cx, cy, cz, X.nbx, X.nby);
+      ts[k] = t;
       ls[k] = ell;
       ns = k + 1;
-      if (tn > F.t) F.t = tn;
-      if (a == 0) {
-        F.cx += sx;
-        if (F.cx < 0 || F.cx >= M.nx) F.out = true;
-        else { F.c += sx; F.tx = plane_r<R>(M, p0x, dx, F.ix, F.cx, 0); }
-      } else if (a == 1) {
-        F.cy += sy;
-        if (F.cy < 0 || F.cy >= M.ny) F.out = true;
-        else { F.c += (int64_t)sy * M.nx; F.ty = plane_r<R>(M, p0y, dy, F.iy, F.cy, 1); }
-      } else {
-        F.cz += sz;
-        if (F.cz < 0 || F.cz >= M.nz) F.out = true;
-        else { F.c += (int64_t)sz * nxy; F.tz = plane_r<R>(M, p0z, dz, F.iz, F.cz, 2); }
-      }
+      if (tn > t) t = tn;
+      const bool mx = !(b1 || b2), my = b1 && !b2;
+      mv |= (uint32_t)(b2 ? 2 : (b1 ? 1 : 0)) << (2 * k);
+      cx += mx ? sx : 0;
+      cy += my ? sy : 0;
+      cz += b2 ? sz : 0;
+      out = (unsigned)cx >= (unsigned)X.nx || (unsigned)cy >= (unsigned)X.ny ||
+            (unsigned)cz >= (unsigned)X.nz;
+      const R e = (b2 ? ez : (b1 ? ey : ex)) + (R)(b2 ? sz : (b1 ? sy : sx));
+      const R tf = face_t<R>(X, e, b2 ? qz : (b1 ? qy : qx), b2 ? ogz : (b1 ? ogy : ogx),
+                             b2 ? p0z : (b1 ? p0y : p0x), b2 ? iz : (b1 ? iy : ix));
+      ex = mx ? e : ex; tx = mx ? tf : tx;
+      ey = my ? e : ey; ty = my ? tf : ty;
+      ez = b2 ? e : ez; tz = b2 ? tf : tz;
     }
   }
+  F.tx = tx; F.ty = ty; F.tz = tz; F.ex = ex; F.ey = ey; F.ez = ez;
+  F.t = t; F.cx = cx; F.cy = cy; F.cz = cz; F.out = out;
 #pragma unroll
-  for (int k = 0; k < K; ++k) rh[k] = (k < ns) ? X.rho[cs[k]] : (R)0;
+  for (int k = 0; k < K; ++k) rh[k] = (k < ns) ? gld(X.rho_b + cs[k]) : (R)0;
+  // cell of step k: the current cell with the moves of steps k .. ns-1 undone
+  auto cell_of = [&](int k, int &ux, int &uy, int &uz) {
+    ux = cx; uy = cy; uz = cz;
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+      if (j >= k && j < ns) {
+        const uint32_t a = (mv >> (2 * j)) & 3u;
+        ux -= (a == 0) ? sx : 0;
+        uy -= (a == 1) ? sy : 0;
+        uz -= (a == 2) ? sz : 0;
+      }
+    }
+  };
+  auto lin = [&](int ux, int uy, int uz) { return ((int64_t)uz * X.ny + uy) * X.nx + ux; };
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     if (k < ns) {
-      R rho = rh[k];
-      R dtau = rho * kx * ls[k];
-      bool thin = is_thin(X, rho);
-      if (REC) upd_margin(P.mm, (double)(m_fabs(F.tau + dtau - tau_star) / tau_star));
-      if (F.tau + dtau > tau_star) {
-        R tint = ts[k] + (tau_star - F.tau) / (rho * kx);
-        if (thin) lucy_deposit(X, P, cs[k], rho, tint - ts[k]);
+      const R rho = rh[k];
+      const R dtau = rho * kx * ls[k];
+      const bool thin = is_thin(X, rho);
+      if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tau_star) / tau_star));
+      if (tau + dtau > tau_star) {
+        const R tint = ts[k] + (tau_star - tau) / (rho * kx);
+        int ux, uy, uz;
+        cell_of(k, ux, uy, uz);
+        if (thin) lucy_deposit(X, P, lin(ux, uy, uz), rho, tint - ts[k]);
         P.p[0] = p0x + tint * dx;
         P.p[1] = p0y + tint * dy;
         P.p[2] = p0z + tint * dz;
-        const int64_t ck = cs[k];
-        P.c[2] = (int)(ck / nxy);
-        P.c[1] = (int)((ck / M.nx) % M.ny);
-        P.c[0] = (int)(ck % M.nx);
+        P.c[0] = ux; P.c[1] = uy; P.c[2] = uz;
+        P.rho = rho;
+        F.tau = tau;
         return 1;
       }
-      if (thin) lucy_deposit(X, P, cs[k], rho, ls[k]);
-      F.tau += dtau;
+      if (thin) {
+        int ux, uy, uz;
+        cell_of(k, ux, uy, uz);
+        lucy_deposit(X, P, lin(ux, uy, uz), rho, ls[k]);
+      }
+      tau += dtau;
       P.n_cross++;
     }
   }
-  if (!F.out) return 0;
-  P.p[0] = p0x + F.t * dx;
-  P.p[1] = p0y + F.t * dy;
-  P.p[2] = p0z + F.t * dz;
-  P.c[0] = F.cx; P.c[1] = F.cy; P.c[2] = F.cz;
+  F.tau = tau;
+  if (!out) return 0;
+  P.p[0] = p0x + t * dx;
+  P.p[1] = p0y + t * dy;
+  P.p[2] = p0z + t * dz;
+  P.c[0] = cx; P.c[1] = cy; P.c[2] = cz;
   return 2;
 }
 
-template <typename R>
-__device__ double rosseland(const Ctx<R> &X, double T) {
-  const ModelDev &M = *X.M;
+// Rosseland mean of the mixture opacity at T (sect. 3.2). The FP64 means
+// and the MRW spectrum below are kept out of line so that their loops do
+// not add registers to the whole transport kernel.
+static __device__ __noinline__ double rosseland_mean(const double *w, const double *hnu,
+                                                     const double *a, const double *kext, int nl,
+                                                     double T) {
   double num = 0.0, den = 0.0;
-  for (int j = M.nl - 1; j >= 0; --j) {
-    double ke = X.dt[X.o.kext + j];
+  for (int j = nl - 1; j >= 0; --j) {
+    double ke = kext[j];
     if (!(ke > 0.0)) return 0.0;
-    double db = X.dt[X.o.w + j] * dplanck_d(X.dt[X.o.hnu + j], X.dt[X.o.a + j], T);
+    double db = w[j] * dplanck_d(hnu[j], a[j], T);
     num += db;
     den += db / ke;
   }
   return (den > 0.0) ? num / den : 0.0;
 }
 
-template <typename R>
-__device__ double planck_mean(const Ctx<R> &X, int s, double T) {
-  const ModelDev &M = *X.M;
+// Planck mean of one species' absorption opacity at T.
+static __device__ __noinline__ double planck_mean(const double *w, const double *hnu,
+                                                  const double *a, const double *kabs, int nl,
+                                                  double T) {
   double num = 0.0, den = 0.0;
-  for (int j = M.nl - 1; j >= 0; --j) {
-    double b = X.dt[X.o.w + j] * planck_d(X.dt[X.o.hnu + j], X.dt[X.o.a + j], T);
-    num += b * X.dt[X.o.kabs + s * M.nl + j];
+  for (int j = nl - 1; j >= 0; --j) {
+    double b = w[j] * planck_d(hnu[j], a[j], T);
+    num += b * kabs[j];
     den += b;
   }
   return (den > 0.0) ? num / den : 0.0;
+}
+
+// Thermal emission wavelength after an MRW step: inverse CDF of
+// sum_s w_j f_s kabs_s,j B_j(T_s) over the thermal species.
+struct PickOut {
+  int j;
+  double mm;
+};
+template <bool REC>
+static __device__ __noinline__ PickOut mrw_pick(const double *wfk, const double *hnu,
+                                                const double *a, int nl, int ns, int pah,
+                                                double T0, double T1, double T2, double T3,
+                                                double u) {
+  PickOut r;
+  r.mm = 1e300;
+  r.j = pick_desc_fn<double, REC>(nl, u, r.mm, [&](int j) {
+    double f = 0.0;
+#pragma unroll
+    for (int s = 0; s < MAX_NS; ++s) {
+      if (s >= ns || s == pah) continue;
+      const double T = s == 0 ? T0 : (s == 1 ? T1 : (s == 2 ? T2 : T3));
+      f += wfk[s * nl + j] * planck_d(hnu[j], a[j], T);
+    }
+    return f;
+  });
+  return r;
 }
 
 __device__ __forceinline__ int first_thermal(const ModelDev &M) {
@@ -366,7 +459,7 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
   const ModelDev &M = *X.M;
   if (!(M.mrw_tau > 0.0)) return false;
   int64_t c = ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0];
-  double rho = (double)X.rho[c];
+  double rho = (double)gld(X.rho + c);
   if (!(rho > 0.0)) return false;
   if (!(rho * M.kext_max * M.dcell > M.mrw_tau)) return false;
   int s0 = first_thermal(M);
@@ -379,7 +472,7 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
     int k = (xk >= 0.0 && xk < (double)(NT_TAB - 1)) ? (int)xk : NT_TAB - 1;
     if (!(rho * X.dt[X.o.krmax + k] * M.dcell > M.mrw_tau)) return false;
   }
-  double kr = rosseland(X, T0);
+  double kr = rosseland_mean(X.dt + X.o.w, X.dt + X.o.hnu, X.dt + X.o.a, X.dt + X.o.kext, M.nl, T0);
   double taur = rho * kr * M.dcell;
   if (REC) upd_margin(P.mm, fabs(taur - M.mrw_tau) / M.mrw_tau);
   if (!(taur > M.mrw_tau)) return false;
@@ -411,23 +504,21 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.p[k] = (R)((double)P.p[k] + Rs * ds[k]);
   const int nl = M.nl;
-  double Ts[MAX_NS];
-  for (int s = 0; s < M.ns; ++s) {
-    Ts[s] = 0.0;
-    if (s == M.pah) continue;
-    Ts[s] = mode_T(X, s, c, rho);
-    double kp = planck_mean(X, s, Ts[s]);
-    atomicAdd(&M.epath[(int64_t)s * X.nc + c], M.xi * rho * X.dt[X.o.frac + s] * kp * ell);
+  double Ts[MAX_NS] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < MAX_NS; ++s) {
+    if (s >= M.ns || s == M.pah) continue;
+    const double T = mode_T(X, s, c, rho);
+    Ts[s] = T;
+    double kp = planck_mean(X.dt + X.o.w, X.dt + X.o.hnu, X.dt + X.o.a, X.dt + X.o.kabs + s * nl,
+                            nl, T);
+    gatomic_add(&M.epath[(int64_t)s * X.nc + c], M.xi * rho * X.dt[X.o.frac + s] * kp * ell);
   }
-  M.dirty[c] = 1;
-  P.j = pick_desc_fn<double, REC>(nl, ul, P.mm, [&](int j) {
-    double f = 0.0;
-    for (int s = 0; s < M.ns; ++s) {
-      if (s == M.pah) continue;
-      f += X.dt[X.o.wfk + s * nl + j] * planck_d(X.dt[X.o.hnu + j], X.dt[X.o.a + j], Ts[s]);
-    }
-    return f;
-  });
+  if (M.mode == M_BW_EPOCH) M.dirty[c] = 1;
+  const PickOut pk = mrw_pick<REC>(X.dt + X.o.wfk, X.dt + X.o.hnu, X.dt + X.o.a, nl, M.ns, M.pah,
+                                   Ts[0], Ts[1], Ts[2], Ts[3], ul);
+  P.j = pk.j;
+  if (REC) upd_margin(P.mm, pk.mm);
   iso_dir<R>(uph, umu, P.d);
   P.n_mrw++;
   stat_add(X.st, 7, 1ull);
@@ -435,9 +526,8 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
 }
 
 template <typename R>
-__device__ __forceinline__ int pah_row(const Ctx<R> &X, int64_t c) {
+__device__ __forceinline__ int pah_row(const Ctx<R> &X, int64_t c, double rho) {
   const ModelDev &M = *X.M;
-  double rho = (double)X.rho[c];
   double q = (double)M.kpah[c] * M.xi / (4.0 * PI_D * X.dt[X.o.frac + M.pah] * rho * M.V);
   int r = 0;
   while (r < M.nrows - 1 && q >= X.dt[X.o.pahe + r]) r++;
@@ -469,22 +559,21 @@ __device__ __forceinline__ int pick_thermal(const Ctx<R> &X, int s, double T, R 
     const R *wk = X.rt + X.o.r_wk + s * nl;
     const R *hnu = X.rt + X.o.r_hnu;
     const R *a = X.rt + X.o.r_a;
-    const R kT = (R)(K_BO * T);
-    const R Tr = (R)T;
+    const R rkT = (R)(1.0 / (K_BO * T));
     const R cut = x_cut<R>();
-    // e^x - 1 from the hardware exponential, with a 3-term series below 0.03
+    // e^x - 1 from the hardware exponential, with a 3-term series below 0.03;
+    // weights drop the common factor 1/T of dB/dT (the CDF is normalised)
     auto em1 = [](R x) { return x < (R)0.03 ? x * ((R)1 + x * ((R)0.5 + x * (R)(1.0 / 6.0))) : __expf(x) - (R)1; };
     if (M.mode == M_FROZEN)
       return pick_desc_fn<R, REC>(nl, u, mm, [&](int j) {
-        R x = hnu[j] / kT;
-        return x > cut ? (R)0 : wk[j] * (a[j] / em1(x));
+        R x = hnu[j] * rkT;
+        return x > cut ? (R)0 : wk[j] * a[j] * __builtin_amdgcn_rcpf(em1(x));
       });
     return pick_desc_fn<R, REC>(nl, u, mm, [&](int j) {
-      R x = hnu[j] / kT;
+      R x = hnu[j] * rkT;
       if (x > cut) return (R)0;
-      R em = em1(x);
-      R B = a[j] / em;
-      return wk[j] * (B * (x / Tr) * ((R)1 + (R)1 / em));
+      R r = __builtin_amdgcn_rcpf(em1(x));
+      return wk[j] * a[j] * x * r * ((R)1 + r);
     });
   }
 }
@@ -556,7 +645,7 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
       P.c[k] = cc[k];
       P.p[k] = (R)M.origin[k] + ((R)cc[k] + u3[k]) * (R)M.dcell;
     }
-    P.j = pick_pah<R, REC>(X, pah_row(X, c), ul, P.mm);
+    P.j = pick_pah<R, REC>(X, pah_row(X, c, (double)gld(X.rho + c)), ul, P.mm);
     iso_dir<R>(uph, umu, P.d);
     return;
   }
@@ -614,7 +703,7 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
         R cb = P.d[0] * (R)M.kv[v][0] + P.d[1] * (R)M.kv[v][1] + P.d[2] * (R)M.kv[v][2];
         // sums kept in units of ssca_unit (the packet energy): erg/s sums overflow FP32
         R add = (R)(M.xi / M.ssca_unit) * hg_phase<R>(g, cb);
-        atomicAdd((R *)M.ssca + ((int64_t)v * M.nimg + q) * X.nc + c, add);
+        gatomic_add((R *)M.ssca + ((int64_t)v * M.nimg + q) * X.nc + c, add);
       }
     }
     rotate_dir<R>(P.d, mu, (R)2 * (R)PI_D * uph);
@@ -626,31 +715,31 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
     stat_add(X.st, 6, 1ull);
     if (s == M.pah) {
       if (M.pass != 2) {
-        atomicAdd(&M.kpah[c], 1u);
+        gatomic_add(&M.kpah[c], 1u);
         P.status = ST_PAH_STOP;
         return;
       }
       double ul = rng_u<double>(P.rng), uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
-      P.j = pick_pah<R, REC>(X, pah_row(X, c), ul, P.mm);
+      P.j = pick_pah<R, REC>(X, pah_row(X, c, (double)P.rho), ul, P.mm);
       iso_dir<R>(uph, umu, P.d);
     } else {
-      R rho = X.rho[c];
+      const R rho = P.rho;
       bool thin = is_thin(X, rho);
       int64_t qk = (int64_t)s * X.nc + c;
       double T;
       if (M.mode == M_BW_TICKET) {
         uint64_t kold = thin ? *(volatile uint64_t *)&M.k[qk]
-                             : (uint64_t)atomicAdd((unsigned long long *)&M.k[qk], 1ull);
+                             : gatomic_add(&M.k[qk], (uint64_t)1);
         double e = (double)kold * M.xi + *(volatile double *)&M.epath[qk];
         double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s] * (double)rho * M.V);
         bool cl = false;
         T = invert_T_fast(M.herm, X.dt, X.o, nl, s, rhs, &cl);
         if (cl) stat_add(X.st, 9, 1ull);
       } else {
-        if (!thin) atomicAdd((unsigned long long *)&M.k[qk], 1ull);
+        if (!thin) gatomic_add(&M.k[qk], (uint64_t)1);
         T = mode_T(X, s, c, (double)rho);
       }
-      M.dirty[c] = 1;
+      if (M.mode == M_BW_EPOCH) M.dirty[c] = 1;
       R ul = rng_u<R>(P.rng);
       double uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
       P.j = pick_thermal<R, REC>(X, s, T, ul, P.mm);
@@ -677,9 +766,11 @@ __device__ int pick_model(const ModelDev *models, int nmodels) {
   return -1;
 }
 
+// Two waves per SIMD: the interaction code keeps the register file at 256
+// per lane; the FP64 helpers it calls are out of line for that reason.
 template <typename R, bool REC>
-__global__ void __launch_bounds__(256) k_transport(const ModelDev *__restrict__ models,
-                                                    int nmodels) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_transport(const ModelDev *__restrict__ models, int nmodels) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int s_model;
   __shared__ unsigned long long s_stat[NSTAT];
@@ -697,6 +788,11 @@ __global__ void __launch_bounds__(256) k_transport(const ModelDev *__restrict__ 
     X.nc = (int64_t)M.ncell;
     X.rho = (const R *)M.rho;
     X.rho_thin = (M.lucy_tau > 0.0) ? (R)(M.lucy_tau / (M.kext_max * M.dcell)) : (R)0;
+    X.og[0] = (R)M.origin[0]; X.og[1] = (R)M.origin[1]; X.og[2] = (R)M.origin[2];
+    X.dc = (R)M.dcell;
+    X.nx = M.nx; X.ny = M.ny; X.nz = M.nz;
+    X.rho_b = (const R *)M.rho_b;
+    X.nbx = M.nbx; X.nby = M.nby;
     double *dt = (double *)lds_raw;
     R *rt = (R *)(dt + X.o.dtotal);
     int *im = (int *)(rt + X.o.r_total + (X.o.r_total & 1));
@@ -812,6 +908,35 @@ __global__ void k_epoch_snapshot(const ModelDev *__restrict__ md) {
     }
     M.dirty[i] = 0;
   }
+}
+
+// Copy of the density in 4x4x4 bricks for the walk (padding cells stay 0).
+template <typename R>
+__global__ void k_brick(const R *__restrict__ rho, R *__restrict__ rb, int nx, int ny, int nz,
+                        int nbx, int nby) {
+  const uint64_t n = (uint64_t)nx * ny * nz;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const int cx = (int)(i % (uint64_t)nx);
+    const uint64_t r = i / (uint64_t)nx;
+    const int cy = (int)(r % (uint64_t)ny), cz = (int)(r / (uint64_t)ny);
+    rb[brick_index(cx, cy, cz, nbx, nby)] = rho[i];
+  }
+}
+
+hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, int nz, int nbx,
+                        int nby, hipStream_t st) {
+  const uint64_t n = (uint64_t)nx * ny * nz;
+  const uint64_t nb = (n + 255) / 256;
+  const unsigned g = (unsigned)(nb < 65536 ? nb : 65536);
+  if (fp64)
+    hipLaunchKernelGGL(k_brick<double>, dim3(g), dim3(256), 0, st, (const double *)rho,
+                       (double *)rb, nx, ny, nz, nbx, nby);
+  else
+    hipLaunchKernelGGL(k_brick<float>, dim3(g), dim3(256), 0, st, (const float *)rho,
+                       (float *)rb, nx, ny, nz, nbx, nby);
+  return hipGetLastError();
 }
 
 // Eq. 4 for every cell and thermal species; optionally also writes E.
