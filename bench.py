@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--npix", type=int, default=512)
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--queue-depth", type=int, default=0,
+                    help="packets per wavefront queue (0: the library default)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one elementwise copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -88,7 +90,7 @@ def main():
     sed = torch.empty((len(views), len(idx)), dtype=torch.float64, device="cuda")
     grad = torch.empty(ctx.ncells, dtype=torch.float32, device="cuda")
     opts = dict(mode="bw_ticket", n_total=N, mrw_tau=50.0, mrw_gamma=2.0, lucy_tau=1e-2,
-                max_interactions=10_000_000, sed_theta_bins=10)
+                max_interactions=10_000_000, sed_theta_bins=10, queue_depth=args.queue_depth)
 
     def step(seed):
         ctx.reset()
@@ -131,6 +133,12 @@ def main():
     b_alg = np.mean([algorithmic_bytes(r[0], ns_th, len(views)) + algorithmic_bytes(r[1], ns_th, len(views))
                      for r in rec])
     t_k = t_tr + t_pah
+    # bytes per launch measured by the committed counter runs, reported only
+    # for the workload they were taken on and while the kernel is unchanged
+    traffic = None
+    if N == 100_000_000 and args.grid == 256:
+        from paper_1203_2941_amd import profiling
+        traffic = profiling.read_traffic()
     out = {
         "metric": METRIC,
         "value": N / (ms / 1e3),
@@ -168,7 +176,8 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": b_alg / t_k / HBM_PEAK,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (L2 <-> memory, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "launches_per_step": 2,
             "avg_launch_ms": t_k * 1e3 / 2,
             "algorithmic_bytes_per_step": b_alg,

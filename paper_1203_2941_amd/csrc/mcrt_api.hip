@@ -30,6 +30,10 @@ hipError_t launch_init_T(const ModelDev *d, bool fp64, double *T, hipStream_t st
 hipError_t launch_build_S(const ModelDev *d, bool fp64, void *S, hipStream_t st);
 hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, int nz, int nbx,
                         int nby, hipStream_t st);
+hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
+                           int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
+                           hipStream_t st);
+size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64);
 hipError_t launch_vox_torus(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
                             int ncl, const double *dC, double r_clump, double rho_cl,
                             double rho_int, double r_in, double r_out, double s1, void *rho,
@@ -73,6 +77,7 @@ struct mcrt_ctx {
   // tables
   std::vector<double> h_tab;
   double kext_max = 0.0, ltot = 0.0;
+  double kr_gmax = 0.0, phi_tmin = 0.0;  // MRW pre-test bounds (see build_tables)
   double *d_tab = nullptr;
   void *d_rtab = nullptr;
   int32_t *d_imgmap = nullptr;
@@ -93,7 +98,11 @@ struct mcrt_ctx {
   size_t ssca_cap = 0;
   void *d_rec = nullptr;
   uint64_t rec_cap = 0, rec_n = 0;
-  uint64_t *d_counter = nullptr;
+  WfCtl *d_ctl = nullptr;   // wavefront queue counters (ctl->emitted is the packet counter)
+  WfCtl *h_ctl = nullptr;   // pinned copy read between rounds
+  void *d_q = nullptr;      // the two packet queues
+  uint32_t qcap = 0;
+  QBuf q[2] = {};
   unsigned long long *d_stats = nullptr;
   ModelDev *d_model = nullptr;
   ModelDev h_model;
@@ -204,7 +213,8 @@ extern "C" mcrt_status mcrt_create(mcrt_ctx **out, int device, int precision) {
       hipEventCreate(&ctx->evf1) != hipSuccess || hipEventCreate(&ctx->eva0) != hipSuccess ||
       hipEventCreate(&ctx->eva1) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipMalloc((void **)&ctx->d_counter, sizeof(uint64_t)) != hipSuccess ||
+      hipMalloc((void **)&ctx->d_ctl, sizeof(WfCtl)) != hipSuccess ||
+      hipHostMalloc((void **)&ctx->h_ctl, sizeof(WfCtl), hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void **)&ctx->d_stats, sizeof(unsigned long long) * NSTAT) != hipSuccess ||
       hipMalloc((void **)&ctx->d_model, sizeof(ModelDev)) != hipSuccess ||
       hipMalloc((void **)&ctx->d_rt, sizeof(RtArgs)) != hipSuccess) {
@@ -222,12 +232,13 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   (void)hipDeviceSynchronize();
   void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_k, ctx->d_epath,
                 ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
-                ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_counter, ctx->d_stats,
+                ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_ctl, ctx->d_q, ctx->d_stats,
                 ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
                 ctx->d_temp};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
   if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -365,17 +376,26 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
   }
   for (int s = 0; s < ns; ++s) t[o.frac + s] = ctx->frac[s];
   ctx->ltot = 0.0;
+  // source and PAH emission spectra as running sums of w_j L_j taken from
+  // the highest index down (the order of the inverse-CDF walk), so that a
+  // binary search finds the same bin as the sequential walk
   for (int s = 0; s < ctx->nsrc; ++s) {
-    for (int j = 0; j < nl; ++j) {
-      t[o.lnu + s * nl + j] = ctx->src_lnu[s * nl + j];
-      t[o.srcf + s * nl + j] = w[j] * ctx->src_lnu[s * nl + j];
+    double c = 0.0;
+    for (int j = nl - 1; j >= 0; --j) {
+      c += w[j] * ctx->src_lnu[s * nl + j];
+      t[o.srccum + s * nl + j] = c;
     }
+    for (int j = 0; j < nl; ++j) t[o.lnu + s * nl + j] = ctx->src_lnu[s * nl + j];
     t[o.lum + s] = ctx->src_lum[s];
     for (int k = 0; k < 3; ++k) t[o.srcpos + 3 * s + k] = ctx->src_pos[3 * s + k];
     ctx->ltot += ctx->src_lum[s];
   }
   for (int r = 0; r < ctx->nrows; ++r) {
-    for (int j = 0; j < nl; ++j) t[o.pahw + r * nl + j] = w[j] * ctx->pah_emis[r * nl + j];
+    double c = 0.0;
+    for (int j = nl - 1; j >= 0; --j) {
+      c += w[j] * ctx->pah_emis[r * nl + j];
+      t[o.pahcum + r * nl + j] = c;
+    }
     if (r < ctx->nrows - 1) t[o.pahe + r] = ctx->pah_edges[r];
   }
   const double lt0 = std::log(T_TAB_MIN), dlt = (std::log(T_MAX) - lt0) / (NT_TAB - 1);
@@ -412,6 +432,12 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
       if (mx > gmax) gmax = mx;
     }
     t[o.krmax + NT_TAB - 1] = ctx->kext_max;  // outside the grid: the hard bound
+    ctx->kr_gmax = 1.02 * gmax;
+  }
+  {
+    int s0 = 0;
+    while (s0 < ns && s0 == ctx->pah) ++s0;
+    ctx->phi_tmin = s0 < ns ? std::exp(t[o.logphi + s0 * NT_TAB]) : 0.0;
   }
   // walk-precision table
   std::vector<double> r(o.r_total, 0.0);
@@ -846,6 +872,8 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.mrw_gamma = o ? o->mrw_gamma : 2.0;
   M.kext_max = ctx->kext_max;
   M.ssca_unit = ctx->ssca_unit;
+  M.kr_gmax = ctx->kr_gmax;
+  M.phi_tmin = ctx->phi_tmin;
   M.max_int = o ? o->max_interactions : 0;
   M.ncell = ctx->ncell;
   M.rho = ctx->d_rho;
@@ -861,7 +889,10 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.sed = ctx->d_sed;
   M.ssca = ctx->d_ssca;
   M.rec = nullptr;
-  M.counter = ctx->d_counter;
+  M.ctl = ctx->d_ctl;
+  M.counter = &ctx->d_ctl->emitted;  // address arithmetic only
+  for (int k = 0; k < 2; ++k) M.q[k] = ctx->q[k];
+  M.qcap = ctx->qcap;
   M.stats = ctx->d_stats;
   for (int v = 0; v < ctx->nview; ++v) {
     double th = ctx->views[2 * v] * PI_D / 180.0, ph = ctx->views[2 * v + 1] * PI_D / 180.0;
@@ -895,7 +926,12 @@ static void launch_shape(mcrt_ctx *ctx, const mcrt_run_opts *o, int &grid, int &
 __global__ void k_set_range(ModelDev *m, uint64_t first, uint64_t n) {
   m->first = first;
   m->n = n;
-  *m->counter = 0;
+  WfCtl *c = m->ctl;
+  c->emitted = 0;
+  c->first = 0;
+  c->n[0] = c->n[1] = 0u;
+  c->work[0] = c->work[1] = c->work[2] = 0u;
+  c->take = 0u;
 }
 
 static mcrt_status set_range(mcrt_ctx *ctx, uint64_t first, uint64_t n, hipStream_t st) {
@@ -904,13 +940,59 @@ static mcrt_status set_range(mcrt_ctx *ctx, uint64_t first, uint64_t n, hipStrea
   return MCRT_OK;
 }
 
-static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, hipStream_t st) {
-  int grid, block;
-  launch_shape(ctx, o, grid, block);
+// Wavefront queues: two queues of Q packets as structures of arrays,
+// carved from one allocation (256-byte aligned arrays).
+static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n) {
+  uint64_t want = (o && o->queue_depth > 0) ? (uint64_t)o->queue_depth : (1ull << 21);
+  if (want > (1ull << 26)) want = 1ull << 26;
+  uint64_t need = (n + 4095) / 4096 * 4096;
+  if (need < 4096) need = 4096;
+  const uint32_t Q = (uint32_t)(want < need ? want : need);
+  if (Q <= ctx->qcap && ctx->d_q) return MCRT_OK;
+  const size_t rs = rsize(ctx);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t per = 8 * al(Q * rs) + 4 * al(Q * 4) + al(Q * 8) + 7 * al(Q * 4) + al(Q * 8);
+  HIPCHK(dev_alloc(&ctx->d_q, 2 * per));
+  char *b = (char *)ctx->d_q;
+  for (int k = 0; k < 2; ++k) {
+    QBuf &q = ctx->q[k];
+    void **rv[8] = {&q.px, &q.py, &q.pz, &q.dx, &q.dy, &q.dz, &q.rho, &q.tau};
+    for (void **r : rv) { *r = b; b += al(Q * rs); }
+    int32_t **iv[4] = {&q.cx, &q.cy, &q.cz, &q.j};
+    for (int32_t **r : iv) { *r = (int32_t *)b; b += al(Q * 4); }
+    q.pid = (uint64_t *)b; b += al(Q * 8);
+    uint32_t **uv[7] = {&q.rngd, &q.nint, &q.ncross, &q.nscat, &q.nabs, &q.nmrw, &q.nlucy};
+    for (uint32_t **r : uv) { *r = (uint32_t *)b; b += al(Q * 4); }
+    q.mm = (double *)b; b += al(Q * 8);
+  }
+  ctx->qcap = Q;
+  return MCRT_OK;
+}
+
+// Transport of the n packets set by set_range: wavefront rounds until every
+// packet has been started and has ended. The host reads the queue counters
+// every few rounds to stop.
+static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n,
+                                    hipStream_t st) {
   size_t lds = transport_lds_bytes(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows, ctx->ntheta, ctx->fp64);
+  size_t lds_w = walk_lds_bytes(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows, ctx->ntheta, ctx->fp64);
   if (lds > ctx->lds_max)
     return fail(ctx, MCRT_EINVAL, "tables need %zu bytes of LDS (limit %zu): fewer wavelengths, species or SED bins", lds, ctx->lds_max);
-  HIPCHK(launch_transport(ctx->d_model, 1, ctx->fp64, o->record != 0, grid, block, lds, st));
+  const int gfull = ctx->num_cu * ((o && o->blocks_per_cu > 0) ? o->blocks_per_cu : 2);
+  const int gwalk = ctx->num_cu * ((o && o->walk_blocks_per_cu > 0) ? o->walk_blocks_per_cu : 4);
+  const bool rec = o->record != 0;
+  const int every = 4;
+  for (uint64_t r = 0;; ++r) {
+    const int fcur = (int)(r & 1);
+    HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w, st));
+    if ((r + 1) % every == 0) {
+      HIPCHK(hipMemcpyAsync(ctx->h_ctl, ctx->d_ctl, sizeof(WfCtl), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      const WfCtl &c = *ctx->h_ctl;
+      if (c.n[1 - fcur] == 0u && c.emitted >= n) break;
+    }
+    if (r > (1ull << 32)) return fail(ctx, MCRT_EDEVICE, "transport did not finish");
+  }
   if (o->mode != MCRT_BW_EPOCH) ctx->snap_stale = true;
   return MCRT_OK;
 }
@@ -1000,6 +1082,8 @@ extern "C" mcrt_status mcrt_run_packets(mcrt_ctx *ctx, uint64_t first, uint64_t 
     s = ensure_records(ctx, n);
     if (s) return s;
   }
+  s = ensure_queues(ctx, opts, opts->mode == MCRT_BW_EPOCH && opts->epoch_packets < n ? opts->epoch_packets : n);
+  if (s) return s;
   ModelDev &M = ctx->h_model;
   fill_model(ctx, M, opts, 0);
   M.seed = seed;
@@ -1017,7 +1101,7 @@ extern "C" mcrt_status mcrt_run_packets(mcrt_ctx *ctx, uint64_t first, uint64_t 
       HIPCHK(stage_copy(ctx, ctx->d_model, &M, sizeof M, st));
       s = set_range(ctx, first, n, st);
       if (s) return s;
-      s = transport_launch(ctx, opts, st);
+      s = transport_launch(ctx, opts, n, st);
       if (s) return s;
       HIPCHK(launch_finalize_T(ctx->d_model, ctx->fp64, ctx->d_T, nullptr, st));
     }
@@ -1026,7 +1110,7 @@ extern "C" mcrt_status mcrt_run_packets(mcrt_ctx *ctx, uint64_t first, uint64_t 
     if (opts->mode == MCRT_BW_TICKET) {
       s = set_range(ctx, first, n, st);
       if (s) return s;
-      s = transport_launch(ctx, opts, st);
+      s = transport_launch(ctx, opts, n, st);
       if (s) return s;
     } else {
       const uint64_t P = opts->epoch_packets;
@@ -1041,7 +1125,7 @@ extern "C" mcrt_status mcrt_run_packets(mcrt_ctx *ctx, uint64_t first, uint64_t 
         HIPCHK(launch_epoch_snapshot(ctx->d_model, st));
         s = set_range(ctx, a, b - a, st);
         if (s) return s;
-        s = transport_launch(ctx, opts, st);
+        s = transport_launch(ctx, opts, b - a, st);
         if (s) return s;
         a = b;
       }
@@ -1092,6 +1176,8 @@ extern "C" mcrt_status mcrt_run_pah(mcrt_ctx *ctx, uint64_t seed, const mcrt_run
     s = ensure_records(ctx, total);
     if (s) return s;
   }
+  s = ensure_queues(ctx, &o2, o2.mode == MCRT_BW_EPOCH && o2.epoch_packets < total ? o2.epoch_packets : total);
+  if (s) return s;
   ModelDev &M = ctx->h_model;
   fill_model(ctx, M, &o2, 0);
   M.seed = seed;
@@ -1114,14 +1200,14 @@ extern "C" mcrt_status mcrt_run_pah(mcrt_ctx *ctx, uint64_t seed, const mcrt_run
         HIPCHK(launch_epoch_snapshot(ctx->d_model, st));
         s = set_range(ctx, a, b - a, st);
         if (s) return s;
-        s = transport_launch(ctx, &o2, st);
+        s = transport_launch(ctx, &o2, b - a, st);
         if (s) return s;
         a = b;
       }
     } else {
       s = set_range(ctx, 0, total, st);
       if (s) return s;
-      s = transport_launch(ctx, &o2, st);
+      s = transport_launch(ctx, &o2, total, st);
       if (s) return s;
     }
   }
@@ -1600,7 +1686,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   for (int m = 0; m < n_models && cs == MCRT_OK; ++m) {
     mcrt_ctx *c = models[m];
     cs = zero_tallies(c, cs_);
-    if (cs == MCRT_OK && fill<uint64_t>(c->d_counter, 0ull, 1, cs_) != hipSuccess) cs = MCRT_EDEVICE;
+    if (cs == MCRT_OK && fill<uint64_t>(&c->d_ctl->emitted, 0ull, 1, cs_) != hipSuccess) cs = MCRT_EDEVICE;
   }
   hipError_t le = hipSuccess;
   if (cs == MCRT_OK) le = launch_transport(ctx->d_batch, n_models, ctx->fp64, false, grid, block, lds, cs_);

@@ -35,7 +35,7 @@ enum { NSTAT = 10 };  // packets escaped killed pah crossings scatters absorptio
 // source spectra); the R table holds what the packet walk reads per event
 // in the walk's precision.
 struct TabOff {
-  int w, hnu, a, kext, wk, wfk, kabs, frac, srcf, lnu, lum, pahw, pahe, logphi, krmax, srcpos, dtotal;
+  int w, hnu, a, kext, wk, wfk, kabs, frac, srccum, lnu, lum, pahcum, pahe, logphi, krmax, srcpos, dtotal;
   int r_kext, r_kabsm, r_alb, r_fsca, r_fabs, r_g, r_lucy, r_hnu, r_a, r_wk, r_total;
 };
 
@@ -50,10 +50,10 @@ __host__ __device__ inline TabOff tab_offsets(int nl, int ns, int nsrc, int nrow
   o.wfk = p; p += ns * nl;
   o.kabs = p; p += ns * nl;
   o.frac = p; p += MAX_NS;
-  o.srcf = p; p += nsrc * nl;
+  o.srccum = p; p += nsrc * nl;
   o.lnu = p; p += nsrc * nl;
   o.lum = p; p += MAX_SRC;
-  o.pahw = p; p += (nrows > 0 ? nrows : 1) * nl;
+  o.pahcum = p; p += (nrows > 0 ? nrows : 1) * nl;
   o.pahe = p; p += (nrows > 0 ? nrows : 1);
   o.logphi = p; p += ns * NT_TAB;
   o.krmax = p; p += NT_TAB;
@@ -75,12 +75,39 @@ __host__ __device__ inline TabOff tab_offsets(int nl, int ns, int nsrc, int nrow
 }
 
 // One model as the kernels see it (a device array of these drives a launch).
+// Packet queues of the wavefront transport. A round runs three kernels on
+// flight-ready queue f: emission appends new packets to it; the voxel walk
+// takes each packet to its next interaction and writes it back to its own
+// entry (an escape frees the entry); the interactions read the entries in
+// place and append the survivors, with the optical depth of their next
+// flight, to queue 1 - f. Queues hold packets as structures of arrays; the
+// R arrays are in the walk precision.
+struct QBuf {
+  void *px, *py, *pz, *dx, *dy, *dz, *rho, *tau;
+  int32_t *cx, *cy, *cz, *j;
+  uint64_t *pid;
+  uint32_t *rngd, *nint;
+  uint32_t *ncross, *nscat, *nabs, *nmrw, *nlucy;  // kept for packet records
+  double *mm;                                      // kept for packet records
+};
+
+struct WfCtl {
+  uint64_t emitted;  // packets of the launch started so far (launch-relative)
+  uint64_t first;    // launch-relative index of the first packet emitted this round
+  uint32_t n[2];     // packets held in queues 0 and 1
+  uint32_t work[3];  // next queue entry handed out by the emit, walk and interact kernels
+  uint32_t take;     // packets emitted this round
+  uint32_t pad;
+};
+
 struct ModelDev {
   int32_t nx, ny, nz, nl, ns, nsrc, pah, nrows, nview, nimg, ntheta, model_id;
   int32_t mode, record, pass, iter;
   double origin[3];
   double dcell, V, xi, lucy_tau, mrw_tau, mrw_gamma, kext_max;
   double ssca_unit;           // scattering sums are stored in these units (erg/s/sr)
+  double kr_gmax;             // largest Rosseland-mean bound of the table over [T_TAB_MIN, T_MAX]
+  double phi_tmin;            // Phi(T_TAB_MIN) of the first thermal species
   uint64_t max_int, first, n, id_base, rec_first, seed, ncell;
   const void *rho;            // [cells] context precision
   const void *rho_b;          // the same density in 4x4x4 bricks (brick_index), read by the walk
@@ -104,6 +131,10 @@ struct ModelDev {
   uint64_t *counter;          // packet counter of the launch
   unsigned long long *stats;  // [NSTAT]
   double kv[MAX_VIEW][3];     // view directions toward the observer
+  QBuf q[2];                  // wavefront queues
+  WfCtl *ctl;                 // their counters (counter points at ctl->emitted)
+  uint32_t qcap;              // capacity of each queue
+  uint32_t qpad;
 };
 
 // ---------------------------------------------------------------- bricks

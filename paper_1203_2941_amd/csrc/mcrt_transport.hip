@@ -162,6 +162,25 @@ __device__ __forceinline__ int pick_desc_fn(int n, R u, double &mm, F f) {
   return 0;
 }
 
+// The same pick for a fixed spectrum stored as running sums cum[j] (weights
+// of j .. n-1 added from n-1 down): the largest j with cum[j] >= u cum[0],
+// found by bisection.
+template <bool REC>
+__device__ __forceinline__ int pick_desc_cum(const double *cum, int n, double u, double &mm) {
+  const double tot = cum[0], target = u * tot;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cum[mid] >= target) lo = mid; else hi = mid - 1;
+  }
+  if (REC && tot > 0.0) {
+    const double prev = lo + 1 < n ? cum[lo + 1] : 0.0;
+    upd_margin(mm, (cum[lo] - target) / tot);
+    upd_margin(mm, (target - prev) / tot);
+  }
+  return lo;
+}
+
 // Lucy's thin-cell test rho max(kext) dcell < lucy_tau; the FP32 walk
 // compares rho with the equivalent density threshold.
 template <typename R>
@@ -459,10 +478,19 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
   const ModelDev &M = *X.M;
   if (!(M.mrw_tau > 0.0)) return false;
   int64_t c = ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0];
-  double rho = (double)gld(X.rho + c);
+  // the density of the cell came with the packet from its last flight
+  double rho = P.rho > (R)0 ? (double)P.rho : (double)gld(X.rho + c);
   if (!(rho > 0.0)) return false;
   if (!(rho * M.kext_max * M.dcell > M.mrw_tau)) return false;
   int s0 = first_thermal(M);
+  if (!REC && M.mode != M_FROZEN) {
+    // B&W temperatures come from at least one packet's energy; when that
+    // alone reaches Phi(T_TAB_MIN), T lies on the bound table and kappa_R
+    // is below its largest entry, which may already rule the step out
+    // without the temperature
+    const double rmin = M.xi / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * M.V);
+    if (rmin >= 1.001 * M.phi_tmin && !(rho * M.kr_gmax * M.dcell > M.mrw_tau)) return false;
+  }
   double T0 = mode_T(X, s0, c, rho);
   if (!REC) {
     // rigorous upper bound of kappa_R(T) on its table interval: skip the
@@ -536,8 +564,7 @@ __device__ __forceinline__ int pah_row(const Ctx<R> &X, int64_t c, double rho) {
 
 template <typename R, bool REC>
 __device__ __forceinline__ int pick_pah(const Ctx<R> &X, int row, double u, double &mm) {
-  const double *pw = X.dt + X.o.pahw + row * X.M->nl;
-  return pick_desc_fn<double, REC>(X.M->nl, u, mm, [&](int j) { return pw[j]; });
+  return pick_desc_cum<REC>(X.dt + X.o.pahcum + row * X.M->nl, X.M->nl, u, mm);
 }
 
 // Re-emission wavelength of species s at temperature T: Eq. 5 (FROZEN) or
@@ -578,11 +605,16 @@ __device__ __forceinline__ int pick_thermal(const Ctx<R> &X, int s, double T, R 
   }
 }
 
+// End of a packet: escape tally, status counters and its record. The
+// crossings and Lucy deposits of the packet are counted here unless the
+// caller counts them per flight (walk_tallied).
 template <typename R, bool REC>
-__device__ void finish(Ctx<R> &X, Pkt<R> &P) {
+__device__ void finish(Ctx<R> &X, Pkt<R> &P, bool walk_tallied = false) {
   const ModelDev &M = *X.M;
-  stat_add(X.st, 4, P.n_cross);
-  if (P.n_lucy) stat_add(X.st, 8, P.n_lucy);
+  if (!walk_tallied) {
+    stat_add(X.st, 4, P.n_cross);
+    if (P.n_lucy) stat_add(X.st, 8, P.n_lucy);
+  }
   if (P.status == ST_ESCAPED) {
     stat_add(X.st, 1, 1ull);
     int nt = M.ntheta > 0 ? M.ntheta : 1;
@@ -622,6 +654,7 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
   P.pid = M.id_base + M.first + idx;
   rng_init(P.rng, M.seed, P.pid, (uint32_t)M.iter, (uint32_t)M.model_id, M.pass == 2 ? 3u : 0u);
   P.status = ST_ALIVE;
+  P.rho = (R)0;
   P.n_cross = P.n_scat = P.n_abs = P.n_mrw = P.n_lucy = P.n_int = 0;
   P.mm = 1e300;
   stat_add(X.st, 0, 1ull);
@@ -656,8 +689,7 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
   if (M.nsrc > 1) s = pick_asc<double, REC>(X.dt + X.o.lum, 1, M.nsrc, us, P.mm);
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.p[k] = (R)X.dt[X.o.srcpos + 3 * s + k];
-  const double *sf = X.dt + X.o.srcf + s * nl;
-  P.j = pick_desc_fn<double, REC>(nl, ul, P.mm, [&](int j) { return sf[j]; });
+  P.j = pick_desc_cum<REC>(X.dt + X.o.srccum + s * nl, nl, ul, P.mm);
   start_cell<R>(M, P.p, P.d, P.c);
   if (P.c[0] < 0 || P.c[0] >= M.nx || P.c[1] < 0 || P.c[1] >= M.ny || P.c[2] < 0 ||
       P.c[2] >= M.nz)
@@ -665,18 +697,25 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
 }
 
 // Start of a flight: modified random walk steps while they apply, then the
-// optical depth of the flight. Returns false when the packet is killed.
+// optical depth of the flight. Returns a negative depth when the packet is
+// killed.
 template <typename R, bool REC>
-__device__ bool flight_start(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
+__device__ R flight_tau(Ctx<R> &X, Pkt<R> &P) {
   const ModelDev &M = *X.M;
   while (mrw_step<R, REC>(X, P)) {
     P.n_int++;
     if (M.max_int > 0 && P.n_int >= M.max_int) {
       P.status = ST_KILLED;
-      return false;
+      return (R)-1;
     }
   }
-  R tau_star = -m_log(rng_u<R>(P.rng));
+  return -m_log(rng_u<R>(P.rng));
+}
+
+template <typename R, bool REC>
+__device__ bool flight_start(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
+  const R tau_star = flight_tau<R, REC>(X, P);
+  if (tau_star < (R)0) return false;
   flight_setup<R>(X, P, F, tau_star);
   return true;
 }
@@ -861,6 +900,324 @@ k_transport(const ModelDev *__restrict__ models, int nmodels) {
       atomicAdd(&M.stats[threadIdx.x], s_stat[threadIdx.x]);
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------- wavefront
+// Per-block set-up shared by the kernels below: the model's constants in
+// Ctx and its tables staged in LDS. The walk needs only the R table (it
+// reads the extinction of its wavelength and, in thin cells, the Lucy
+// factors) and the SED; the other kernels take every table.
+template <typename R>
+__device__ void stage_model(Ctx<R> &X, const ModelDev &M, unsigned char *lds_raw,
+                            unsigned long long *s_stat, bool full) {
+  X.M = &M;
+  X.o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
+  X.nc = (int64_t)M.ncell;
+  X.rho = (const R *)M.rho;
+  X.rho_thin = (M.lucy_tau > 0.0) ? (R)(M.lucy_tau / (M.kext_max * M.dcell)) : (R)0;
+  X.og[0] = (R)M.origin[0]; X.og[1] = (R)M.origin[1]; X.og[2] = (R)M.origin[2];
+  X.dc = (R)M.dcell;
+  X.nx = M.nx; X.ny = M.ny; X.nz = M.nz;
+  X.rho_b = (const R *)M.rho_b;
+  X.nbx = M.nbx; X.nby = M.nby;
+  double *dt = (double *)lds_raw;
+  R *rt = full ? (R *)(dt + X.o.dtotal) : (R *)lds_raw;
+  int *im = (int *)(rt + X.o.r_total + (X.o.r_total & 1));
+  uint32_t *sed = (uint32_t *)(im + M.nl + (M.nl & 1));
+  if (full)
+    for (int i = threadIdx.x; i < X.o.dtotal; i += blockDim.x) dt[i] = M.tab[i];
+  for (int i = threadIdx.x; i < X.o.r_total; i += blockDim.x) rt[i] = ((const R *)M.rtab)[i];
+  for (int i = threadIdx.x; i < M.nl; i += blockDim.x) im[i] = M.imgmap[i];
+  const int nsed = (M.ntheta > 0 ? M.ntheta : 1) * M.nl;
+  for (int i = threadIdx.x; i < nsed; i += blockDim.x) sed[i] = 0u;
+  if (threadIdx.x < NSTAT) s_stat[threadIdx.x] = 0ull;
+  __syncthreads();
+  X.dt = full ? dt : nullptr;
+  X.rt = rt;
+  X.imgmap = im;
+  X.sed = sed;
+  X.st = s_stat;
+}
+
+// Block SED and statistics into the model's tallies.
+template <typename R>
+__device__ void flush_block(const Ctx<R> &X) {
+  const ModelDev &M = *X.M;
+  __syncthreads();
+  const int nsed = (M.ntheta > 0 ? M.ntheta : 1) * M.nl;
+  for (int i = threadIdx.x; i < nsed; i += blockDim.x)
+    if (X.sed[i]) atomicAdd((unsigned long long *)&M.sed[i], (unsigned long long)X.sed[i]);
+  if (threadIdx.x < NSTAT && X.st[threadIdx.x]) atomicAdd(&M.stats[threadIdx.x], X.st[threadIdx.x]);
+  __syncthreads();
+}
+
+template <typename R, bool REC>
+__device__ __forceinline__ void q_store(const QBuf &b, uint32_t i, const Pkt<R> &P, R tau) {
+  ((R *)b.px)[i] = P.p[0]; ((R *)b.py)[i] = P.p[1]; ((R *)b.pz)[i] = P.p[2];
+  ((R *)b.dx)[i] = P.d[0]; ((R *)b.dy)[i] = P.d[1]; ((R *)b.dz)[i] = P.d[2];
+  ((R *)b.rho)[i] = P.rho;
+  ((R *)b.tau)[i] = tau;
+  b.cx[i] = P.c[0]; b.cy[i] = P.c[1]; b.cz[i] = P.c[2];
+  b.j[i] = P.j;
+  b.pid[i] = P.pid;
+  b.rngd[i] = P.rng.d;
+  b.nint[i] = P.n_int;
+  if (REC) {
+    b.ncross[i] = P.n_cross; b.nscat[i] = P.n_scat; b.nabs[i] = P.n_abs;
+    b.nmrw[i] = P.n_mrw; b.nlucy[i] = P.n_lucy;
+    b.mm[i] = P.mm;
+  }
+}
+
+// Loads a queued packet; its RNG stream is re-keyed from the packet id and
+// continues at the stored draw index.
+template <typename R, bool REC>
+__device__ __forceinline__ R q_load(const ModelDev &M, const QBuf &b, uint32_t i, Pkt<R> &P) {
+  P.p[0] = gld((const R *)b.px + i); P.p[1] = gld((const R *)b.py + i);
+  P.p[2] = gld((const R *)b.pz + i);
+  P.d[0] = gld((const R *)b.dx + i); P.d[1] = gld((const R *)b.dy + i);
+  P.d[2] = gld((const R *)b.dz + i);
+  P.rho = gld((const R *)b.rho + i);
+  const R tau = gld((const R *)b.tau + i);
+  P.c[0] = gld(b.cx + i); P.c[1] = gld(b.cy + i); P.c[2] = gld(b.cz + i);
+  P.j = gld(b.j + i);
+  P.pid = gld(b.pid + i);
+  rng_init(P.rng, M.seed, P.pid, (uint32_t)M.iter, (uint32_t)M.model_id, M.pass == 2 ? 3u : 0u);
+  P.rng.d = gld(b.rngd + i);
+  P.n_int = gld(b.nint + i);
+  P.status = ST_ALIVE;
+  P.n_cross = P.n_scat = P.n_abs = P.n_mrw = P.n_lucy = 0;
+  P.mm = 1e300;
+  if (REC) {
+    P.n_cross = gld(b.ncross + i); P.n_scat = gld(b.nscat + i); P.n_abs = gld(b.nabs + i);
+    P.n_mrw = gld(b.nmrw + i); P.n_lucy = gld(b.nlucy + i);
+    P.mm = gld(b.mm + i);
+  }
+  return tau;
+}
+
+// One entry per lane in `pred` lanes: wave-aggregated reservation of
+// consecutive queue slots (every lane of the wave must call).
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t *count, bool pred, int lane,
+                                                 uint64_t lt_mask) {
+  const uint64_t m = __ballot(pred);
+  if (!m) return 0u;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0u;
+  if (lane == leader) base = gatomic_add(count, (uint32_t)__popcll(m));
+  base = (uint32_t)__shfl((int)base, leader);
+  return base + (uint32_t)__popcll(m & lt_mask);
+}
+
+// Next block of 64 entries of a work counter for this wave.
+__device__ __forceinline__ uint32_t wave_grab(uint32_t *work, int lane) {
+  uint32_t base = 0u;
+  if (lane == 0) base = gatomic_add(work, 64u);
+  return (uint32_t)__shfl((int)base, 0);
+}
+
+// Round set-up (one thread per model): how many new packets to start, and
+// the queues that this round empties.
+__global__ void k_wf_plan(const ModelDev *__restrict__ models, int nmodels, int fcur) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nmodels) return;
+  const ModelDev &M = models[m];
+  WfCtl *c = M.ctl;
+  const uint64_t left = M.n > c->emitted ? M.n - c->emitted : 0;
+  const uint32_t room = M.qcap > c->n[fcur] ? M.qcap - c->n[fcur] : 0u;
+  const uint32_t take = left < (uint64_t)room ? (uint32_t)left : room;
+  c->first = c->emitted;
+  c->emitted += take;
+  c->take = take;
+  c->n[1 - fcur] = 0u;
+  c->work[0] = c->work[1] = c->work[2] = 0u;
+}
+
+// Emission: new packets of the launch are started, sample the optical
+// depth of their first flight and join flight-ready queue fcur.
+template <typename R, bool REC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ unsigned long long s_stat[NSTAT];
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int mm = 0; mm < nmodels; ++mm) {
+    const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
+    WfCtl *c = M.ctl;
+    const uint32_t take = c->take;
+    if (take == 0u) continue;
+    Ctx<R> X;
+    stage_model<R>(X, M, lds_raw, s_stat, true);
+    const QBuf &qo = M.q[fcur];
+    for (;;) {
+      const uint32_t base = wave_grab(&c->work[0], lane);
+      if (base >= take) break;
+      const uint32_t i = base + (uint32_t)lane;
+      Pkt<R> P;
+      R tau = (R)-1;
+      bool keep = false;
+      if (i < take) {
+        start_packet<R, REC>(X, P, c->first + i);
+        if (P.status == ST_ALIVE) tau = flight_tau<R, REC>(X, P);
+        keep = P.status == ST_ALIVE;
+        if (!keep) finish<R, REC>(X, P, true);
+      }
+      const uint32_t slot = wave_reserve(&c->n[fcur], keep, lane, lt_mask);
+      if (keep && slot < M.qcap) q_store<R, REC>(qo, slot, P, tau);
+    }
+    flush_block(X);
+  }
+}
+
+// Voxel walk of every flight-ready packet of queue fcur to its next
+// interaction or out of the grid; the packet is written back to its own
+// entry. Lanes refill one by one, so flights of different lengths keep the
+// wave busy.
+template <typename R, bool REC>
+__global__ void __launch_bounds__(256)
+k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ unsigned long long s_stat[NSTAT];
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int mm = 0; mm < nmodels; ++mm) {
+    const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
+    WfCtl *c = M.ctl;
+    const uint32_t n = c->n[fcur];
+    if (n == 0u) continue;
+    Ctx<R> X;
+    stage_model<R>(X, M, lds_raw, s_stat, false);
+    const QBuf &qi = M.q[fcur];
+    Pkt<R> P;
+    Flight<R> F;
+    uint32_t mine = 0u;         // queue entry of the lane's packet
+    uint32_t c0 = 0u, l0 = 0u;  // crossings and Lucy deposits before this flight
+    // entries are taken from the queue 64 at a time into a wave-local pool
+    // (one atomic per 64 flights); lanes refill from the pool one by one
+    uint32_t pool = 0u, left = 0u;
+    int state = 0;  // 0 needs a packet, 1 walking, 2 no work left
+    for (;;) {
+      const uint64_t need = __ballot(state == 0);
+      if (need) {
+        const uint32_t k = (uint32_t)__popcll(need);
+        const uint32_t rank = (uint32_t)__popcll(need & lt_mask);
+        uint32_t fresh = 0u;
+        if (k > left) fresh = wave_grab(&c->work[1], lane);
+        if (state == 0) {
+          const uint32_t i = rank < left ? pool + rank : fresh + (rank - left);
+          if (i < n) {
+            mine = i;
+            const R tau = q_load<R, REC>(M, qi, i, P);
+            flight_setup<R>(X, P, F, tau);
+            c0 = P.n_cross;
+            l0 = P.n_lucy;
+            state = 1;
+          } else {
+            state = 2;
+          }
+        }
+        if (k > left) {
+          pool = fresh + (k - left);
+          left = 64u - (k - left);
+        } else {
+          pool += k;
+          left -= k;
+        }
+      }
+      if (!__any(state != 2)) break;
+      int r = 0;
+      if (state == 1) r = flight_batch<R, REC>(X, P, F);
+      if (r != 0) {
+        stat_add(X.st, 4, (unsigned long long)(P.n_cross - c0));
+        if (P.n_lucy != l0) stat_add(X.st, 8, (unsigned long long)(P.n_lucy - l0));
+        state = 0;
+      }
+      // the packet goes back to its own entry, which the interaction kernel
+      // reads next; an escape leaves the entry marked free (depth < 0)
+      if (r == 1) {
+        q_store<R, REC>(qi, mine, P, (R)0);
+      } else if (r == 2) {
+        ((R *)qi.tau)[mine] = (R)-1;
+        P.status = ST_ESCAPED;
+        finish<R, REC>(X, P, true);
+      }
+    }
+    flush_block(X);
+  }
+}
+
+// Interactions of the walked queue fcur (entries freed by escapes are
+// skipped); survivors sample their next flight and join flight-ready queue
+// 1 - fcur.
+template <typename R, bool REC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_wf_interact(const ModelDev *__restrict__ models, int nmodels, int fcur) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ unsigned long long s_stat[NSTAT];
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int mm = 0; mm < nmodels; ++mm) {
+    const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
+    WfCtl *c = M.ctl;
+    const uint32_t n = c->n[fcur];
+    if (n == 0u) continue;
+    Ctx<R> X;
+    stage_model<R>(X, M, lds_raw, s_stat, true);
+    const QBuf &qi = M.q[fcur];
+    const QBuf &qo = M.q[1 - fcur];
+    for (;;) {
+      const uint32_t base = wave_grab(&c->work[2], lane);
+      if (base >= n) break;
+      const uint32_t i = base + (uint32_t)lane;
+      Pkt<R> P;
+      R tau = (R)-1;
+      bool keep = false;
+      if (i < n && gld((const R *)qi.tau + i) >= (R)0) {
+        (void)q_load<R, REC>(M, qi, i, P);
+        interact<R, REC>(X, P);
+        if (P.status == ST_ALIVE) tau = flight_tau<R, REC>(X, P);
+        keep = P.status == ST_ALIVE;
+        if (!keep) finish<R, REC>(X, P, true);
+      }
+      const uint32_t slot = wave_reserve(&c->n[1 - fcur], keep, lane, lt_mask);
+      if (keep && slot < M.qcap) q_store<R, REC>(qo, slot, P, tau);
+    }
+    flush_block(X);
+  }
+}
+
+size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64) {
+  TabOff o = tab_offsets(nl, ns, nsrc, nrows);
+  size_t rs = fp64 ? 8 : 4;
+  return (size_t)(o.r_total + (o.r_total & 1)) * rs + (size_t)(nl + (nl & 1)) * 4 +
+         (size_t)(ntheta > 0 ? ntheta : 1) * nl * 4;
+}
+
+template <typename R, bool REC>
+static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_full, int grid_walk,
+                      size_t lds_full, size_t lds_walk, hipStream_t st) {
+  hipLaunchKernelGGL((k_wf_emit<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
+                     nmodels, fcur);
+  hipLaunchKernelGGL((k_wf_walk<R, REC>), dim3(grid_walk), dim3(256), lds_walk, st, d_models,
+                     nmodels, fcur);
+  hipLaunchKernelGGL((k_wf_interact<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
+                     nmodels, fcur);
+}
+
+// One round for nmodels models: plan, emit, walk, interact (stream order).
+hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
+                           int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_wf_plan, dim3((nmodels + 63) / 64), dim3(64), 0, st, d_models, nmodels, fcur);
+  if (fp64) {
+    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, st);
+    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, st);
+  } else {
+    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, st);
+    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, st);
+  }
+  return hipGetLastError();
 }
 
 // Lane-side layout size of the LDS tables for a model.

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_binding_structs_match_header_sizes():
     from paper_1203_2941_amd import _lib
     assert C.sizeof(_lib.PacketRecord) == 120
-    assert C.sizeof(_lib.RunOpts) == 72
+    assert C.sizeof(_lib.RunOpts) == 80
     assert C.sizeof(_lib.RunStats) == 88
 
 
