@@ -70,12 +70,11 @@ typedef struct {
   uint64_t max_interactions; /* per-packet cap; 0 = none; capped packets are killed */
   int32_t sed_theta_bins;    /* photon-counting SED bins, equal in cos(theta) */
   int32_t record;            /* 1: keep one mcrt_packet_record per packet */
-  int32_t block_size;        /* threads per block of the batched single-launch transport,
-                                multiple of 64 up to 256 (0 = 256) */
-  int32_t blocks_per_cu;     /* persistent blocks per compute unit: batched launch (0 = 4),
-                                emission and interaction kernels of a round (0 = 2) */
-  int32_t queue_depth;       /* packets per wavefront queue, 0 = 2^21 (at most 2^26) */
-  int32_t walk_blocks_per_cu; /* 256-thread blocks per compute unit of the walk kernel (0 = 4) */
+  int32_t blocks_per_cu;     /* 256-thread blocks per compute unit of the emission and
+                                interaction kernels of a round (0 = 2; 1..32) */
+  int32_t queue_depth;       /* packets per wavefront queue (0 = 2^21; 64..2^26) */
+  int32_t walk_blocks_per_cu; /* 256-thread blocks per compute unit of the walk kernel
+                                (0 = 4; 1..32) */
 } mcrt_run_opts;
 
 typedef struct {

@@ -26,8 +26,8 @@ class RunOpts(C.Structure):
         ("mode", C.c_int32), ("n_iter", C.c_int32), ("epoch_packets", C.c_uint64),
         ("n_total", C.c_uint64), ("lucy_tau", C.c_double), ("mrw_tau", C.c_double),
         ("mrw_gamma", C.c_double), ("max_interactions", C.c_uint64),
-        ("sed_theta_bins", C.c_int32), ("record", C.c_int32), ("block_size", C.c_int32),
-        ("blocks_per_cu", C.c_int32), ("queue_depth", C.c_int32), ("walk_blocks_per_cu", C.c_int32),
+        ("sed_theta_bins", C.c_int32), ("record", C.c_int32), ("blocks_per_cu", C.c_int32),
+        ("queue_depth", C.c_int32), ("walk_blocks_per_cu", C.c_int32),
     ]
 
 

@@ -1,10 +1,12 @@
-"""Launch-shape autotuner for the persistent transport kernel.
+"""Queue-depth and launch-shape autotuner for the wavefront transport.
 
-The queue depth of the persistent kernel is the number of lanes in flight,
-block_size x blocks_per_cu x CUs. The tuner times a packet subsample of the
-caller's models (one batched launch per candidate shape, same seeds) and
-keeps the shape with the highest packet rate. Results are cached per model
-signature in a JSON file.
+A candidate is (queue_depth, walk_blocks_per_cu, blocks_per_cu): packets
+per queue, 256-thread blocks per CU of the walk kernel, and blocks per CU of
+the emission and interaction kernels. Deeper queues give each round more
+flights per lane (shorter round tails) at the cost of memory. The tuner
+times a packet subsample of the caller's models (one batch per candidate,
+same seeds) and keeps the fastest. Results are cached per model signature
+in a JSON file.
 """
 from __future__ import annotations
 
@@ -16,7 +18,9 @@ from typing import Dict, List, Sequence, Tuple
 
 from .context import Context, run_batch
 
-CANDIDATES: List[Tuple[int, int]] = [(64, 8), (128, 4), (128, 8), (256, 2), (256, 4), (256, 8)]
+CANDIDATES: List[Tuple[int, int, int]] = [
+    (1 << 19, 4, 2), (1 << 20, 4, 2), (1 << 21, 4, 2), (1 << 21, 3, 2), (1 << 21, 6, 2),
+    (1 << 21, 4, 1), (1 << 22, 4, 2)]
 CACHE = os.environ.get("MCRT_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "mcrt_autotune.json"))
 
@@ -48,8 +52,8 @@ def _store(d: Dict) -> None:
 def tune(contexts: Sequence[Context], n_packets: Sequence[int], seeds: Sequence[int],
          sample_frac: float = 0.05, min_packets: int = 20000, candidates=None,
          use_cache: bool = True, **opts) -> Dict:
-    """Best (block_size, blocks_per_cu) for a batch; returns a dict with the
-    choice and the measured rates of every candidate."""
+    """Best (queue_depth, walk_blocks_per_cu, blocks_per_cu) for a batch;
+    returns a dict with the choice and the measured rates of every candidate."""
     mode = opts.get("mode", "bw_ticket")
     key = signature(contexts, str(mode))
     cache = _load() if use_cache else {}
@@ -58,16 +62,17 @@ def tune(contexts: Sequence[Context], n_packets: Sequence[int], seeds: Sequence[
     cand = candidates or CANDIDATES
     sub = [max(min_packets, int(n * sample_frac)) for n in n_packets]
     rates = {}
-    for bs, bpc in cand:
+    for qd, wb, bpc in cand:
         t0 = time.perf_counter()
-        st = run_batch(contexts, sub, seeds, block_size=bs, blocks_per_cu=bpc, **opts)
+        st = run_batch(contexts, sub, seeds, queue_depth=qd, walk_blocks_per_cu=wb,
+                       blocks_per_cu=bpc, **opts)
         dt = time.perf_counter() - t0
         ms = st[0]["kernel_ms"] if st else dt * 1e3
-        rates[f"{bs}x{bpc}"] = sum(sub) / (ms / 1e3)
+        rates[f"{qd}x{wb}x{bpc}"] = sum(sub) / (ms / 1e3)
     best = max(rates, key=rates.get)
-    bs, bpc = (int(x) for x in best.split("x"))
-    res = {"block_size": bs, "blocks_per_cu": bpc, "packets_per_s": rates[best], "rates": rates,
-           "sample_packets": int(sum(sub))}
+    qd, wb, bpc = (int(x) for x in best.split("x"))
+    res = {"queue_depth": qd, "walk_blocks_per_cu": wb, "blocks_per_cu": bpc,
+           "packets_per_s": rates[best], "rates": rates, "sample_packets": int(sum(sub))}
     if use_cache:
         cache[key] = res
         _store(cache)

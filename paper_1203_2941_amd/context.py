@@ -43,15 +43,14 @@ def _stream(stream):
 
 def run_opts(mode="bw_ticket", n_iter=3, epoch_packets=4096, n_total=0, lucy_tau=1e-2,
              mrw_tau=0.0, mrw_gamma=2.0, max_interactions=10_000_000, sed_theta_bins=10,
-             record=False, block_size=0, blocks_per_cu=0, queue_depth=0, walk_blocks_per_cu=0):
+             record=False, blocks_per_cu=0, queue_depth=0, walk_blocks_per_cu=0):
     modes = {"frozen": L.FROZEN, "bw_epoch": L.BW_EPOCH, "bw_ticket": L.BW_TICKET}
     o = L.RunOpts()
     o.mode = modes[mode] if isinstance(mode, str) else int(mode)
     o.n_iter, o.epoch_packets, o.n_total = n_iter, epoch_packets, n_total
     o.lucy_tau, o.mrw_tau, o.mrw_gamma = lucy_tau, mrw_tau, mrw_gamma
     o.max_interactions, o.sed_theta_bins, o.record = max_interactions, sed_theta_bins, int(record)
-    o.block_size, o.blocks_per_cu = block_size, blocks_per_cu
-    o.queue_depth, o.walk_blocks_per_cu = queue_depth, walk_blocks_per_cu
+    o.blocks_per_cu, o.queue_depth, o.walk_blocks_per_cu = blocks_per_cu, queue_depth, walk_blocks_per_cu
     return o
 
 

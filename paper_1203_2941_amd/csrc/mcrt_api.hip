@@ -22,8 +22,6 @@
 
 namespace mcrt {
 size_t transport_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64);
-hipError_t launch_transport(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int grid,
-                            int block, size_t lds, hipStream_t st);
 hipError_t launch_epoch_snapshot(const ModelDev *d, hipStream_t st);
 hipError_t launch_finalize_T(const ModelDev *d, bool fp64, double *T, double *E, hipStream_t st);
 hipError_t launch_init_T(const ModelDev *d, bool fp64, double *T, hipStream_t st);
@@ -34,6 +32,8 @@ hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, boo
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
                            hipStream_t st);
 size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64);
+hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
+                          hipStream_t st);
 hipError_t launch_vox_torus(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
                             int ncl, const double *dC, double r_clump, double rho_cl,
                             double rho_int, double r_in, double r_out, double s1, void *rho,
@@ -910,16 +910,12 @@ static mcrt_status check_opts(mcrt_ctx *ctx, const mcrt_run_opts *o) {
   if (o->sed_theta_bins < 1 || o->sed_theta_bins > 180) return fail(ctx, MCRT_EINVAL, "sed_theta_bins must be 1..180");
   if (o->mrw_tau > 0.0 && !(o->mrw_gamma > 0.0)) return fail(ctx, MCRT_EINVAL, "mrw_gamma must be > 0");
   if (!std::isfinite(o->lucy_tau) || !std::isfinite(o->mrw_tau)) return fail(ctx, MCRT_EINVAL, "non-finite threshold");
-  if (o->block_size < 0 || o->block_size > 256 || (o->block_size % 64) != 0)
-    return fail(ctx, MCRT_EINVAL, "block_size must be 64, 128, 192 or 256");
   if (o->blocks_per_cu < 0 || o->blocks_per_cu > 32) return fail(ctx, MCRT_EINVAL, "blocks_per_cu must be 0..32");
+  if (o->walk_blocks_per_cu < 0 || o->walk_blocks_per_cu > 32)
+    return fail(ctx, MCRT_EINVAL, "walk_blocks_per_cu must be 0..32");
+  if (o->queue_depth != 0 && (o->queue_depth < 64 || o->queue_depth > (1 << 26)))
+    return fail(ctx, MCRT_EINVAL, "queue_depth must be 0 or 64..2^26");
   return MCRT_OK;
-}
-
-static void launch_shape(mcrt_ctx *ctx, const mcrt_run_opts *o, int &grid, int &block) {
-  block = (o && o->block_size > 0) ? o->block_size : 256;
-  int bpc = (o && o->blocks_per_cu > 0) ? o->blocks_per_cu : 4;
-  grid = ctx->num_cu * bpc;
 }
 
 // Packet range of the next launch (device-side, in stream order).
@@ -1638,6 +1634,18 @@ extern "C" mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_
 
 // ------------------------------------------------------------------ batch
 
+// Queue counters of every model of a batch back to the start of a launch.
+__global__ void k_wf_reset(const ModelDev *models, int nmodels) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nmodels) return;
+  WfCtl *c = models[m].ctl;
+  c->emitted = 0;
+  c->first = 0;
+  c->n[0] = c->n[1] = 0u;
+  c->work[0] = c->work[1] = c->work[2] = 0u;
+  c->take = 0u;
+}
+
 extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
                                       const uint64_t *n_packets, const uint64_t *seeds,
                                       const mcrt_run_opts *opts, mcrt_run_stats *stats,
@@ -1645,6 +1653,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   if (!models || n_models < 1 || !models[0]) return MCRT_EINVAL;
   mcrt_ctx *ctx = models[0];
   if (!n_packets || !seeds) return fail(ctx, MCRT_EINVAL, "NULL n_packets/seeds");
+  if (n_models > 1024) return fail(ctx, MCRT_EINVAL, "at most 1024 models per batch");
   mcrt_status s = check_opts(ctx, opts);
   if (s) return s;
   if (opts->mode == MCRT_BW_EPOCH || (opts->mode == MCRT_FROZEN && opts->n_iter != 1))
@@ -1653,12 +1662,14 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device));
   std::vector<ModelDev> hm(n_models);
-  size_t lds = 0;
+  size_t lds = 0, lds_w = 0;
   for (int m = 0; m < n_models; ++m) {
     mcrt_ctx *c = models[m];
     if (!c || c->device != ctx->device || c->fp64 != ctx->fp64)
       return fail(ctx, MCRT_EINVAL, "model %d: same device and precision required", m);
     s = prepare_run(c, opts, n_packets[m], st);
+    if (s) return fail(ctx, s, "model %d: %s", m, c->err.c_str());
+    s = ensure_queues(c, opts, n_packets[m]);
     if (s) return fail(ctx, s, "model %d: %s", m, c->err.c_str());
     fill_model(c, hm[m], opts, 0);  // same streams as the model's own run_packets
     hm[m].seed = seeds[m];
@@ -1666,6 +1677,8 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
     hm[m].n = n_packets[m];
     size_t b = transport_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->fp64);
     if (b > lds) lds = b;
+    b = walk_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->fp64);
+    if (b > lds_w) lds_w = b;
   }
   if (lds > ctx->lds_max) return fail(ctx, MCRT_EINVAL, "batch tables need %zu bytes of LDS (limit %zu)", lds, ctx->lds_max);
   if (n_models > ctx->batch_cap) {
@@ -1674,38 +1687,58 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   }
   if (sizeof(ModelDev) * n_models > STAGE_BYTES) return fail(ctx, MCRT_EINVAL, "too many models");
   HIPCHK(stage_copy(ctx, ctx->d_batch, hm.data(), sizeof(ModelDev) * n_models, st));
-  int grid, block;
-  launch_shape(ctx, opts, grid, block);
-  // one graph: reset tallies and counters, the persistent transport, Eq. 4.
-  // Captured on the library's own stream, launched on the caller's.
+  for (int m = 0; m < n_models; ++m) {
+    s = zero_tallies(models[m], st);
+    if (s) return s;
+    models[m]->snap_stale = true;
+  }
+  hipLaunchKernelGGL(k_wf_reset, dim3((n_models + 63) / 64), dim3(64), 0, st, ctx->d_batch, n_models);
+  HIPCHK(hipGetLastError());
+  const int gfull = ctx->num_cu * (opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2);
+  const int gwalk = ctx->num_cu * (opts->walk_blocks_per_cu > 0 ? opts->walk_blocks_per_cu : 4);
+  // ROUNDS wavefront rounds over every model of the batch and the count of
+  // models still busy, captured once on the library's own stream and
+  // replayed on the caller's until no model has packets left
+  constexpr int ROUNDS = 8;
+  uint32_t *d_busy = &ctx->d_ctl->busy;  // address arithmetic only
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cs_ = ctx->cap_stream;
   HIPCHK(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
-  mcrt_status cs = MCRT_OK;
-  for (int m = 0; m < n_models && cs == MCRT_OK; ++m) {
-    mcrt_ctx *c = models[m];
-    cs = zero_tallies(c, cs_);
-    if (cs == MCRT_OK && fill<uint64_t>(&c->d_ctl->emitted, 0ull, 1, cs_) != hipSuccess) cs = MCRT_EDEVICE;
-  }
   hipError_t le = hipSuccess;
-  if (cs == MCRT_OK) le = launch_transport(ctx->d_batch, n_models, ctx->fp64, false, grid, block, lds, cs_);
-  for (int m = 0; m < n_models; ++m) models[m]->snap_stale = true;
-  for (int m = 0; m < n_models && cs == MCRT_OK && le == hipSuccess; ++m)
-    le = launch_finalize_T(ctx->d_batch + m, ctx->fp64, models[m]->d_T, nullptr, cs_);
+  for (int r = 0; r < ROUNDS && le == hipSuccess; ++r)
+    le = launch_wf_round(ctx->d_batch, n_models, ctx->fp64, false, r & 1, gfull, gwalk, lds, lds_w, cs_);
+  if (le == hipSuccess) le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, cs_);
   hipError_t ce = hipStreamEndCapture(cs_, &graph);
-  if (cs != MCRT_OK || le != hipSuccess || ce != hipSuccess) {
+  if (le != hipSuccess || ce != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     return fail(ctx, MCRT_EDEVICE, "graph capture failed: %s",
                 hipGetErrorString(le != hipSuccess ? le : ce));
   }
   HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   HIPCHK(hipEventRecord(ctx->ev0, st));
-  HIPCHK(hipGraphLaunch(exec, st));
-  HIPCHK(hipEventRecord(ctx->ev1, st));
-  HIPCHK(hipStreamSynchronize(st));
+  mcrt_status rs = MCRT_OK;
+  for (uint64_t rep = 0;; ++rep) {
+    hipError_t e = hipGraphLaunch(exec, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ctx->h_ctl->busy, d_busy, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      rs = fail(ctx, MCRT_EDEVICE, "batch round: %s", hipGetErrorString(e));
+      break;
+    }
+    if (ctx->h_ctl->busy == 0u) break;
+    if (rep > (1ull << 30)) {
+      rs = fail(ctx, MCRT_EDEVICE, "batch did not finish");
+      break;
+    }
+  }
   (void)hipGraphExecDestroy(exec);
   (void)hipGraphDestroy(graph);
+  if (rs) return rs;
+  for (int m = 0; m < n_models; ++m)
+    HIPCHK(launch_finalize_T(ctx->d_batch + m, ctx->fp64, models[m]->d_T, nullptr, st));
+  HIPCHK(hipEventRecord(ctx->ev1, st));
+  HIPCHK(hipStreamSynchronize(st));
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   ctx->t_transport = ms;

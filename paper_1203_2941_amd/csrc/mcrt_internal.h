@@ -97,7 +97,7 @@ struct WfCtl {
   uint32_t n[2];     // packets held in queues 0 and 1
   uint32_t work[3];  // next queue entry handed out by the emit, walk and interact kernels
   uint32_t take;     // packets emitted this round
-  uint32_t pad;
+  uint32_t busy;     // batch: models with packets left (first model's counters only)
 };
 
 struct ModelDev {

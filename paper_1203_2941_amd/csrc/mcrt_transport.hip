@@ -1,16 +1,19 @@
 // mcrt_transport.hip - Monte Carlo packet transport (sect. 2-3 of Heymann &
-// Siebenmorgen) as one persistent kernel for gfx950.
+// Siebenmorgen) for gfx950 as wavefront rounds over packet queues.
 //
-// Each block picks a model that still has packets (one model for
-// run_packets, many for run_batch), stages that model's opacity, Planck and
-// source tables in LDS, and its 64-wide waves refill lanes from the model's
-// packet counter with one atomic per wave. A lane runs its packet event by
-// event: emission (Eq. 1 packets, isotropic directions), optional modified
-// random walk (sect. 3.2), one flight of sampled optical depth through the
-// voxel grid (Eqs. 2-3) with Lucy deposits in thin cells (Eq. 9), then an
-// interaction: Henyey-Greenstein scattering (Eq. 15) or absorption with
-// re-emission by Eq. 5 (iterative scheme) or Eq. 10 (Bjorkman & Wood).
-// Escapes are counted into an LDS copy of the photon-counting SED.
+// A packet's history is a chain of events: emission (Eq. 1 packets,
+// isotropic directions), optional modified random walk steps (sect. 3.2),
+// one flight of sampled optical depth through the voxel grid (Eqs. 2-3)
+// with Lucy deposits in thin cells (Eq. 9), then an interaction:
+// Henyey-Greenstein scattering (Eq. 15) or absorption with re-emission by
+// Eq. 5 (iterative scheme) or Eq. 10 (Bjorkman & Wood). A round moves
+// every live packet by one flight and one interaction: an emission kernel
+// tops the flight-ready queue up with new packets, the walk kernel (small
+// register file, high occupancy) takes every queued packet through its
+// flight, and the interaction kernel (FP64 Eq. 4, re-emission spectra)
+// handles the packets whose flight ended in the grid. Each kernel's blocks
+// stage their model's tables in LDS; escapes are counted into an LDS copy
+// of the photon-counting SED.
 #include "mcrt_internal.h"
 
 namespace mcrt {
@@ -712,14 +715,6 @@ __device__ R flight_tau(Ctx<R> &X, Pkt<R> &P) {
   return -m_log(rng_u<R>(P.rng));
 }
 
-template <typename R, bool REC>
-__device__ bool flight_start(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
-  const R tau_star = flight_tau<R, REC>(X, P);
-  if (tau_star < (R)0) return false;
-  flight_setup<R>(X, P, F, tau_star);
-  return true;
-}
-
 // Interaction at P.p in cell P.c: albedo split, HG scattering with its
 // event sums, or absorption with re-emission (or a PAH stop).
 template <typename R, bool REC>
@@ -787,119 +782,6 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
   }
   P.n_int++;
   if (M.max_int > 0 && P.n_int >= M.max_int) P.status = ST_KILLED;
-}
-
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
-  uint32_t lo = __shfl((int)(uint32_t)v, src), hi = __shfl((int)(uint32_t)(v >> 32), src);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Block-wide choice of the next model with packets left (-1 when none).
-__device__ int pick_model(const ModelDev *models, int nmodels) {
-  int start = blockIdx.x % nmodels;
-  for (int i = 0; i < nmodels; ++i) {
-    int m = (start + i) % nmodels;
-    const ModelDev &M = models[m];
-    if (*(volatile uint64_t *)M.counter < M.n) return m;
-  }
-  return -1;
-}
-
-// Two waves per SIMD: the interaction code keeps the register file at 256
-// per lane; the FP64 helpers it calls are out of line for that reason.
-template <typename R, bool REC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_transport(const ModelDev *__restrict__ models, int nmodels) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ int s_model;
-  __shared__ unsigned long long s_stat[NSTAT];
-  const int lane = threadIdx.x & 63;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (;;) {
-    if (threadIdx.x == 0) s_model = pick_model(models, nmodels);
-    __syncthreads();
-    const int m = __builtin_amdgcn_readfirstlane(s_model);
-    if (m < 0) break;
-    const ModelDev &M = models[m];
-    Ctx<R> X;
-    X.M = &M;
-    X.o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
-    X.nc = (int64_t)M.ncell;
-    X.rho = (const R *)M.rho;
-    X.rho_thin = (M.lucy_tau > 0.0) ? (R)(M.lucy_tau / (M.kext_max * M.dcell)) : (R)0;
-    X.og[0] = (R)M.origin[0]; X.og[1] = (R)M.origin[1]; X.og[2] = (R)M.origin[2];
-    X.dc = (R)M.dcell;
-    X.nx = M.nx; X.ny = M.ny; X.nz = M.nz;
-    X.rho_b = (const R *)M.rho_b;
-    X.nbx = M.nbx; X.nby = M.nby;
-    double *dt = (double *)lds_raw;
-    R *rt = (R *)(dt + X.o.dtotal);
-    int *im = (int *)(rt + X.o.r_total + (X.o.r_total & 1));
-    uint32_t *sed = (uint32_t *)(im + M.nl + (M.nl & 1));
-    for (int i = threadIdx.x; i < X.o.dtotal; i += blockDim.x) dt[i] = M.tab[i];
-    for (int i = threadIdx.x; i < X.o.r_total; i += blockDim.x) rt[i] = ((const R *)M.rtab)[i];
-    for (int i = threadIdx.x; i < M.nl; i += blockDim.x) im[i] = M.imgmap[i];
-    const int nsed = (M.ntheta > 0 ? M.ntheta : 1) * M.nl;
-    for (int i = threadIdx.x; i < nsed; i += blockDim.x) sed[i] = 0u;
-    if (threadIdx.x < NSTAT) s_stat[threadIdx.x] = 0ull;
-    __syncthreads();
-    X.dt = dt;
-    X.rt = rt;
-    X.imgmap = im;
-    X.sed = sed;
-    X.st = s_stat;
-
-    Pkt<R> P;
-    Flight<R> F;
-    // lane states: 0 needs a packet, 1 flight start, 2 in flight, 3 interaction, 4 no work left
-    int state = 0;
-    for (;;) {
-      uint64_t need = __ballot(state == 0);
-      if (need) {
-        int leader = __ffsll((unsigned long long)need) - 1;
-        uint64_t base = 0;
-        if (lane == leader) base = atomicAdd((unsigned long long *)M.counter,
-                                             (unsigned long long)__popcll(need));
-        base = shfl64(base, leader);
-        if (state == 0) {
-          uint64_t idx = base + (uint64_t)__popcll(need & lt_mask);
-          if (idx < M.n) {
-            start_packet<R, REC>(X, P, idx);
-            if (P.status != ST_ALIVE) finish<R, REC>(X, P); else state = 1;
-          } else {
-            state = 4;
-          }
-        }
-      }
-      if (!__any(state != 4)) break;
-      // interactions wait until half the wave has one, or nothing else can run
-      const uint64_t mi = __ballot(state == 3);
-      const uint64_t mf = __ballot(state == 1 || state == 2);
-      if (mi && (__popcll(mi) >= 32 || mf == 0)) {
-        if (state == 3) {
-          interact<R, REC>(X, P);
-          if (P.status != ST_ALIVE) { finish<R, REC>(X, P); state = 0; }
-          else state = 1;
-        }
-      }
-      if (state == 1) {
-        if (flight_start<R, REC>(X, P, F)) state = 2;
-        else { finish<R, REC>(X, P); state = 0; }
-      }
-      if (state == 2) {
-        int r = flight_batch<R, REC>(X, P, F);
-        if (r == 1) state = 3;
-        else if (r == 2) { P.status = ST_ESCAPED; finish<R, REC>(X, P); state = 0; }
-      }
-    }
-    // flush block SED and statistics
-    __syncthreads();
-    for (int i = threadIdx.x; i < nsed; i += blockDim.x)
-      if (sed[i]) atomicAdd((unsigned long long *)&M.sed[i], (unsigned long long)sed[i]);
-    if (threadIdx.x < NSTAT && s_stat[threadIdx.x])
-      atomicAdd(&M.stats[threadIdx.x], s_stat[threadIdx.x]);
-    __syncthreads();
-  }
 }
 
 // ------------------------------------------------------------- wavefront
@@ -1046,7 +928,7 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
     const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
     WfCtl *c = M.ctl;
     const uint32_t take = c->take;
-    if (take == 0u) continue;
+    if (take == 0u || *(volatile uint32_t *)&c->work[0] >= take) continue;
     Ctx<R> X;
     stage_model<R>(X, M, lds_raw, s_stat, true);
     const QBuf &qo = M.q[fcur];
@@ -1085,7 +967,7 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
     const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
     WfCtl *c = M.ctl;
     const uint32_t n = c->n[fcur];
-    if (n == 0u) continue;
+    if (n == 0u || *(volatile uint32_t *)&c->work[1] >= n) continue;
     Ctx<R> X;
     stage_model<R>(X, M, lds_raw, s_stat, false);
     const QBuf &qi = M.q[fcur];
@@ -1161,7 +1043,7 @@ k_wf_interact(const ModelDev *__restrict__ models, int nmodels, int fcur) {
     const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
     WfCtl *c = M.ctl;
     const uint32_t n = c->n[fcur];
-    if (n == 0u) continue;
+    if (n == 0u || *(volatile uint32_t *)&c->work[2] >= n) continue;
     Ctx<R> X;
     stage_model<R>(X, M, lds_raw, s_stat, true);
     const QBuf &qi = M.q[fcur];
@@ -1220,6 +1102,28 @@ hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, boo
   return hipGetLastError();
 }
 
+// Number of models with packets left after a round whose emptied queue
+// was fcur (one block; nmodels <= 1024).
+__global__ void k_wf_busy(const ModelDev *__restrict__ models, int nmodels, int fcur,
+                          uint32_t *busy) {
+  __shared__ uint32_t s_busy;
+  if (threadIdx.x == 0) s_busy = 0u;
+  __syncthreads();
+  for (int m = threadIdx.x; m < nmodels; m += blockDim.x) {
+    const ModelDev &M = models[m];
+    const WfCtl *c = M.ctl;
+    if (c->n[1 - fcur] > 0u || c->emitted < M.n) atomicAdd(&s_busy, 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *busy = s_busy;
+}
+
+hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_wf_busy, dim3(1), dim3(256), 0, st, d_models, nmodels, fcur, busy);
+  return hipGetLastError();
+}
+
 // Lane-side layout size of the LDS tables for a model.
 size_t transport_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64) {
   TabOff o = tab_offsets(nl, ns, nsrc, nrows);
@@ -1227,22 +1131,6 @@ size_t transport_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool
   size_t b = (size_t)o.dtotal * 8 + (size_t)(o.r_total + (o.r_total & 1)) * rs +
              (size_t)(nl + (nl & 1)) * 4 + (size_t)(ntheta > 0 ? ntheta : 1) * nl * 4;
   return b;
-}
-
-hipError_t launch_transport(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int grid,
-                            int block, size_t lds, hipStream_t st) {
-  if (fp64) {
-    if (rec)
-      hipLaunchKernelGGL((k_transport<double, true>), dim3(grid), dim3(block), lds, st, d_models, nmodels);
-    else
-      hipLaunchKernelGGL((k_transport<double, false>), dim3(grid), dim3(block), lds, st, d_models, nmodels);
-  } else {
-    if (rec)
-      hipLaunchKernelGGL((k_transport<float, true>), dim3(grid), dim3(block), lds, st, d_models, nmodels);
-    else
-      hipLaunchKernelGGL((k_transport<float, false>), dim3(grid), dim3(block), lds, st, d_models, nmodels);
-  }
-  return hipGetLastError();
 }
 
 // ------------------------------------------------------- per-cell kernels

@@ -71,8 +71,9 @@ def test_autotuner_picks_a_candidate(tmp_path, monkeypatch):
     ms = models()
     ctxs = [gpu_context(m, "fp32") for m in ms]
     res = autotune.tune(ctxs, [m.n_packets for m in ms], [m.seed for m in ms],
-                        candidates=[(128, 4), (256, 4)], mode="bw_ticket")
-    assert (res["block_size"], res["blocks_per_cu"]) in [(128, 4), (256, 4)]
+                        candidates=[(1 << 16, 4, 2), (1 << 18, 3, 2)], mode="bw_ticket")
+    assert (res["queue_depth"], res["walk_blocks_per_cu"], res["blocks_per_cu"]) in [
+        (1 << 16, 4, 2), (1 << 18, 3, 2)]
     assert res["packets_per_s"] > 0
     again = autotune.tune(ctxs, [m.n_packets for m in ms], [m.seed for m in ms], mode="bw_ticket")
     assert again == res  # served from the cache

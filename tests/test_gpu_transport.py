@@ -112,10 +112,10 @@ def test_resume_and_determinism(orc):
     assert np.array_equal(ka, kb)
     np.testing.assert_allclose(ea, eb, rtol=1e-12)
     assert np.array_equal(a.sed()[1], b.sed()[1])
-    # launch shape does not change the result
+    # queue depth and launch shape do not change the result
     c = gpu_context(m)
-    c.run_packets(0, 20000, 0, mode="bw_epoch", epoch_packets=1000, n_total=20000, block_size=64,
-                  blocks_per_cu=1)
+    c.run_packets(0, 20000, 0, mode="bw_epoch", epoch_packets=1000, n_total=20000,
+                  queue_depth=64, walk_blocks_per_cu=1, blocks_per_cu=1)
     assert np.array_equal(ka, c.tallies()[0])
 
 

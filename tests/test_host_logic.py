@@ -26,7 +26,8 @@ def test_autotune_signature_and_cache(tmp_path, monkeypatch):
     assert autotune.signature(a, "bw_ticket") != autotune.signature(a, "frozen")
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "t.json"))
     key = autotune.signature(a, "bw_ticket")
-    hit = {"block_size": 128, "blocks_per_cu": 4, "packets_per_s": 1.0, "rates": {}, "sample_packets": 1}
+    hit = {"queue_depth": 1 << 20, "walk_blocks_per_cu": 4, "blocks_per_cu": 2,
+           "packets_per_s": 1.0, "rates": {}, "sample_packets": 1}
     (tmp_path / "t.json").write_text(json.dumps({key: hit}))
     # a cached entry is returned without touching the GPU
     assert autotune.tune(a, [1, 1], [0, 1], mode="bw_ticket") == hit
