@@ -54,6 +54,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queue-depth", type=int, default=0,
                     help="packets per wavefront queue (0: the library default)")
+    ap.add_argument("--walk-blocks-per-cu", type=int, default=0,
+                    help="walk-kernel blocks per CU (0: the library default)")
+    ap.add_argument("--blocks-per-cu", type=int, default=0,
+                    help="emission/interaction blocks per CU (0: the library default)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one elementwise copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -90,7 +94,8 @@ def main():
     sed = torch.empty((len(views), len(idx)), dtype=torch.float64, device="cuda")
     grad = torch.empty(ctx.ncells, dtype=torch.float32, device="cuda")
     opts = dict(mode="bw_ticket", n_total=N, mrw_tau=50.0, mrw_gamma=2.0, lucy_tau=1e-2,
-                max_interactions=10_000_000, sed_theta_bins=10, queue_depth=args.queue_depth)
+                max_interactions=10_000_000, sed_theta_bins=10, queue_depth=args.queue_depth,
+                walk_blocks_per_cu=args.walk_blocks_per_cu, blocks_per_cu=args.blocks_per_cu)
 
     def step(seed):
         ctx.reset()

@@ -30,7 +30,7 @@ hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, in
                         int nby, hipStream_t st);
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
-                           hipStream_t st);
+                           bool idx32, hipStream_t st);
 size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64);
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
                           hipStream_t st);
@@ -535,6 +535,10 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
 
 // Bricked copy of the density read by the walk; rebuilt whenever the
 // density changes.
+static uint64_t brick_cells(const mcrt_ctx *ctx) {
+  return (uint64_t)ctx->nbx * ctx->nby * ctx->nbz * 64;
+}
+
 static mcrt_status build_brick(mcrt_ctx *ctx) {
   ctx->nbx = (ctx->nx + 3) / 4;
   ctx->nby = (ctx->ny + 3) / 4;
@@ -939,7 +943,7 @@ static mcrt_status set_range(mcrt_ctx *ctx, uint64_t first, uint64_t n, hipStrea
 // Wavefront queues: two queues of Q packets as structures of arrays,
 // carved from one allocation (256-byte aligned arrays).
 static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n) {
-  uint64_t want = (o && o->queue_depth > 0) ? (uint64_t)o->queue_depth : (1ull << 21);
+  uint64_t want = (o && o->queue_depth > 0) ? (uint64_t)o->queue_depth : (1ull << 23);
   if (want > (1ull << 26)) want = 1ull << 26;
   uint64_t need = (n + 4095) / 4096 * 4096;
   if (need < 4096) need = 4096;
@@ -980,7 +984,8 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
   const int every = 4;
   for (uint64_t r = 0;; ++r) {
     const int fcur = (int)(r & 1);
-    HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w, st));
+    HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w,
+                           brick_cells(ctx) < (1ull << 32), st));
     if ((r + 1) % every == 0) {
       HIPCHK(hipMemcpyAsync(ctx->h_ctl, ctx->d_ctl, sizeof(WfCtl), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -1663,8 +1668,10 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   HIPCHK(hipSetDevice(ctx->device));
   std::vector<ModelDev> hm(n_models);
   size_t lds = 0, lds_w = 0;
+  bool idx32 = true;
   for (int m = 0; m < n_models; ++m) {
     mcrt_ctx *c = models[m];
+    if (c && brick_cells(c) >= (1ull << 32)) idx32 = false;
     if (!c || c->device != ctx->device || c->fp64 != ctx->fp64)
       return fail(ctx, MCRT_EINVAL, "model %d: same device and precision required", m);
     s = prepare_run(c, opts, n_packets[m], st);
@@ -1707,7 +1714,8 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   HIPCHK(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int r = 0; r < ROUNDS && le == hipSuccess; ++r)
-    le = launch_wf_round(ctx->d_batch, n_models, ctx->fp64, false, r & 1, gfull, gwalk, lds, lds_w, cs_);
+    le = launch_wf_round(ctx->d_batch, n_models, ctx->fp64, false, r & 1, gfull, gwalk, lds, lds_w,
+                         idx32, cs_);
   if (le == hipSuccess) le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, cs_);
   hipError_t ce = hipStreamEndCapture(cs_, &graph);
   if (le != hipSuccess || ce != hipSuccess) {

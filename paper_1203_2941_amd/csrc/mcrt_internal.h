@@ -147,6 +147,13 @@ __host__ __device__ __forceinline__ int64_t brick_index(int cx, int cy, int cz, 
   return ((((int64_t)(cz >> 2) * nby + (cy >> 2)) * nbx + (cx >> 2)) << 6) +
          (((cz & 3) << 4) | ((cy & 3) << 2) | (cx & 3));
 }
+// The same in 32-bit arithmetic, for bricked grids of fewer than 2^32 cells
+// (cells in range, so every coordinate is >= 0).
+__device__ __forceinline__ uint32_t brick_index32(int cx, int cy, int cz, int nbx, int nby) {
+  const uint32_t b = ((uint32_t)(cz >> 2) * (uint32_t)nby + (uint32_t)(cy >> 2)) * (uint32_t)nbx +
+                     (uint32_t)(cx >> 2);
+  return (b << 6) | (uint32_t)(((cz & 3) << 4) | ((cy & 3) << 2) | (cx & 3));
+}
 
 // ---------------------------------------------------------------- RNG
 // Philox4x32-10 (Salmon et al. 2011); key = seed, counter = (draw block,

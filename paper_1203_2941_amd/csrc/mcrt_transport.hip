@@ -14,6 +14,8 @@
 // handles the packets whose flight ended in the grid. Each kernel's blocks
 // stage their model's tables in LDS; escapes are counted into an LDS copy
 // of the photon-counting SED.
+#include <type_traits>
+
 #include "mcrt_internal.h"
 
 namespace mcrt {
@@ -303,7 +305,7 @@ __device__ __forceinline__ void flight_setup(const Ctx<R> &X, const Pkt<R> &P, F
 // at the exit point). Each crossing leaves by the nearest face, ties going
 // to x, then y, then z; the step is written with selects so that lanes
 // leaving by different axes do not diverge.
-template <typename R, bool REC>
+template <typename R, bool REC, bool I32>
 __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   constexpr int K = Ahead<R>::K;
   const R p0x = P.p[0], p0y = P.p[1], p0z = P.p[2];
@@ -318,7 +320,8 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   const R tau_star = F.tstar, kx = F.kx;
   int cx = F.cx, cy = F.cy, cz = F.cz;
   bool out = F.out;
-  int64_t cs[K];
+  using Idx = typename std::conditional<I32, uint32_t, int64_t>::type;
+  Idx cs[K];
   R ts[K], ls[K], rh[K];
   uint32_t mv = 0;  // exit axis of step k in bits 2k..2k+1
   int ns = 0;
@@ -336,7 +339,8 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
       }
       R ell = tn - t;
       if (ell < (R)0) ell = (R)0;
-      cs[k] = brick_index(cx, cy, cz, X.nbx, X.nby);
+      if constexpr (I32) cs[k] = brick_index32(cx, cy, cz, X.nbx, X.nby);
+      else cs[k] = brick_index(cx, cy, cz, X.nbx, X.nby);
       ts[k] = t;
       ls[k] = ell;
       ns = k + 1;
@@ -806,9 +810,12 @@ __device__ void stage_model(Ctx<R> &X, const ModelDev &M, unsigned char *lds_raw
   R *rt = full ? (R *)(dt + X.o.dtotal) : (R *)lds_raw;
   int *im = (int *)(rt + X.o.r_total + (X.o.r_total & 1));
   uint32_t *sed = (uint32_t *)(im + M.nl + (M.nl & 1));
-  if (full)
-    for (int i = threadIdx.x; i < X.o.dtotal; i += blockDim.x) dt[i] = M.tab[i];
-  for (int i = threadIdx.x; i < X.o.r_total; i += blockDim.x) rt[i] = ((const R *)M.rtab)[i];
+  if (full) {
+#pragma unroll 8
+    for (int i = threadIdx.x; i < X.o.dtotal; i += blockDim.x) dt[i] = gld(M.tab + i);
+  }
+#pragma unroll 8
+  for (int i = threadIdx.x; i < X.o.r_total; i += blockDim.x) rt[i] = gld((const R *)M.rtab + i);
   for (int i = threadIdx.x; i < M.nl; i += blockDim.x) im[i] = M.imgmap[i];
   const int nsed = (M.ntheta > 0 ? M.ntheta : 1) * M.nl;
   for (int i = threadIdx.x; i < nsed; i += blockDim.x) sed[i] = 0u;
@@ -956,7 +963,7 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
 // interaction or out of the grid; the packet is written back to its own
 // entry. Lanes refill one by one, so flights of different lengths keep the
 // wave busy.
-template <typename R, bool REC>
+template <typename R, bool REC, bool I32>
 __global__ void __launch_bounds__(256)
 k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1009,7 +1016,7 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
       }
       if (!__any(state != 2)) break;
       int r = 0;
-      if (state == 1) r = flight_batch<R, REC>(X, P, F);
+      if (state == 1) r = flight_batch<R, REC, I32>(X, P, F);
       if (r != 0) {
         stat_add(X.st, 4, (unsigned long long)(P.n_cross - c0));
         if (P.n_lucy != l0) stat_add(X.st, 8, (unsigned long long)(P.n_lucy - l0));
@@ -1078,26 +1085,31 @@ size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64
 
 template <typename R, bool REC>
 static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_full, int grid_walk,
-                      size_t lds_full, size_t lds_walk, hipStream_t st) {
+                      size_t lds_full, size_t lds_walk, bool idx32, hipStream_t st) {
   hipLaunchKernelGGL((k_wf_emit<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
                      nmodels, fcur);
-  hipLaunchKernelGGL((k_wf_walk<R, REC>), dim3(grid_walk), dim3(256), lds_walk, st, d_models,
-                     nmodels, fcur);
+  if (idx32)
+    hipLaunchKernelGGL((k_wf_walk<R, REC, true>), dim3(grid_walk), dim3(256), lds_walk, st,
+                       d_models, nmodels, fcur);
+  else
+    hipLaunchKernelGGL((k_wf_walk<R, REC, false>), dim3(grid_walk), dim3(256), lds_walk, st,
+                       d_models, nmodels, fcur);
   hipLaunchKernelGGL((k_wf_interact<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
                      nmodels, fcur);
 }
 
 // One round for nmodels models: plan, emit, walk, interact (stream order).
+// idx32: every model's bricked grid has fewer than 2^32 cells.
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
-                           hipStream_t st) {
+                           bool idx32, hipStream_t st) {
   hipLaunchKernelGGL(k_wf_plan, dim3((nmodels + 63) / 64), dim3(64), 0, st, d_models, nmodels, fcur);
   if (fp64) {
-    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, st);
-    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, st);
+    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
+    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
   } else {
-    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, st);
-    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, st);
+    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
+    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
   }
   return hipGetLastError();
 }
