@@ -897,6 +897,7 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.counter = &ctx->d_ctl->emitted;  // address arithmetic only
   for (int k = 0; k < 2; ++k) M.q[k] = ctx->q[k];
   M.qcap = ctx->qcap;
+  M.qseg = ctx->qcap / NSEG;
   M.stats = ctx->d_stats;
   for (int v = 0; v < ctx->nview; ++v) {
     double th = ctx->views[2 * v] * PI_D / 180.0, ph = ctx->views[2 * v + 1] * PI_D / 180.0;
@@ -923,19 +924,22 @@ static mcrt_status check_opts(mcrt_ctx *ctx, const mcrt_run_opts *o) {
 }
 
 // Packet range of the next launch (device-side, in stream order).
+// Every queue counter of a model back to zero (one block).
+__device__ void wf_zero(WfCtl *c) {
+  uint32_t *w = (uint32_t *)c;
+  for (size_t i = threadIdx.x; i < sizeof(WfCtl) / 4; i += blockDim.x) w[i] = 0u;
+}
+
 __global__ void k_set_range(ModelDev *m, uint64_t first, uint64_t n) {
-  m->first = first;
-  m->n = n;
-  WfCtl *c = m->ctl;
-  c->emitted = 0;
-  c->first = 0;
-  c->n[0] = c->n[1] = 0u;
-  c->work[0] = c->work[1] = c->work[2] = 0u;
-  c->take = 0u;
+  if (threadIdx.x == 0) {
+    m->first = first;
+    m->n = n;
+  }
+  wf_zero(m->ctl);
 }
 
 static mcrt_status set_range(mcrt_ctx *ctx, uint64_t first, uint64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_range, dim3(1), dim3(1), 0, st, ctx->d_model, first, n);
+  hipLaunchKernelGGL(k_set_range, dim3(1), dim3(256), 0, st, ctx->d_model, first, n);
   HIPCHK(hipGetLastError());
   return MCRT_OK;
 }
@@ -947,7 +951,9 @@ static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t
   if (want > (1ull << 26)) want = 1ull << 26;
   uint64_t need = (n + 4095) / 4096 * 4096;
   if (need < 4096) need = 4096;
-  const uint32_t Q = (uint32_t)(want < need ? want : need);
+  uint32_t Q = (uint32_t)(want < need ? want : need);
+  Q = Q / NSEG * NSEG;  // whole segments
+  if (Q < NSEG) Q = NSEG;
   if (Q <= ctx->qcap && ctx->d_q) return MCRT_OK;
   const size_t rs = rsize(ctx);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -987,10 +993,10 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
     HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w,
                            brick_cells(ctx) < (1ull << 32), st));
     if ((r + 1) % every == 0) {
-      HIPCHK(hipMemcpyAsync(ctx->h_ctl, ctx->d_ctl, sizeof(WfCtl), hipMemcpyDeviceToHost, st));
+      HIPCHK(launch_wf_busy(ctx->d_model, 1, fcur, &ctx->d_ctl->busy, st));
+      HIPCHK(hipMemcpyAsync(&ctx->h_ctl->busy, &ctx->d_ctl->busy, 4, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      const WfCtl &c = *ctx->h_ctl;
-      if (c.n[1 - fcur] == 0u && c.emitted >= n) break;
+      if (ctx->h_ctl->busy == 0u) break;
     }
     if (r > (1ull << 32)) return fail(ctx, MCRT_EDEVICE, "transport did not finish");
   }
@@ -1641,14 +1647,7 @@ extern "C" mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_
 
 // Queue counters of every model of a batch back to the start of a launch.
 __global__ void k_wf_reset(const ModelDev *models, int nmodels) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nmodels) return;
-  WfCtl *c = models[m].ctl;
-  c->emitted = 0;
-  c->first = 0;
-  c->n[0] = c->n[1] = 0u;
-  c->work[0] = c->work[1] = c->work[2] = 0u;
-  c->take = 0u;
+  wf_zero(models[blockIdx.x].ctl);
 }
 
 extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
@@ -1699,7 +1698,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
     if (s) return s;
     models[m]->snap_stale = true;
   }
-  hipLaunchKernelGGL(k_wf_reset, dim3((n_models + 63) / 64), dim3(64), 0, st, ctx->d_batch, n_models);
+  hipLaunchKernelGGL(k_wf_reset, dim3(n_models), dim3(256), 0, st, ctx->d_batch, n_models);
   HIPCHK(hipGetLastError());
   const int gfull = ctx->num_cu * (opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2);
   const int gwalk = ctx->num_cu * (opts->walk_blocks_per_cu > 0 ? opts->walk_blocks_per_cu : 4);

@@ -91,13 +91,23 @@ struct QBuf {
   double *mm;                                      // kept for packet records
 };
 
+// Queue counters. Each queue is split into NSEG segments of equal
+// capacity; every counter sits on its own 128-byte line. A wave takes work
+// from and appends to its home segment and moves on only when that one is
+// exhausted or full: device-scope atomics on one address serialise (about
+// 11 ns each on this GPU), on distinct lines they do not.
+constexpr int NSEG = 64;
+constexpr int CLINE = 32;  // uint32 per counter line
+
 struct WfCtl {
   uint64_t emitted;  // packets of the launch started so far (launch-relative)
   uint64_t first;    // launch-relative index of the first packet emitted this round
-  uint32_t n[2];     // packets held in queues 0 and 1
-  uint32_t work[3];  // next queue entry handed out by the emit, walk and interact kernels
   uint32_t take;     // packets emitted this round
-  uint32_t busy;     // batch: models with packets left (first model's counters only)
+  uint32_t busy;     // models with packets left (written by k_wf_busy)
+  uint32_t inq;      // upper bound of this round's flight-ready packets (plan)
+  uint32_t pad[25];
+  uint32_t nseg[2][NSEG][CLINE];  // entries appended to segment g of queue f (clamp to capacity)
+  uint32_t work[3][NSEG][CLINE];  // next entry of segment g handed out by emit, walk, interact
 };
 
 struct ModelDev {
@@ -134,7 +144,7 @@ struct ModelDev {
   QBuf q[2];                  // wavefront queues
   WfCtl *ctl;                 // their counters (counter points at ctl->emitted)
   uint32_t qcap;              // capacity of each queue
-  uint32_t qpad;
+  uint32_t qseg;              // capacity of each of its NSEG segments
 };
 
 // ---------------------------------------------------------------- bricks

@@ -885,41 +885,100 @@ __device__ __forceinline__ R q_load(const ModelDev &M, const QBuf &b, uint32_t i
   return tau;
 }
 
-// One entry per lane in `pred` lanes: wave-aggregated reservation of
-// consecutive queue slots (every lane of the wave must call).
-__device__ __forceinline__ uint32_t wave_reserve(uint32_t *count, bool pred, int lane,
-                                                 uint64_t lt_mask) {
+// ---- segmented queues (see WfCtl)
+__device__ __forceinline__ int home_segment() {
+  return (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (NSEG - 1));
+}
+
+__device__ __forceinline__ uint32_t seg_count(const WfCtl *c, int f, int g, uint32_t S) {
+  const uint32_t v = *(volatile const uint32_t *)&c->nseg[f][g][0];
+  return v < S ? v : S;
+}
+
+// Next chunk [lo, hi) of up to 64 entries for this wave from work counter
+// k, searching the segments from g on; seg(g, beg, cnt) gives the entries
+// of segment g. False once every segment is handed out. Wave-uniform.
+template <typename Seg>
+__device__ __forceinline__ bool seg_grab(WfCtl *c, int k, int &g, int lane, uint32_t &lo,
+                                         uint32_t &hi, Seg seg) {
+  for (int t = 0; t < NSEG; ++t) {
+    uint32_t beg, cnt;
+    seg(g, beg, cnt);
+    if (*(volatile uint32_t *)&c->work[k][g][0] < cnt) {
+      uint32_t base = 0u;
+      if (lane == 0) base = gatomic_add(&c->work[k][g][0], 64u);
+      base = (uint32_t)__shfl((int)base, 0);
+      if (base < cnt) {
+        lo = beg + base;
+        hi = beg + (base + 64u < cnt ? base + 64u : cnt);
+        return true;
+      }
+    }
+    g = (g + 1) & (NSEG - 1);
+  }
+  return false;
+}
+
+// One slot of queue f per lane with pred: appended to segment g, spilling
+// into the next segments when it is full. Every lane of the wave calls;
+// returns the slot of a pred lane. The queue's capacity always covers the
+// packets appended in a round (at most the packets it started with).
+__device__ __forceinline__ uint32_t seg_reserve(WfCtl *c, int f, uint32_t S, int g, bool pred,
+                                                int lane, uint64_t lt_mask) {
   const uint64_t m = __ballot(pred);
-  if (!m) return 0u;
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  uint32_t base = 0u;
-  if (lane == leader) base = gatomic_add(count, (uint32_t)__popcll(m));
-  base = (uint32_t)__shfl((int)base, leader);
-  return base + (uint32_t)__popcll(m & lt_mask);
+  const uint32_t k = (uint32_t)__popcll(m), rank = (uint32_t)__popcll(m & lt_mask);
+  uint32_t slot = 0xFFFFFFFFu, done = 0u;
+  for (int t = 0; t < NSEG && done < k; ++t) {
+    uint32_t base = 0u;
+    if (lane == 0) base = gatomic_add(&c->nseg[f][g][0], k - done);
+    base = (uint32_t)__shfl((int)base, 0);
+    const uint32_t room = base < S ? S - base : 0u;
+    const uint32_t got = room < k - done ? room : k - done;
+    if (pred && rank >= done && rank < done + got) slot = (uint32_t)g * S + base + (rank - done);
+    done += got;
+    g = (g + 1) & (NSEG - 1);
+  }
+  return slot;
 }
 
-// Next block of 64 entries of a work counter for this wave.
-__device__ __forceinline__ uint32_t wave_grab(uint32_t *work, int lane) {
-  uint32_t base = 0u;
-  if (lane == 0) base = gatomic_add(work, 64u);
-  return (uint32_t)__shfl((int)base, 0);
+// Queues the packet at its reserved slot. A slot outside the queue cannot
+// occur (capacity covers a round's appends); were it to, the packet would be
+// ended as killed rather than written out of bounds.
+template <typename R, bool REC>
+__device__ __forceinline__ void store_or_drop(Ctx<R> &X, const QBuf &q, uint32_t slot, Pkt<R> &P,
+                                              R tau) {
+  if (slot < X.M->qcap) {
+    q_store<R, REC>(q, slot, P, tau);
+  } else {
+    P.status = ST_KILLED;
+    finish<R, REC>(X, P, true);
+  }
 }
 
-// Round set-up (one thread per model): how many new packets to start, and
-// the queues that this round empties.
+// Round set-up (one block per model): how many new packets to start, and
+// the counters of the queue this round fills.
 __global__ void k_wf_plan(const ModelDev *__restrict__ models, int nmodels, int fcur) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nmodels) return;
-  const ModelDev &M = models[m];
+  const ModelDev &M = models[blockIdx.x];
   WfCtl *c = M.ctl;
-  const uint64_t left = M.n > c->emitted ? M.n - c->emitted : 0;
-  const uint32_t room = M.qcap > c->n[fcur] ? M.qcap - c->n[fcur] : 0u;
-  const uint32_t take = left < (uint64_t)room ? (uint32_t)left : room;
-  c->first = c->emitted;
-  c->emitted += take;
-  c->take = take;
-  c->n[1 - fcur] = 0u;
-  c->work[0] = c->work[1] = c->work[2] = 0u;
+  __shared__ uint32_t s_held;
+  if (threadIdx.x == 0) s_held = 0u;
+  __syncthreads();
+  for (int g = threadIdx.x; g < NSEG; g += blockDim.x) {
+    const uint32_t v = c->nseg[fcur][g][0];
+    atomicAdd(&s_held, v < M.qseg ? v : M.qseg);
+    c->nseg[1 - fcur][g][0] = 0u;
+    c->work[0][g][0] = c->work[1][g][0] = c->work[2][g][0] = 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t left = M.n > c->emitted ? M.n - c->emitted : 0;
+    const uint32_t room = M.qcap > s_held ? M.qcap - s_held : 0u;
+    const uint32_t take = left < (uint64_t)room ? (uint32_t)left : room;
+    c->first = c->emitted;
+    c->emitted += take;
+    c->take = take;
+    c->inq = s_held + take;
+  }
 }
 
 // Emission: new packets of the launch are started, sample the optical
@@ -935,25 +994,31 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
     const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
     WfCtl *c = M.ctl;
     const uint32_t take = c->take;
-    if (take == 0u || *(volatile uint32_t *)&c->work[0] >= take) continue;
+    if (take == 0u) continue;
     Ctx<R> X;
     stage_model<R>(X, M, lds_raw, s_stat, true);
     const QBuf &qo = M.q[fcur];
-    for (;;) {
-      const uint32_t base = wave_grab(&c->work[0], lane);
-      if (base >= take) break;
-      const uint32_t i = base + (uint32_t)lane;
+    const int home = home_segment();
+    int g = home;
+    // the round's new packets in NSEG equal slices, one per segment
+    auto slice = [&](int s, uint32_t &beg, uint32_t &cnt) {
+      beg = (uint32_t)((uint64_t)take * (uint64_t)s / NSEG);
+      cnt = (uint32_t)((uint64_t)take * (uint64_t)(s + 1) / NSEG) - beg;
+    };
+    uint32_t lo, hi;
+    while (seg_grab(c, 0, g, lane, lo, hi, slice)) {
+      const uint32_t i = lo + (uint32_t)lane;
       Pkt<R> P;
       R tau = (R)-1;
       bool keep = false;
-      if (i < take) {
+      if (i < hi) {
         start_packet<R, REC>(X, P, c->first + i);
         if (P.status == ST_ALIVE) tau = flight_tau<R, REC>(X, P);
         keep = P.status == ST_ALIVE;
         if (!keep) finish<R, REC>(X, P, true);
       }
-      const uint32_t slot = wave_reserve(&c->n[fcur], keep, lane, lt_mask);
-      if (keep && slot < M.qcap) q_store<R, REC>(qo, slot, P, tau);
+      const uint32_t slot = seg_reserve(c, fcur, M.qseg, home, keep, lane, lt_mask);
+      if (keep) store_or_drop<R, REC>(X, qo, slot, P, tau);
     }
     flush_block(X);
   }
@@ -961,8 +1026,8 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
 
 // Voxel walk of every flight-ready packet of queue fcur to its next
 // interaction or out of the grid; the packet is written back to its own
-// entry. Lanes refill one by one, so flights of different lengths keep the
-// wave busy.
+// entry. Lanes refill one by one from a wave-local chunk, so flights of
+// different lengths keep the wave busy.
 template <typename R, bool REC, bool I32>
 __global__ void __launch_bounds__(256)
 k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
@@ -973,45 +1038,52 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
   for (int mm = 0; mm < nmodels; ++mm) {
     const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
     WfCtl *c = M.ctl;
-    const uint32_t n = c->n[fcur];
-    if (n == 0u || *(volatile uint32_t *)&c->work[1] >= n) continue;
+    if (c->inq == 0u) continue;
     Ctx<R> X;
     stage_model<R>(X, M, lds_raw, s_stat, false);
     const QBuf &qi = M.q[fcur];
+    const uint32_t S = M.qseg;
+    auto seg = [&](int s, uint32_t &beg, uint32_t &cnt) {
+      beg = (uint32_t)s * S;
+      cnt = seg_count(c, fcur, s, S);
+    };
     Pkt<R> P;
     Flight<R> F;
     uint32_t mine = 0u;         // queue entry of the lane's packet
     uint32_t c0 = 0u, l0 = 0u;  // crossings and Lucy deposits before this flight
-    // entries are taken from the queue 64 at a time into a wave-local pool
-    // (one atomic per 64 flights); lanes refill from the pool one by one
-    uint32_t pool = 0u, left = 0u;
-    int state = 0;  // 0 needs a packet, 1 walking, 2 no work left
+    uint32_t plo = 0u, phi = 0u;  // wave-local chunk of entries not yet started
+    int g = home_segment();
+    bool more = true;           // some segment may still hand out entries
+    int state = 0;              // 0 needs a packet, 1 walking, 2 no work left
     for (;;) {
       const uint64_t need = __ballot(state == 0);
       if (need) {
         const uint32_t k = (uint32_t)__popcll(need);
         const uint32_t rank = (uint32_t)__popcll(need & lt_mask);
-        uint32_t fresh = 0u;
-        if (k > left) fresh = wave_grab(&c->work[1], lane);
+        const uint32_t avail = phi - plo;
+        uint32_t flo = 0u, fhi = 0u;
+        if (k > avail && more) more = seg_grab(c, 1, g, lane, flo, fhi, seg);
         if (state == 0) {
-          const uint32_t i = rank < left ? pool + rank : fresh + (rank - left);
-          if (i < n) {
+          uint32_t i = 0xFFFFFFFFu;
+          if (rank < avail) i = plo + rank;
+          else if (rank - avail < fhi - flo) i = flo + (rank - avail);
+          if (i != 0xFFFFFFFFu) {
             mine = i;
             const R tau = q_load<R, REC>(M, qi, i, P);
             flight_setup<R>(X, P, F, tau);
             c0 = P.n_cross;
             l0 = P.n_lucy;
             state = 1;
-          } else {
+          } else if (!more) {
             state = 2;
           }
         }
-        if (k > left) {
-          pool = fresh + (k - left);
-          left = 64u - (k - left);
+        if (k > avail) {
+          const uint32_t used = k - avail < fhi - flo ? k - avail : fhi - flo;
+          plo = flo + used;
+          phi = fhi;
         } else {
-          pool += k;
-          left -= k;
+          plo += k;
         }
       }
       if (!__any(state != 2)) break;
@@ -1049,28 +1121,33 @@ k_wf_interact(const ModelDev *__restrict__ models, int nmodels, int fcur) {
   for (int mm = 0; mm < nmodels; ++mm) {
     const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
     WfCtl *c = M.ctl;
-    const uint32_t n = c->n[fcur];
-    if (n == 0u || *(volatile uint32_t *)&c->work[2] >= n) continue;
+    if (c->inq == 0u) continue;
     Ctx<R> X;
     stage_model<R>(X, M, lds_raw, s_stat, true);
     const QBuf &qi = M.q[fcur];
     const QBuf &qo = M.q[1 - fcur];
-    for (;;) {
-      const uint32_t base = wave_grab(&c->work[2], lane);
-      if (base >= n) break;
-      const uint32_t i = base + (uint32_t)lane;
+    const uint32_t S = M.qseg;
+    auto seg = [&](int s, uint32_t &beg, uint32_t &cnt) {
+      beg = (uint32_t)s * S;
+      cnt = seg_count(c, fcur, s, S);
+    };
+    const int home = home_segment();
+    int g = home;
+    uint32_t lo, hi;
+    while (seg_grab(c, 2, g, lane, lo, hi, seg)) {
+      const uint32_t i = lo + (uint32_t)lane;
       Pkt<R> P;
       R tau = (R)-1;
       bool keep = false;
-      if (i < n && gld((const R *)qi.tau + i) >= (R)0) {
+      if (i < hi && gld((const R *)qi.tau + i) >= (R)0) {
         (void)q_load<R, REC>(M, qi, i, P);
         interact<R, REC>(X, P);
         if (P.status == ST_ALIVE) tau = flight_tau<R, REC>(X, P);
         keep = P.status == ST_ALIVE;
         if (!keep) finish<R, REC>(X, P, true);
       }
-      const uint32_t slot = wave_reserve(&c->n[1 - fcur], keep, lane, lt_mask);
-      if (keep && slot < M.qcap) q_store<R, REC>(qo, slot, P, tau);
+      const uint32_t slot = seg_reserve(c, 1 - fcur, S, home, keep, lane, lt_mask);
+      if (keep) store_or_drop<R, REC>(X, qo, slot, P, tau);
     }
     flush_block(X);
   }
@@ -1103,7 +1180,7 @@ static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
                            bool idx32, hipStream_t st) {
-  hipLaunchKernelGGL(k_wf_plan, dim3((nmodels + 63) / 64), dim3(64), 0, st, d_models, nmodels, fcur);
+  hipLaunchKernelGGL(k_wf_plan, dim3(nmodels), dim3(64), 0, st, d_models, nmodels, fcur);
   if (fp64) {
     if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
     else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
@@ -1124,7 +1201,9 @@ __global__ void k_wf_busy(const ModelDev *__restrict__ models, int nmodels, int 
   for (int m = threadIdx.x; m < nmodels; m += blockDim.x) {
     const ModelDev &M = models[m];
     const WfCtl *c = M.ctl;
-    if (c->n[1 - fcur] > 0u || c->emitted < M.n) atomicAdd(&s_busy, 1u);
+    bool live = c->emitted < M.n;
+    for (int g = 0; g < NSEG && !live; ++g) live = seg_count(c, 1 - fcur, g, M.qseg) > 0u;
+    if (live) atomicAdd(&s_busy, 1u);
   }
   __syncthreads();
   if (threadIdx.x == 0) *busy = s_busy;
