@@ -31,15 +31,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(st, ns_thermal, nview):
-    """Bytes the transport must move for its events (FP32 density walk):
-    4 per crossing (density gather), 24 per absorption (count read-modify-
-    write 16 + path-energy read 8), 16 per Lucy deposit and thermal species,
-    8 per scattering and view (event sum read-modify-write, an upper bound:
-    only scatterings at imaged wavelengths write), 16 per MRW step and
-    thermal species. Packet state stays in registers (no queue traffic)."""
-    return (4 * st["crossings"] + 24 * st["absorptions"] + 16 * ns_thermal * st["lucy_deposits"]
-            + 8 * nview * st["scatters"] + 16 * ns_thermal * st["mrw_steps"])
+def walk_bytes(st, ns_thermal):
+    """Bytes the walk kernel must move for one run (FP32): 4 per cell
+    crossing (density gather), 64 per flight to read the queued packet
+    (positions, direction, density, depth: 8 x 4 B; cell and wavelength:
+    4 x 4 B; id 8 B; RNG position and interaction count 2 x 4 B), 64 per
+    flight ending in an interaction to write it back, 4 per escape to free
+    its entry, and 16 per Lucy deposit and thermal species (read-modify-
+    write of the FP64 path energy)."""
+    inter = st["scatters"] + st["absorptions"]
+    flights = inter + st["escaped"]
+    return (4 * st["crossings"] + 64 * flights + 64 * inter + 4 * st["escaped"]
+            + 16 * ns_thermal * st["lucy_deposits"])
 
 
 def main():
@@ -100,13 +103,16 @@ def main():
     def step(seed):
         ctx.reset()
         st = ctx.run_packets(0, N, seed, **opts)
+        ph = ctx.phase_timings()
         sp = ctx.run_pah(seed, **opts)
+        ph2 = ctx.phase_timings()
         ctx.finalize_temperatures()
         ctx.raytrace_device(npx, npy, img=img, sed=sed)
         t = ctx.timings()
         ctx.raytrace_adjoint_device(npx, npy, w_img=w_img, out=grad)
         t2 = ctx.timings()
-        return st, sp, t["rt_fwd_ms"], t2["rt_adj_ms"]
+        phases = {k: ph[k] + ph2[k] for k in ("emit_ms", "walk_ms", "interact_ms", "rounds")}
+        return st, sp, t["rt_fwd_ms"], t2["rt_adj_ms"], phases
 
     for w in range(args.warmup):
         t0 = time.perf_counter()
@@ -117,11 +123,11 @@ def main():
     for k in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, sp, fwd_ms, adj_ms = step(k)
+        st, sp, fwd_ms, adj_ms, phases = step(k)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         times.append(dt)
-        rec.append((st, sp, fwd_ms, adj_ms))
+        rec.append((st, sp, fwd_ms, adj_ms, phases))
         log(f"step {k}: {dt:.3f} s, transport {st['kernel_ms']:.1f} ms, pah {sp['kernel_ms']:.1f} ms,"
             f" rt fwd {fwd_ms:.2f} ms, adj {adj_ms:.2f} ms, crossings {st['crossings']}")
     ms = 1000.0 * float(np.mean(times))
@@ -133,17 +139,22 @@ def main():
     adj = np.mean([r[3] for r in rec]) / 1e3
     rays = len(views) * npx * npy
     ns_th = m.ns - (1 if m.pah_species >= 0 else 0)
-    # k_transport runs twice per step (source packets, PAH re-emission); the
-    # roofline covers both launches, matching the profiler's per-kernel average
-    b_alg = np.mean([algorithmic_bytes(r[0], ns_th, len(views)) + algorithmic_bytes(r[1], ns_th, len(views))
-                     for r in rec])
-    t_k = t_tr + t_pah
+    # roofline of the walk kernel (the largest share of the step): its
+    # algorithmic bytes over its device time, both summed over the source
+    # and PAH runs of a step; launches = rounds
+    b_alg = np.mean([walk_bytes(r[0], ns_th) + walk_bytes(r[1], ns_th) for r in rec])
+    t_walk = np.mean([r[4]["walk_ms"] for r in rec]) / 1e3
+    t_emit = np.mean([r[4]["emit_ms"] for r in rec]) / 1e3
+    t_int = np.mean([r[4]["interact_ms"] for r in rec]) / 1e3
+    n_walk = float(np.mean([r[4]["rounds"] for r in rec]))
     # bytes per launch measured by the committed counter runs, reported only
     # for the workload they were taken on and while the kernel is unchanged
-    traffic = None
-    if N == 100_000_000 and args.grid == 256:
+    traffic = traffic_step = None
+    if N == 100_000_000 and args.grid == 256 and not args.queue_depth:
         from paper_1203_2941_amd import profiling
-        traffic = profiling.read_traffic()
+        traffic_step = profiling.read_traffic()
+        if traffic_step is not None:
+            traffic = traffic_step / n_walk
     out = {
         "metric": METRIC,
         "value": N / (ms / 1e3),
@@ -174,18 +185,23 @@ def main():
         "transport_ms": t_tr * 1e3,
         "pah_pass_ms": t_pah * 1e3,
         "events_per_step": {k: int(v) for k, v in st0.items() if k != "kernel_ms"},
+        "phase_ms": {"emit": t_emit * 1e3, "walk": t_walk * 1e3, "interact": t_int * 1e3,
+                     "rounds": n_walk},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_transport<float, false>",
-            "achieved": b_alg / t_k / 1e9,
+            "kernel": "k_wf_walk<float, false, true>",
+            "achieved": b_alg / t_walk / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
-            "frac": b_alg / t_k / HBM_PEAK,
+            "frac": b_alg / t_walk / HBM_PEAK,
             "traffic": traffic,
-            "traffic_unit": "bytes per launch (L2 <-> memory, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-            "launches_per_step": 2,
-            "avg_launch_ms": t_k * 1e3 / 2,
+            "traffic_unit": "bytes per launch (L2 <-> memory, rocprofv3 FETCH_SIZE + WRITE_SIZE "
+                            "per step over launches_per_step)",
+            "traffic_per_step": traffic_step,
+            "launches_per_step": n_walk,
+            "avg_launch_ms": t_walk * 1e3 / n_walk,
             "algorithmic_bytes_per_step": b_alg,
+            "algorithmic_bytes_per_launch": b_alg / n_walk,
         },
     }
     if not args.no_cpu_baseline:

@@ -213,15 +213,17 @@ mcrt_status mcrt_raytrace_adjoint(mcrt_ctx *ctx, int npx, int npy, const void *r
                                   const void *dL_dimg, const double *dL_dsed, void *dL_drho,
                                   int mem, void *stream);
 
-/* Batched transport: n_models contexts (same device and precision, each
- * with grid, dust and sources set) run packets 0..n_packets[m]-1 with
- * seeds[m] in one persistent launch captured in a HIP graph; blocks pick
- * models with work left and refill their lanes from per-model counters.
- * Each model draws the same Philox streams as its own mcrt_run_packets with
- * the same seed (seeds distinguish the models), so FROZEN batches reproduce
- * per-model runs exactly. Modes FROZEN (n_iter = 1) and BW_TICKET. Tallies are reset first and
- * temperatures finalised (Eq. 4, FP64) inside the same graph. stats
- * (nullable) [n_models]. */
+/* Batched transport: n_models (<= 1024) contexts (same device and
+ * precision, each with grid, dust and sources set) run packets
+ * 0..n_packets[m]-1 with seeds[m]. Every kernel of a wavefront round covers
+ * all models (blocks visit the models in turn and take queue entries of
+ * each); eight rounds are captured in one HIP graph on the library's
+ * stream and replayed on the caller's stream until no model has packets
+ * left. Each model draws the same Philox streams as its own
+ * mcrt_run_packets with the same seed (seeds distinguish the models), so
+ * FROZEN batches reproduce per-model runs exactly. Modes FROZEN (n_iter =
+ * 1) and BW_TICKET. Tallies are reset first and temperatures finalised
+ * (Eq. 4, FP64) afterwards. stats (nullable) [n_models]. */
 mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models, const uint64_t *n_packets,
                            const uint64_t *seeds, const mcrt_run_opts *opts,
                            mcrt_run_stats *stats, void *stream);
@@ -230,6 +232,13 @@ mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models, const uint64_t
  * the last transport launch sequence (HIP events on the call's stream). */
 mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_ms, double *rt_fwd_ms,
                               double *rt_adj_ms);
+
+/* Device time in ms of the emission, walk and interaction kernels summed
+ * over the rounds of the last mcrt_run_packets / mcrt_run_pah call (HIP
+ * events around each kernel on the call's stream), and the number of
+ * rounds. Any pointer may be NULL. Batched runs are not timed by phase. */
+mcrt_status mcrt_phase_timings(const mcrt_ctx *ctx, double *emit_ms, double *walk_ms,
+                               double *interact_ms, uint64_t *rounds);
 
 #ifdef __cplusplus
 }

@@ -308,9 +308,18 @@ class Context:
         self._chk(self.lib.mcrt_last_timings(self.h, C.byref(t[0]), C.byref(t[1]), C.byref(t[2])))
         return {"transport_ms": t[0].value, "rt_fwd_ms": t[1].value, "rt_adj_ms": t[2].value}
 
+    def phase_timings(self):
+        """Emission, walk and interaction kernel time (ms) of the last run, and its rounds."""
+        t = (C.c_double(), C.c_double(), C.c_double())
+        r = C.c_uint64()
+        self._chk(self.lib.mcrt_phase_timings(self.h, C.byref(t[0]), C.byref(t[1]), C.byref(t[2]),
+                                              C.byref(r)))
+        return {"emit_ms": t[0].value, "walk_ms": t[1].value, "interact_ms": t[2].value,
+                "rounds": r.value}
+
 
 def run_batch(contexts, n_packets, seeds, stream=None, **opts):
-    """One persistent launch over many contexts (see mcrt_run_batch)."""
+    """Wavefront rounds over many contexts in one replayed HIP graph (see mcrt_run_batch)."""
     lib = L.lib()
     n = len(contexts)
     arr = (C.c_void_p * n)(*[c.h.value for c in contexts])

@@ -30,7 +30,7 @@ hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, in
                         int nby, hipStream_t st);
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
-                           bool idx32, hipStream_t st);
+                           bool idx32, const hipEvent_t *ev, hipStream_t st);
 size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64);
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
                           hipStream_t st);
@@ -99,6 +99,12 @@ struct mcrt_ctx {
   void *d_rec = nullptr;
   uint64_t rec_cap = 0, rec_n = 0;
   WfCtl *d_ctl = nullptr;   // wavefront queue counters (ctl->emitted is the packet counter)
+  // events bracketing the emission, walk and interaction kernels of every
+  // round since the last phase_reset (4 per round), and the phase totals
+  std::vector<hipEvent_t> pev;
+  size_t pev_used = 0;
+  double t_phase[3] = {0, 0, 0};
+  uint64_t n_rounds = 0;
   WfCtl *h_ctl = nullptr;   // pinned copy read between rounds
   void *d_q = nullptr;      // the two packet queues
   uint32_t qcap = 0;
@@ -239,6 +245,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
     if (p) (void)hipFree(p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+  for (hipEvent_t e : ctx->pev) (void)hipEventDestroy(e);
   if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -975,6 +982,34 @@ static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t
   return MCRT_OK;
 }
 
+// Four fresh events for the next round's phase timing (null when the
+// pool cannot grow; timing is then skipped for that round).
+static const hipEvent_t *phase_events(mcrt_ctx *ctx) {
+  if (ctx->pev_used + 4 > ctx->pev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->pev.push_back(e);
+    }
+  }
+  const hipEvent_t *e = ctx->pev.data() + ctx->pev_used;
+  ctx->pev_used += 4;
+  return e;
+}
+
+// Adds the recorded rounds' kernel times to the phase totals (after a sync).
+static void phase_collect(mcrt_ctx *ctx) {
+  for (size_t i = 0; i + 3 < ctx->pev_used; i += 4) {
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ctx->pev[i + k], ctx->pev[i + k + 1]) == hipSuccess)
+        ctx->t_phase[k] += ms;
+    }
+    ctx->n_rounds++;
+  }
+  ctx->pev_used = 0;
+}
+
 // Transport of the n packets set by set_range: wavefront rounds until every
 // packet has been started and has ended. The host reads the queue counters
 // every few rounds to stop.
@@ -990,12 +1025,14 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
   const int every = 4;
   for (uint64_t r = 0;; ++r) {
     const int fcur = (int)(r & 1);
+    const hipEvent_t *ev = phase_events(ctx);
     HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w,
-                           brick_cells(ctx) < (1ull << 32), st));
+                           brick_cells(ctx) < (1ull << 32), ev, st));
     if ((r + 1) % every == 0) {
       HIPCHK(launch_wf_busy(ctx->d_model, 1, fcur, &ctx->d_ctl->busy, st));
       HIPCHK(hipMemcpyAsync(&ctx->h_ctl->busy, &ctx->d_ctl->busy, 4, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      phase_collect(ctx);
       if (ctx->h_ctl->busy == 0u) break;
     }
     if (r > (1ull << 32)) return fail(ctx, MCRT_EDEVICE, "transport did not finish");
@@ -1065,6 +1102,9 @@ static mcrt_status prepare_run(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n
   s = set_ssca_unit(ctx, ctx->xi, st);
   if (s) return s;
   HIPCHK(fill<unsigned long long>(ctx->d_stats, 0ull, NSTAT, st));
+  ctx->t_phase[0] = ctx->t_phase[1] = ctx->t_phase[2] = 0.0;
+  ctx->n_rounds = 0;
+  ctx->pev_used = 0;
   return MCRT_OK;
 }
 
@@ -1643,6 +1683,16 @@ extern "C" mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_
   return MCRT_OK;
 }
 
+extern "C" mcrt_status mcrt_phase_timings(const mcrt_ctx *ctx, double *emit_ms, double *walk_ms,
+                                          double *interact_ms, uint64_t *rounds) {
+  if (!ctx) return MCRT_EINVAL;
+  if (emit_ms) *emit_ms = ctx->t_phase[0];
+  if (walk_ms) *walk_ms = ctx->t_phase[1];
+  if (interact_ms) *interact_ms = ctx->t_phase[2];
+  if (rounds) *rounds = ctx->n_rounds;
+  return MCRT_OK;
+}
+
 // ------------------------------------------------------------------ batch
 
 // Queue counters of every model of a batch back to the start of a launch.
@@ -1714,7 +1764,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   hipError_t le = hipSuccess;
   for (int r = 0; r < ROUNDS && le == hipSuccess; ++r)
     le = launch_wf_round(ctx->d_batch, n_models, ctx->fp64, false, r & 1, gfull, gwalk, lds, lds_w,
-                         idx32, cs_);
+                         idx32, nullptr, cs_);
   if (le == hipSuccess) le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, cs_);
   hipError_t ce = hipStreamEndCapture(cs_, &graph);
   if (le != hipSuccess || ce != hipSuccess) {

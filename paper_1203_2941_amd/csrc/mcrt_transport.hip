@@ -1162,31 +1162,37 @@ size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64
 
 template <typename R, bool REC>
 static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_full, int grid_walk,
-                      size_t lds_full, size_t lds_walk, bool idx32, hipStream_t st) {
+                      size_t lds_full, size_t lds_walk, bool idx32, const hipEvent_t *ev,
+                      hipStream_t st) {
+  if (ev) (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((k_wf_emit<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
                      nmodels, fcur);
+  if (ev) (void)hipEventRecord(ev[1], st);
   if (idx32)
     hipLaunchKernelGGL((k_wf_walk<R, REC, true>), dim3(grid_walk), dim3(256), lds_walk, st,
                        d_models, nmodels, fcur);
   else
     hipLaunchKernelGGL((k_wf_walk<R, REC, false>), dim3(grid_walk), dim3(256), lds_walk, st,
                        d_models, nmodels, fcur);
+  if (ev) (void)hipEventRecord(ev[2], st);
   hipLaunchKernelGGL((k_wf_interact<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
                      nmodels, fcur);
+  if (ev) (void)hipEventRecord(ev[3], st);
 }
 
 // One round for nmodels models: plan, emit, walk, interact (stream order).
-// idx32: every model's bricked grid has fewer than 2^32 cells.
+// idx32: every model's bricked grid has fewer than 2^32 cells. ev (null or
+// four events) brackets the emission, walk and interaction kernels.
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
-                           bool idx32, hipStream_t st) {
+                           bool idx32, const hipEvent_t *ev, hipStream_t st) {
   hipLaunchKernelGGL(k_wf_plan, dim3(nmodels), dim3(64), 0, st, d_models, nmodels, fcur);
   if (fp64) {
-    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
-    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
+    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, ev, st);
+    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, ev, st);
   } else {
-    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
-    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, st);
+    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, ev, st);
+    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, ev, st);
   }
   return hipGetLastError();
 }

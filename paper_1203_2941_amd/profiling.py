@@ -29,8 +29,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 TRANSPORT_SOURCES = ("csrc/mcrt_transport.hip", "csrc/mcrt_internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_transport_torus256_1e8_traffic.md")
-TRANSPORT_KERNEL = "k_transport<float, false>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_wf_walk_torus256_1e8_traffic.md")
+TRANSPORT_KERNEL = "k_wf_walk<float, false, true>"
 CALIB_KERNEL = "MulFunctor"
 
 
@@ -86,10 +86,10 @@ def traffic_md(fetch_db: str, write_db: str, calib_mib: int, cmd: str) -> str:
     per = [f * sf + w * sw for f, w in zip(fetch, write)]
     mean = sum(per) / len(per)
     lines = [
-        "# HBM traffic of the transport kernel: 256^3 clumpy torus, 1e8 packets, FP32",
+        "# HBM traffic of the walk kernel: 256^3 clumpy torus, 1e8 packets, FP32",
         "",
-        "Two counter runs of one bench step each (source-packet launch, then the",
-        "PAH re-emission launch), FETCH_SIZE and WRITE_SIZE in separate runs. A",
+        "Two counter runs of one bench step each (all walk launches of the source",
+        "and PAH runs), FETCH_SIZE and WRITE_SIZE in separate runs. A",
         f"{calib_mib} MiB elementwise copy in the same process calibrates each counter:",
         f"it read {cal_f[0]:.6g} FETCH_SIZE units and wrote {cal_w[0]:.6g} WRITE_SIZE",
         f"units, so one unit is {sf:.6g} B read / {sw:.6g} B written.",
@@ -105,6 +105,10 @@ def traffic_md(fetch_db: str, write_db: str, calib_mib: int, cmd: str) -> str:
     ]
     for i, (f, w) in enumerate(zip(fetch, write)):
         lines.append(f"| {i} | {f:.6g} | {w:.6g} | {f * sf:.6g} | {w * sw:.6g} | {per[i]:.6g} |")
+    if len(per) > 12:
+        lines = lines[:-len(per)] + [
+            f"| all {len(per)} | {sum(fetch):.6g} | {sum(write):.6g} | {sum(fetch) * sf:.6g} | "
+            f"{sum(write) * sw:.6g} | {sum(per):.6g} |"]
     lines += [
         "",
         f"traffic_bytes_per_launch: {mean:.6g}",
@@ -117,14 +121,15 @@ def traffic_md(fetch_db: str, write_db: str, calib_mib: int, cmd: str) -> str:
 
 
 def read_traffic(path: str = TRAFFIC_FILE):
-    """Measured bytes per transport launch, or None when the summary is
-    missing or was taken from other transport sources."""
+    """Measured bytes of the walk kernel per bench step (all its launches),
+    or None when the summary is missing or was taken from other transport
+    sources."""
     try:
         with open(path) as f:
             text = f.read()
     except OSError:
         return None
-    m = re.search(r"^traffic_bytes_per_launch: (\S+)$", text, re.M)
+    m = re.search(r"^traffic_bytes_per_step: (\S+)$", text, re.M)
     d = re.search(r"^source_sha256: (\S+)$", text, re.M)
     if not m or not d or d.group(1) != source_digest():
         return None
