@@ -233,6 +233,16 @@ mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models, const uint64_t
 mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_ms, double *rt_fwd_ms,
                               double *rt_adj_ms);
 
+/* n draws of the wavelength bin that species `species` (thermal) re-emits
+ * at temperature T (K) after an absorption, taken exactly as the transport
+ * takes them: mode MCRT_FROZEN gives Eq. 5 (weights w kabs B), the B&W
+ * modes Eq. 10 (weights w kabs dB/dT). FP64 contexts walk the inverse CDF;
+ * FP32 contexts sample by rejection from a tabulated envelope (exact in
+ * distribution). Draw i uses Philox stream (seed, i, tag 7). counts: host
+ * [n_lambda], overwritten. For validation of the sampler. */
+mcrt_status mcrt_sample_reemission(mcrt_ctx *ctx, int species, int mode, double T, uint64_t n,
+                                   uint64_t seed, uint64_t *counts);
+
 /* Device time in ms of the emission, walk and interaction kernels summed
  * over the rounds of the last mcrt_run_packets / mcrt_run_pah call (HIP
  * events around each kernel on the call's stream), and the number of

@@ -308,6 +308,16 @@ class Context:
         self._chk(self.lib.mcrt_last_timings(self.h, C.byref(t[0]), C.byref(t[1]), C.byref(t[2])))
         return {"transport_ms": t[0].value, "rt_fwd_ms": t[1].value, "rt_adj_ms": t[2].value}
 
+    def sample_reemission(self, species, T, n, seed=0, mode="bw_ticket"):
+        """Histogram [n_lambda] of n re-emission bins at temperature T (see
+        mcrt_sample_reemission)."""
+        modes = {"frozen": L.FROZEN, "bw_epoch": L.BW_EPOCH, "bw_ticket": L.BW_TICKET}
+        out = np.zeros(self.nl, dtype=np.uint64)
+        self._chk(self.lib.mcrt_sample_reemission(
+            self.h, int(species), modes[mode] if isinstance(mode, str) else int(mode), float(T),
+            int(n), int(seed), out.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return out
+
     def phase_timings(self):
         """Emission, walk and interaction kernel time (ms) of the last run, and its rounds."""
         t = (C.c_double(), C.c_double(), C.c_double())

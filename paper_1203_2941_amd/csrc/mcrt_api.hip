@@ -34,6 +34,9 @@ hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, boo
 size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64);
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
                           hipStream_t st);
+hipError_t launch_sample_reem(const ModelDev *d, bool fp64, int s, double T, uint64_t n,
+                              uint64_t seed, unsigned long long *counts, size_t lds,
+                              hipStream_t st);
 hipError_t launch_vox_torus(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
                             int ncl, const double *dC, double r_clump, double rho_cl,
                             double rho_int, double r_in, double r_out, double s1, void *rho,
@@ -82,6 +85,8 @@ struct mcrt_ctx {
   void *d_rtab = nullptr;
   int32_t *d_imgmap = nullptr;
   double *d_herm = nullptr;
+  float *d_rej_pe = nullptr;   // FP32 re-emission proposal tables (alias prob, envelope)
+  uint8_t *d_rej_al = nullptr;
   size_t tab_cap = 0, rtab_cap = 0;
   bool tables_ok = false;
   // state
@@ -236,7 +241,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_k, ctx->d_epath,
+  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_rej_pe, ctx->d_rej_al, ctx->d_k, ctx->d_epath,
                 ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
                 ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_ctl, ctx->d_q, ctx->d_stats,
                 ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
@@ -336,6 +341,32 @@ static mcrt_status zero_epoch(mcrt_ctx *ctx, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- tables
+
+// Vose's alias table for weights v[0..n-1] (all >= 0): prob[j] in [0, 1] and
+// alias[j] such that bin j0 drawn uniformly, kept when a second uniform is
+// below prob[j0] and replaced by alias[j0] otherwise, has probability
+// v_j / sum v. A zero sum gives a uniform table.
+static void alias_table(const double *v, int n, float *prob, uint8_t *alias) {
+  double sum = 0.0;
+  for (int j = 0; j < n; ++j) sum += v[j];
+  std::vector<double> q(n);
+  std::vector<int> small, large;
+  for (int j = 0; j < n; ++j) {
+    q[j] = sum > 0.0 ? v[j] * n / sum : 1.0;
+    (q[j] < 1.0 ? small : large).push_back(j);
+  }
+  while (!small.empty() && !large.empty()) {
+    const int l = small.back(), g = large.back();
+    small.pop_back();
+    large.pop_back();
+    prob[l] = (float)q[l];
+    alias[l] = (uint8_t)g;
+    q[g] = (q[g] + q[l]) - 1.0;
+    (q[g] < 1.0 ? small : large).push_back(g);
+  }
+  for (int j : small) { prob[j] = 1.0f; alias[j] = (uint8_t)j; }
+  for (int j : large) { prob[j] = 1.0f; alias[j] = (uint8_t)j; }
+}
 
 static double h_planck(double nu, double T) {
   if (!(T > 0.0)) return 0.0;
@@ -509,6 +540,43 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
       hh[4 + 2 * k] = p / (T * dp);  // d ln T / d ln Phi
     }
   }
+  // FP32 walk: re-emission proposals. For each mode (0: Eq. 5, weights
+  // w kabs B; 1: Eq. 10, weights w kabs dB/dT), species and ln T bin, the
+  // spectrum at the bin's upper temperature as an envelope (B and dB/dT grow
+  // with T at fixed nu, so it bounds the spectrum anywhere in the bin; 2e-4
+  // headroom covers FP32 evaluation on the GPU) and its alias table.
+  std::vector<float> rej_pe;
+  std::vector<uint8_t> rej_al;
+  if (!ctx->fp64 && nl <= 256) {
+    const size_t per = (size_t)NK_REJ * nl, tot = 2 * (size_t)ns * per;
+    rej_pe.assign(2 * tot, 0.0f);
+    rej_al.assign(tot, 0);
+    const double lt0 = std::log(T_TAB_MIN), dlt = (std::log(T_MAX) - lt0) / NK_REJ;
+    std::vector<double> env(nl);
+    std::vector<float> prob(nl);
+    std::vector<uint8_t> al(nl);
+    for (int mode = 0; mode < 2; ++mode)
+      for (int s = 0; s < ns; ++s)
+        for (int k = 0; k < NK_REJ; ++k) {
+          const double T = std::exp(lt0 + (k + 1) * dlt);
+          for (int j = 0; j < nl; ++j) {
+            const double x = H_PL * nu[j] / (K_BO * T);
+            double d = 0.0;
+            if (x <= 700.0) {
+              const double em = std::expm1(x), B = t[o.a + j] / em;
+              d = mode == 0 ? B : B * (x / T) * (1.0 + 1.0 / em);
+            }
+            env[j] = t[o.wk + s * nl + j] * d * (1.0 + 2e-4);
+          }
+          alias_table(env.data(), nl, prob.data(), al.data());
+          const size_t base = ((size_t)mode * ns + s) * per + (size_t)k * nl;
+          for (int j = 0; j < nl; ++j) {
+            rej_pe[2 * (base + j)] = prob[j];
+            rej_pe[2 * (base + j) + 1] = (float)env[j];
+            rej_al[base + j] = al[j];
+          }
+        }
+  }
   std::vector<int32_t> im(nl, -1);
   for (int q = 0; q < ctx->nimg; ++q) im[ctx->img_idx[q]] = q;
   mcrt_ctx *c = ctx;
@@ -524,6 +592,12 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
   HIPCHK(dev_alloc((void **)&ctx->d_imgmap, (size_t)nl * 4));
   HIPCHK(dev_alloc((void **)&ctx->d_herm, herm.size() * 8));
   HIPCHK(hipMemcpy(ctx->d_herm, herm.data(), herm.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(dev_alloc((void **)&ctx->d_rej_pe, rej_pe.size() * 4));
+  HIPCHK(dev_alloc((void **)&ctx->d_rej_al, rej_al.size()));
+  if (!rej_pe.empty()) {
+    HIPCHK(hipMemcpy(ctx->d_rej_pe, rej_pe.data(), rej_pe.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_rej_al, rej_al.data(), rej_al.size(), hipMemcpyHostToDevice));
+  }
   HIPCHK(hipMemcpy(ctx->d_tab, t.data(), tb, hipMemcpyHostToDevice));
   if (ctx->fp64) {
     HIPCHK(hipMemcpy(ctx->d_rtab, r.data(), rb, hipMemcpyHostToDevice));
@@ -894,6 +968,8 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.rtab = ctx->d_rtab;
   M.imgmap = ctx->d_imgmap;
   M.herm = ctx->d_herm;
+  M.rej_pe = ctx->d_rej_pe;
+  M.rej_al = ctx->d_rej_al;
   for (int q = 0; q < ctx->nimg; ++q) M.img_j[q] = ctx->img_idx[q];
   M.k = ctx->d_k; M.epath = ctx->d_epath; M.T = ctx->d_T; M.esnap = ctx->d_esnap; M.tt = ctx->d_tt;
   M.dirty = ctx->d_dirty; M.kpah = ctx->d_kpah; M.kpah_prefix = ctx->d_prefix;
@@ -1680,6 +1756,36 @@ extern "C" mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_
   if (transport_ms) *transport_ms = ctx->t_transport;
   if (rt_fwd_ms) *rt_fwd_ms = ctx->have_f ? event_ms(ctx->evf0, ctx->evf1) : 0.0;
   if (rt_adj_ms) *rt_adj_ms = ctx->have_a ? event_ms(ctx->eva0, ctx->eva1) : 0.0;
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_sample_reemission(mcrt_ctx *ctx, int species, int mode, double T,
+                                              uint64_t n, uint64_t seed, uint64_t *counts) {
+  mcrt_status s = ready(ctx);
+  if (s) return s;
+  if (species < 0 || species >= ctx->ns || species == ctx->pah)
+    return fail(ctx, MCRT_EINVAL, "species must be a thermal species");
+  if (mode < MCRT_FROZEN || mode > MCRT_BW_TICKET) return fail(ctx, MCRT_EINVAL, "bad mode");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(ctx, MCRT_EINVAL, "T must be > 0");
+  if (!counts) return fail(ctx, MCRT_EINVAL, "counts is NULL");
+  size_t lds = transport_lds_bytes(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows, ctx->ntheta, ctx->fp64);
+  if (lds > ctx->lds_max) return fail(ctx, MCRT_EINVAL, "tables exceed LDS");
+  HIPCHK(hipSetDevice(ctx->device));
+  mcrt_run_opts o{};
+  o.mode = mode;
+  o.sed_theta_bins = ctx->ntheta > 0 ? ctx->ntheta : 1;
+  ModelDev M;
+  fill_model(ctx, M, &o, 0);
+  M.ntheta = o.sed_theta_bins;
+  unsigned long long *d_counts = nullptr;
+  HIPCHK(hipMalloc((void **)&d_counts, (size_t)ctx->nl * 8));
+  hipError_t e = hipMemset(d_counts, 0, (size_t)ctx->nl * 8);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_model, &M, sizeof M, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_sample_reem(ctx->d_model, ctx->fp64, species, T, n, seed, d_counts, lds, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(counts, d_counts, (size_t)ctx->nl * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(d_counts);
+  if (e != hipSuccess) return fail(ctx, MCRT_EDEVICE, "re-emission sampling: %s", hipGetErrorString(e));
   return MCRT_OK;
 }
 

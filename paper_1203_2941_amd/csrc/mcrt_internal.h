@@ -19,6 +19,7 @@ constexpr int NT_TAB = 256;          // points of the ln(Phi) vs ln(T) table per
 constexpr int NH_TAB = 2048;         // nodes of the Hermite table ln T(ln Phi) per species
 constexpr double T_HERM_MIN = 3.0;   // K, lower end of the Hermite table
 constexpr double T_TAB_MIN = 1.0;    // K
+constexpr int NK_REJ = 512;          // T bins of the FP32 re-emission proposal tables
 constexpr double T_MAX = 1.0e5;      // K, upper end of the Eq. 4 search
 constexpr double T_FLOOR = 10.0;     // K, emission temperature of a cell with T = 0
 constexpr double H_PL = 6.62607015e-27;
@@ -126,6 +127,8 @@ struct ModelDev {
   const void *rtab;           // packed R table
   const int32_t *imgmap;      // [nl] -> imaged index or -1
   const double *herm;         // [ns][3 + 2*NH_TAB]: u0, du, n, then (ln T, dlnT/dlnPhi) per node
+  const float *rej_pe;        // FP32 walk: [2 modes][ns][NK_REJ][nl] (alias prob, envelope) pairs
+  const uint8_t *rej_al;      // FP32 walk: [2 modes][ns][NK_REJ][nl] alias bins
   int32_t img_j[MAX_IMG];     // wavelength index of each imaged wavelength
   uint64_t *k;                // [ns][cells]
   double *epath;              // [ns][cells]

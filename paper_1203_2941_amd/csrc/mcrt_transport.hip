@@ -615,6 +615,49 @@ __device__ __forceinline__ int pick_thermal(const Ctx<R> &X, int s, double T, R 
 // End of a packet: escape tally, status counters and its record. The
 // crossings and Lucy deposits of the packet are counted here unless the
 // caller counts them per flight (walk_tallied).
+// Re-emission bin in the FP32 walk by rejection: a proposal from the alias
+// table of T's ln T bin (whose spectrum, taken at the bin's upper edge,
+// bounds the spectrum at T), accepted with probability p_j(T) / env_j.
+// Exact in distribution; about 1.1 proposals per absorption over 512 bins
+// from 1 K to 1e5 K. -1 outside the table or after 64 rejections (the
+// caller then walks the inverse CDF).
+__device__ __forceinline__ int rej_thermal(const Ctx<float> &X, int s, double T, Rng &rng) {
+  const ModelDev &M = *X.M;
+  if (!M.rej_pe || !(T > 0.0)) return -1;
+  const int nl = M.nl;
+  const double lt0 = log(T_TAB_MIN), dlt = (log(T_MAX) - lt0) / NK_REJ;
+  const double kf = (log(T) - lt0) / dlt;
+  if (!(kf >= 0.0 && kf < (double)NK_REJ)) return -1;
+  const int k = (int)kf;
+  const size_t base = ((size_t)(M.mode == M_FROZEN ? 0 : 1) * M.ns + s) * ((size_t)NK_REJ * nl) +
+                      (size_t)k * nl;
+  const float *pe = M.rej_pe + 2 * base;
+  const uint8_t *al = M.rej_al + base;
+  const float *wk = X.rt + X.o.r_wk + s * nl;
+  const float *hnu = X.rt + X.o.r_hnu;
+  const float *a = X.rt + X.o.r_a;
+  const float rkT = (float)(1.0 / (K_BO * T)), rT = (float)(1.0 / T);
+  const bool bw = M.mode != M_FROZEN;
+  for (int t = 0; t < 64; ++t) {
+    const float u1 = rng_u<float>(rng), u2 = rng_u<float>(rng);
+    const float xf = u1 * (float)nl;
+    int j = (int)xf;
+    if (j > nl - 1) j = nl - 1;
+    const float fr = xf - (float)j;
+    if (!(fr < gld(pe + 2 * j))) j = gld(al + j);
+    const float env = gld(pe + 2 * j + 1);
+    const float x = hnu[j] * rkT;
+    float p = 0.0f;
+    if (x <= 80.0f) {
+      const float em = x < 0.03f ? x * (1.0f + x * (0.5f + x * (1.0f / 6.0f))) : __expf(x) - 1.0f;
+      const float r = __builtin_amdgcn_rcpf(em);
+      p = bw ? wk[j] * a[j] * r * x * rT * (1.0f + r) : wk[j] * a[j] * r;
+    }
+    if (u2 * env <= p) return j;
+  }
+  return -1;
+}
+
 template <typename R, bool REC>
 __device__ void finish(Ctx<R> &X, Pkt<R> &P, bool walk_tallied = false) {
   const ModelDev &M = *X.M;
@@ -778,9 +821,14 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
         T = mode_T(X, s, c, (double)rho);
       }
       if (M.mode == M_BW_EPOCH) M.dirty[c] = 1;
-      R ul = rng_u<R>(P.rng);
+      int jr = -1;
+      if constexpr (sizeof(R) == 4) jr = rej_thermal(X, s, T, P.rng);
+      if (jr < 0) {
+        R ul = rng_u<R>(P.rng);
+        jr = pick_thermal<R, REC>(X, s, T, ul, P.mm);
+      }
+      P.j = jr;
       double uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
-      P.j = pick_thermal<R, REC>(X, s, T, ul, P.mm);
       iso_dir<R>(uph, umu, P.d);
     }
   }
@@ -1218,6 +1266,48 @@ __global__ void k_wf_busy(const ModelDev *__restrict__ models, int nmodels, int 
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_wf_busy, dim3(1), dim3(256), 0, st, d_models, nmodels, fcur, busy);
+  return hipGetLastError();
+}
+
+// n draws of the re-emission bin of species s at temperature T, exactly as
+// an absorption in the transport takes them (FP32: rejection with the
+// inverse CDF as fallback; FP64: the inverse CDF), counted per bin.
+template <typename R>
+__global__ void __launch_bounds__(256) k_sample_reem(const ModelDev *__restrict__ md, int s, double T,
+                                                     uint64_t n, uint64_t seed,
+                                                     unsigned long long *counts) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ unsigned long long s_stat[NSTAT];
+  __shared__ unsigned int hist[256];
+  const ModelDev &M = *md;
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0u;
+  Ctx<R> X;
+  stage_model<R>(X, M, lds_raw, s_stat, true);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    Rng rng;
+    rng_init(rng, seed, i, 0u, 0u, 7u);
+    int j = -1;
+    if constexpr (sizeof(R) == 4) j = rej_thermal(X, s, T, rng);
+    if (j < 0) {
+      double mm = 1e300;
+      const R u = rng_u<R>(rng);
+      j = pick_thermal<R, false>(X, s, T, u, mm);
+    }
+    atomicAdd(&hist[j], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < M.nl; i += blockDim.x)
+    if (hist[i]) atomicAdd(&counts[i], (unsigned long long)hist[i]);
+}
+
+hipError_t launch_sample_reem(const ModelDev *d, bool fp64, int s, double T, uint64_t n,
+                              uint64_t seed, unsigned long long *counts, size_t lds,
+                              hipStream_t st) {
+  if (fp64)
+    hipLaunchKernelGGL(k_sample_reem<double>, dim3(1024), dim3(256), lds, st, d, s, T, n, seed, counts);
+  else
+    hipLaunchKernelGGL(k_sample_reem<float>, dim3(1024), dim3(256), lds, st, d, s, T, n, seed, counts);
   return hipGetLastError();
 }
 
