@@ -311,6 +311,7 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   const R p0x = P.p[0], p0y = P.p[1], p0z = P.p[2];
   const R dx = P.d[0], dy = P.d[1], dz = P.d[2];
   const int sx = dx > (R)0 ? 1 : -1, sy = dy > (R)0 ? 1 : -1, sz = dz > (R)0 ? 1 : -1;
+  const R fsx = (R)sx, fsy = (R)sy, fsz = (R)sz;
   // the flight state is worked on in locals (selects between struct members
   // would otherwise become address arithmetic and push the struct to scratch)
   R tx = F.tx, ty = F.ty, tz = F.tz, ex = F.ex, ey = F.ey, ez = F.ez;
@@ -352,12 +353,27 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
       cz += b2 ? sz : 0;
       out = (unsigned)cx >= (unsigned)X.nx || (unsigned)cy >= (unsigned)X.ny ||
             (unsigned)cz >= (unsigned)X.nz;
-      const R e = (b2 ? ez : (b1 ? ey : ex)) + (R)(b2 ? sz : (b1 ? sy : sx));
-      const R tf = face_t<R>(X, e, b2 ? qz : (b1 ? qy : qx), b2 ? ogz : (b1 ? ogy : ogx),
-                             b2 ? p0z : (b1 ? p0y : p0x), b2 ? iz : (b1 ? iy : ix));
-      ex = mx ? e : ex; tx = mx ? tf : tx;
-      ey = my ? e : ey; ty = my ? tf : ty;
-      ez = b2 ? e : ez; tz = b2 ? tf : tz;
+      if constexpr (sizeof(R) == 4) {
+        // FP32: step the face index of the moved axis, then work out all
+        // three next-face distances (two operations each) and keep the
+        // moved axis' one; cheaper than selecting the operands
+        ex += mx ? fsx : 0.0f;
+        ey += my ? fsy : 0.0f;
+        ez += b2 ? fsz : 0.0f;
+        const R nxt = face_t<R>(X, ex, qx, ogx, p0x, ix);
+        const R nyt = face_t<R>(X, ey, qy, ogy, p0y, iy);
+        const R nzt = face_t<R>(X, ez, qz, ogz, p0z, iz);
+        tx = mx ? nxt : tx;
+        ty = my ? nyt : ty;
+        tz = b2 ? nzt : tz;
+      } else {
+        const R e = (b2 ? ez : (b1 ? ey : ex)) + (R)(b2 ? sz : (b1 ? sy : sx));
+        const R tf = face_t<R>(X, e, b2 ? qz : (b1 ? qy : qx), b2 ? ogz : (b1 ? ogy : ogx),
+                               b2 ? p0z : (b1 ? p0y : p0x), b2 ? iz : (b1 ? iy : ix));
+        ex = mx ? e : ex; tx = mx ? tf : tx;
+        ey = my ? e : ey; ty = my ? tf : ty;
+        ez = b2 ? e : ez; tz = b2 ? tf : tz;
+      }
     }
   }
   F.tx = tx; F.ty = ty; F.tz = tz; F.ex = ex; F.ey = ey; F.ez = ez;
