@@ -31,7 +31,9 @@ hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, in
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
                            bool idx32, const hipEvent_t *ev, hipStream_t st);
-size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64);
+size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, int occ_words, bool fp64);
+hipError_t launch_occ(bool fp64, const void *rho, uint32_t *occ, int nx, int ny, int nz, int osh,
+                      int obx, int oby, int obz, hipStream_t st);
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
                           hipStream_t st);
 hipError_t launch_sample_reem(const ModelDev *d, bool fp64, int s, double T, uint64_t n,
@@ -64,6 +66,8 @@ struct mcrt_ctx {
   void *d_rho = nullptr;
   void *d_rho_b = nullptr;  // density in 4x4x4 bricks for the walk
   int nbx = 0, nby = 0, nbz = 0;
+  uint32_t *d_occ = nullptr;  // super-brick occupancy bits for the walk
+  int osh = 0, obx = 0, oby = 0, obz = 0, ow = 0;
   // dust
   bool has_dust = false;
   int nl = 0, ns = 0, pah = -1, nrows = 0;
@@ -241,7 +245,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_rej_pe, ctx->d_rej_al, ctx->d_k, ctx->d_epath,
+  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_occ, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_rej_pe, ctx->d_rej_al, ctx->d_k, ctx->d_epath,
                 ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
                 ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_ctl, ctx->d_q, ctx->d_stats,
                 ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
@@ -614,8 +618,8 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
 
 // ------------------------------------------------------------------- set
 
-// Bricked copy of the density read by the walk; rebuilt whenever the
-// density changes.
+// Bricked copy of the density read by the walk, and the occupancy bits of
+// its super-bricks; rebuilt whenever the density changes.
 static uint64_t brick_cells(const mcrt_ctx *ctx) {
   return (uint64_t)ctx->nbx * ctx->nby * ctx->nbz * 64;
 }
@@ -629,6 +633,23 @@ static mcrt_status build_brick(mcrt_ctx *ctx) {
   HIPCHK(hipMemset(ctx->d_rho_b, 0, nb * rsize(ctx)));
   HIPCHK(launch_brick(ctx->fp64, ctx->d_rho, ctx->d_rho_b, ctx->nx, ctx->ny, ctx->nz, ctx->nbx,
                       ctx->nby, 0));
+  // smallest super-brick side 2^osh >= 4 whose bits fit OCC_MAX_WORDS words
+  int osh = 2;
+  for (;; ++osh) {
+    const uint64_t bx = ((uint64_t)ctx->nx + (1u << osh) - 1) >> osh;
+    const uint64_t by = ((uint64_t)ctx->ny + (1u << osh) - 1) >> osh;
+    const uint64_t bz = ((uint64_t)ctx->nz + (1u << osh) - 1) >> osh;
+    if ((bx * by * bz + 31) / 32 <= (uint64_t)OCC_MAX_WORDS) {
+      ctx->obx = (int)bx; ctx->oby = (int)by; ctx->obz = (int)bz;
+      break;
+    }
+  }
+  ctx->osh = osh;
+  const uint64_t nsb = (uint64_t)ctx->obx * ctx->oby * ctx->obz;
+  ctx->ow = (int)((nsb + 31) / 32);
+  HIPCHK(dev_alloc((void **)&ctx->d_occ, (nsb + 63) / 64 * 8));
+  HIPCHK(launch_occ(ctx->fp64, ctx->d_rho, ctx->d_occ, ctx->nx, ctx->ny, ctx->nz, osh, ctx->obx,
+                    ctx->oby, ctx->obz, 0));
   HIPCHK(hipDeviceSynchronize());
   return MCRT_OK;
 }
@@ -964,6 +985,8 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.rho = ctx->d_rho;
   M.rho_b = ctx->d_rho_b;
   M.nbx = ctx->nbx; M.nby = ctx->nby; M.nbz = ctx->nbz;
+  M.occ = ctx->d_occ;
+  M.osh = ctx->osh; M.obx = ctx->obx; M.oby = ctx->oby; M.ow = ctx->ow;
   M.tab = ctx->d_tab;
   M.rtab = ctx->d_rtab;
   M.imgmap = ctx->d_imgmap;
@@ -1092,9 +1115,10 @@ static void phase_collect(mcrt_ctx *ctx) {
 static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n,
                                     hipStream_t st) {
   size_t lds = transport_lds_bytes(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows, ctx->ntheta, ctx->fp64);
-  size_t lds_w = walk_lds_bytes(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows, ctx->ntheta, ctx->fp64);
-  if (lds > ctx->lds_max)
-    return fail(ctx, MCRT_EINVAL, "tables need %zu bytes of LDS (limit %zu): fewer wavelengths, species or SED bins", lds, ctx->lds_max);
+  size_t lds_w = walk_lds_bytes(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows, ctx->ntheta, ctx->ow,
+                                ctx->fp64);
+  if (lds > ctx->lds_max || lds_w > ctx->lds_max)
+    return fail(ctx, MCRT_EINVAL, "tables need %zu bytes of LDS (limit %zu): fewer wavelengths, species or SED bins", lds > lds_w ? lds : lds_w, ctx->lds_max);
   const int gfull = ctx->num_cu * ((o && o->blocks_per_cu > 0) ? o->blocks_per_cu : 2);
   const int gwalk = ctx->num_cu * ((o && o->walk_blocks_per_cu > 0) ? o->walk_blocks_per_cu : 4);
   const bool rec = o->record != 0;
@@ -1839,10 +1863,11 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
     hm[m].n = n_packets[m];
     size_t b = transport_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->fp64);
     if (b > lds) lds = b;
-    b = walk_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->fp64);
+    b = walk_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->ow, c->fp64);
     if (b > lds_w) lds_w = b;
   }
-  if (lds > ctx->lds_max) return fail(ctx, MCRT_EINVAL, "batch tables need %zu bytes of LDS (limit %zu)", lds, ctx->lds_max);
+  if (lds > ctx->lds_max || lds_w > ctx->lds_max)
+    return fail(ctx, MCRT_EINVAL, "batch tables need %zu bytes of LDS (limit %zu)", lds > lds_w ? lds : lds_w, ctx->lds_max);
   if (n_models > ctx->batch_cap) {
     HIPCHK(dev_alloc((void **)&ctx->d_batch, sizeof(ModelDev) * n_models));
     ctx->batch_cap = n_models;

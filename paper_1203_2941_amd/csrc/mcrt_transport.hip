@@ -48,6 +48,8 @@ struct Ctx {
   int nx, ny, nz;
   const R *rho_b;          // bricked density (brick_index)
   int nbx, nby;
+  const uint32_t *occ;     // walk: LDS copy of the super-brick occupancy bits (else null)
+  int osh, obx, oby;
 };
 
 __device__ __forceinline__ void stat_add(unsigned long long *st, int i, unsigned long long v) {
@@ -323,6 +325,7 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   bool out = F.out;
   using Idx = typename std::conditional<I32, uint32_t, int64_t>::type;
   Idx cs[K];
+  uint32_t ob[K];  // super-brick of step k (occupancy bit index)
   R ts[K], ls[K], rh[K];
   uint32_t mv = 0;  // exit axis of step k in bits 2k..2k+1
   int ns = 0;
@@ -342,6 +345,8 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
       if (ell < (R)0) ell = (R)0;
       if constexpr (I32) cs[k] = brick_index32(cx, cy, cz, X.nbx, X.nby);
       else cs[k] = brick_index(cx, cy, cz, X.nbx, X.nby);
+      ob[k] = __umul24(__umul24((uint32_t)(cz >> X.osh), (uint32_t)X.oby) +
+                           (uint32_t)(cy >> X.osh), (uint32_t)X.obx) + (uint32_t)(cx >> X.osh);
       ts[k] = t;
       ls[k] = ell;
       ns = k + 1;
@@ -378,8 +383,13 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   }
   F.tx = tx; F.ty = ty; F.tz = tz; F.ex = ex; F.ey = ey; F.ez = ez;
   F.t = t; F.cx = cx; F.cy = cy; F.cz = cz; F.out = out;
+  // a super-brick whose occupancy bit is clear holds only zero densities:
+  // its cells take rho = 0 without a load
+  uint32_t ow[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) rh[k] = (k < ns) ? gld(X.rho_b + cs[k]) : (R)0;
+  for (int k = 0; k < K; ++k) ow[k] = (k < ns) ? X.occ[ob[k] >> 5] : 0u;
+#pragma unroll
+  for (int k = 0; k < K; ++k) rh[k] = ((ow[k] >> (ob[k] & 31u)) & 1u) ? gld(X.rho_b + cs[k]) : (R)0;
   // cell of step k: the current cell with the moves of steps k .. ns-1 undone
   auto cell_of = [&](int k, int &ux, int &uy, int &uz) {
     ux = cx; uy = cy; uz = cz;
@@ -870,6 +880,7 @@ __device__ void stage_model(Ctx<R> &X, const ModelDev &M, unsigned char *lds_raw
   X.nx = M.nx; X.ny = M.ny; X.nz = M.nz;
   X.rho_b = (const R *)M.rho_b;
   X.nbx = M.nbx; X.nby = M.nby;
+  X.osh = M.osh; X.obx = M.obx; X.oby = M.oby;
   double *dt = (double *)lds_raw;
   R *rt = full ? (R *)(dt + X.o.dtotal) : (R *)lds_raw;
   int *im = (int *)(rt + X.o.r_total + (X.o.r_total & 1));
@@ -883,8 +894,14 @@ __device__ void stage_model(Ctx<R> &X, const ModelDev &M, unsigned char *lds_raw
   for (int i = threadIdx.x; i < M.nl; i += blockDim.x) im[i] = M.imgmap[i];
   const int nsed = (M.ntheta > 0 ? M.ntheta : 1) * M.nl;
   for (int i = threadIdx.x; i < nsed; i += blockDim.x) sed[i] = 0u;
+  uint32_t *occ = sed + nsed;
+  if (!full) {
+#pragma unroll 8
+    for (int i = threadIdx.x; i < M.ow; i += blockDim.x) occ[i] = gld(M.occ + i);
+  }
   if (threadIdx.x < NSTAT) s_stat[threadIdx.x] = 0ull;
   __syncthreads();
+  X.occ = full ? nullptr : occ;
   X.dt = full ? dt : nullptr;
   X.rt = rt;
   X.imgmap = im;
@@ -1217,11 +1234,11 @@ k_wf_interact(const ModelDev *__restrict__ models, int nmodels, int fcur) {
   }
 }
 
-size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool fp64) {
+size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, int occ_words, bool fp64) {
   TabOff o = tab_offsets(nl, ns, nsrc, nrows);
   size_t rs = fp64 ? 8 : 4;
   return (size_t)(o.r_total + (o.r_total & 1)) * rs + (size_t)(nl + (nl & 1)) * 4 +
-         (size_t)(ntheta > 0 ? ntheta : 1) * nl * 4;
+         (size_t)(ntheta > 0 ? ntheta : 1) * nl * 4 + (size_t)occ_words * 4;
 }
 
 template <typename R, bool REC>
@@ -1371,6 +1388,51 @@ __global__ void k_brick(const R *__restrict__ rho, R *__restrict__ rb, int nx, i
     const int cy = (int)(r % (uint64_t)ny), cz = (int)(r / (uint64_t)ny);
     rb[brick_index(cx, cy, cz, nbx, nby)] = rho[i];
   }
+}
+
+// Occupancy bit of each super-brick (2^osh cells a side, clipped at the
+// grid's far faces): set if any of its densities is non-zero. One lane per
+// super-brick; each wave writes the two words its 64 lanes cover.
+template <typename R>
+__global__ void k_occ(const R *__restrict__ rho, uint32_t *__restrict__ occ, int nx, int ny,
+                      int nz, int osh, int obx, int oby, int obz) {
+  const uint64_t nsb = (uint64_t)obx * oby * obz;
+  const uint64_t lim = (nsb + 63) / 64 * 64;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < lim; t += stride) {
+    bool any = false;
+    if (t < nsb) {
+      const int bx = (int)(t % (uint64_t)obx);
+      const uint64_t r = t / (uint64_t)obx;
+      const int by = (int)(r % (uint64_t)oby), bz = (int)(r / (uint64_t)oby);
+      const int x0 = bx << osh, y0 = by << osh, z0 = bz << osh;
+      const int x1 = min(x0 + (1 << osh), nx), y1 = min(y0 + (1 << osh), ny),
+                z1 = min(z0 + (1 << osh), nz);
+      for (int z = z0; z < z1 && !any; ++z)
+        for (int y = y0; y < y1 && !any; ++y) {
+          const R *row = rho + ((uint64_t)z * ny + y) * nx;
+          for (int x = x0; x < x1; ++x) any |= row[x] != (R)0;
+        }
+    }
+    const uint64_t b = __ballot(any);
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) occ[t >> 5] = (uint32_t)b;
+    if (lane == 32) occ[t >> 5] = (uint32_t)(b >> 32);
+  }
+}
+
+hipError_t launch_occ(bool fp64, const void *rho, uint32_t *occ, int nx, int ny, int nz, int osh,
+                      int obx, int oby, int obz, hipStream_t st) {
+  const uint64_t nsb = (uint64_t)obx * oby * obz;
+  const uint64_t nb = (nsb + 255) / 256;
+  const unsigned g = (unsigned)(nb < 4096 ? nb : 4096);
+  if (fp64)
+    hipLaunchKernelGGL(k_occ<double>, dim3(g), dim3(256), 0, st, (const double *)rho, occ, nx, ny,
+                       nz, osh, obx, oby, obz);
+  else
+    hipLaunchKernelGGL(k_occ<float>, dim3(g), dim3(256), 0, st, (const float *)rho, occ, nx, ny, nz,
+                       osh, obx, oby, obz);
+  return hipGetLastError();
 }
 
 hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, int nz, int nbx,
