@@ -239,6 +239,12 @@ template <typename R> __device__ __forceinline__ R rng_u(Rng &r) {
 template <typename T> __device__ __forceinline__ T gld(const T *p) {
   return *(const MCRT_AS_GLOBAL T *)p;
 }
+// Racy read of a value other lanes update with atomics (queue counters, the
+// B&W tallies): device scope, relaxed, so it neither tears nor is kept in a
+// register across reads, and it may be served by the L2.
+template <typename T> __device__ __forceinline__ T gload_relaxed(const T *p) {
+  return __hip_atomic_load((const MCRT_AS_GLOBAL T *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 template <typename T> __device__ __forceinline__ T gatomic_add(T *p, T v) {
   return __hip_atomic_fetch_add((MCRT_AS_GLOBAL T *)p, v, __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_AGENT);

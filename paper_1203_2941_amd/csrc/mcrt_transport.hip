@@ -224,7 +224,10 @@ __device__ double mode_T(Ctx<R> &X, int s, int64_t c, double rho) {
       M.tt[q] = T;  // every lane computes the same value from the snapshot
     }
   } else {
-    double e = (double)(*(volatile uint64_t *)&M.k[q]) * M.xi + *(volatile double *)&M.epath[q];
+    // the tallies as last seen by this CU (other packets update them with
+    // atomics while the kernel runs; any value since the kernel began is a
+    // valid reading of the cell's energy so far)
+    double e = (double)gld(&M.k[q]) * M.xi + gld(&M.epath[q]);
     double rhs = (e + M.xi) / (4.0 * PI_D * frac * rho * M.V);
     T = invert_T_fast(M.herm, X.dt, X.o, M.nl, s, rhs, &cl);
   }
@@ -835,9 +838,9 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
       int64_t qk = (int64_t)s * X.nc + c;
       double T;
       if (M.mode == M_BW_TICKET) {
-        uint64_t kold = thin ? *(volatile uint64_t *)&M.k[qk]
+        uint64_t kold = thin ? gld(&M.k[qk])
                              : gatomic_add(&M.k[qk], (uint64_t)1);
-        double e = (double)kold * M.xi + *(volatile double *)&M.epath[qk];
+        double e = (double)kold * M.xi + gld(&M.epath[qk]);  // racy read, as in mode_T
         double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s] * (double)rho * M.V);
         bool cl = false;
         T = invert_T_fast(M.herm, X.dt, X.o, nl, s, rhs, &cl);
@@ -972,7 +975,7 @@ __device__ __forceinline__ int home_segment() {
 }
 
 __device__ __forceinline__ uint32_t seg_count(const WfCtl *c, int f, int g, uint32_t S) {
-  const uint32_t v = *(volatile const uint32_t *)&c->nseg[f][g][0];
+  const uint32_t v = gload_relaxed(&c->nseg[f][g][0]);
   return v < S ? v : S;
 }
 
@@ -985,7 +988,7 @@ __device__ __forceinline__ bool seg_grab(WfCtl *c, int k, int &g, int lane, uint
   for (int t = 0; t < NSEG; ++t) {
     uint32_t beg, cnt;
     seg(g, beg, cnt);
-    if (*(volatile uint32_t *)&c->work[k][g][0] < cnt) {
+    if (gload_relaxed(&c->work[k][g][0]) < cnt) {
       uint32_t base = 0u;
       if (lane == 0) base = gatomic_add(&c->work[k][g][0], 64u);
       base = (uint32_t)__shfl((int)base, 0);
