@@ -32,8 +32,8 @@ hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, boo
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
                            bool idx32, const hipEvent_t *ev, hipStream_t st);
 size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, int occ_words, bool fp64);
-hipError_t launch_occ(bool fp64, const void *rho, uint32_t *occ, int nx, int ny, int nz, int osh,
-                      int obx, int oby, int obz, hipStream_t st);
+hipError_t launch_occ(bool fp64, const void *rb, uint32_t *occ, uint64_t ncell_b, int osh,
+                      hipStream_t st);
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
                           hipStream_t st);
 hipError_t launch_sample_reem(const ModelDev *d, bool fp64, int s, double T, uint64_t n,
@@ -66,8 +66,8 @@ struct mcrt_ctx {
   void *d_rho = nullptr;
   void *d_rho_b = nullptr;  // density in 4x4x4 bricks for the walk
   int nbx = 0, nby = 0, nbz = 0;
-  uint32_t *d_occ = nullptr;  // super-brick occupancy bits for the walk
-  int osh = 0, obx = 0, oby = 0, obz = 0, ow = 0;
+  uint32_t *d_occ = nullptr;  // brick-run occupancy bits for the walk
+  int osh = 0, ow = 0;
   // dust
   bool has_dust = false;
   int nl = 0, ns = 0, pah = -1, nrows = 0;
@@ -619,7 +619,7 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
 // ------------------------------------------------------------------- set
 
 // Bricked copy of the density read by the walk, and the occupancy bits of
-// its super-bricks; rebuilt whenever the density changes.
+// its brick runs; rebuilt whenever the density changes.
 static uint64_t brick_cells(const mcrt_ctx *ctx) {
   return (uint64_t)ctx->nbx * ctx->nby * ctx->nbz * 64;
 }
@@ -633,23 +633,15 @@ static mcrt_status build_brick(mcrt_ctx *ctx) {
   HIPCHK(hipMemset(ctx->d_rho_b, 0, nb * rsize(ctx)));
   HIPCHK(launch_brick(ctx->fp64, ctx->d_rho, ctx->d_rho_b, ctx->nx, ctx->ny, ctx->nz, ctx->nbx,
                       ctx->nby, 0));
-  // smallest super-brick side 2^osh >= 4 whose bits fit OCC_MAX_WORDS words
-  int osh = 2;
-  for (;; ++osh) {
-    const uint64_t bx = ((uint64_t)ctx->nx + (1u << osh) - 1) >> osh;
-    const uint64_t by = ((uint64_t)ctx->ny + (1u << osh) - 1) >> osh;
-    const uint64_t bz = ((uint64_t)ctx->nz + (1u << osh) - 1) >> osh;
-    if ((bx * by * bz + 31) / 32 <= (uint64_t)OCC_MAX_WORDS) {
-      ctx->obx = (int)bx; ctx->oby = (int)by; ctx->obz = (int)bz;
-      break;
-    }
-  }
-  ctx->osh = osh;
-  const uint64_t nsb = (uint64_t)ctx->obx * ctx->oby * ctx->obz;
-  ctx->ow = (int)((nsb + 31) / 32);
-  HIPCHK(dev_alloc((void **)&ctx->d_occ, (nsb + 63) / 64 * 8));
-  HIPCHK(launch_occ(ctx->fp64, ctx->d_rho, ctx->d_occ, ctx->nx, ctx->ny, ctx->nz, osh, ctx->obx,
-                    ctx->oby, ctx->obz, 0));
+  // shortest run of 2^m bricks whose bits fit OCC_MAX_WORDS words
+  const uint64_t nbrick = nb / 64;
+  int m = 0;
+  while (((nbrick + (1ull << m) - 1) >> m) > (uint64_t)OCC_MAX_WORDS * 32) ++m;
+  ctx->osh = 6 + m;
+  const uint64_t nrun = (nbrick + (1ull << m) - 1) >> m;
+  ctx->ow = (int)((nrun + 31) / 32);
+  HIPCHK(dev_alloc((void **)&ctx->d_occ, (nrun + 63) / 64 * 8));
+  HIPCHK(launch_occ(ctx->fp64, ctx->d_rho_b, ctx->d_occ, nb, ctx->osh, 0));
   HIPCHK(hipDeviceSynchronize());
   return MCRT_OK;
 }
@@ -986,7 +978,7 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.rho_b = ctx->d_rho_b;
   M.nbx = ctx->nbx; M.nby = ctx->nby; M.nbz = ctx->nbz;
   M.occ = ctx->d_occ;
-  M.osh = ctx->osh; M.obx = ctx->obx; M.oby = ctx->oby; M.ow = ctx->ow;
+  M.osh = ctx->osh; M.ow = ctx->ow;
   M.tab = ctx->d_tab;
   M.rtab = ctx->d_rtab;
   M.imgmap = ctx->d_imgmap;

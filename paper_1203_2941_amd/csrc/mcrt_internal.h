@@ -92,8 +92,9 @@ struct QBuf {
   double *mm;                                      // kept for packet records
 };
 
-// The walk keeps the occupancy bits of the grid in LDS; the super-brick side
-// is the smallest power of two (at least a brick) that fits this many words.
+// The walk keeps the occupancy bits of the grid in LDS: one bit per run of
+// consecutive bricks (in brick_index order), the shortest power-of-two run
+// whose bits fit this many words.
 constexpr int OCC_MAX_WORDS = 2048;
 
 // Queue counters. Each queue is split into NSEG segments of equal
@@ -127,8 +128,8 @@ struct ModelDev {
   const void *rho;            // [cells] context precision
   const void *rho_b;          // the same density in 4x4x4 bricks (brick_index), read by the walk
   int32_t nbx, nby, nbz;      // bricks per axis
-  const uint32_t *occ;        // bit per super-brick of 2^osh cells a side: 1 if any density != 0
-  int32_t osh, obx, oby, ow;  // super-brick side (log2), super-bricks along x and y, words of occ
+  const uint32_t *occ;        // bit per run of 2^(osh - 6) consecutive bricks: 1 if any density != 0
+  int32_t osh, ow;            // bricked-cell index >> osh is the run; words of occ
   const double *tab;          // packed double table
   const void *rtab;           // packed R table
   const int32_t *imgmap;      // [nl] -> imaged index or -1

@@ -48,8 +48,8 @@ struct Ctx {
   int nx, ny, nz;
   const R *rho_b;          // bricked density (brick_index)
   int nbx, nby;
-  const uint32_t *occ;     // walk: LDS copy of the super-brick occupancy bits (else null)
-  int osh, obx, oby;
+  const uint32_t *occ;     // walk: LDS copy of the brick-run occupancy bits (else null)
+  int osh;                 // bricked-cell index >> osh is its run
 };
 
 __device__ __forceinline__ void stat_add(unsigned long long *st, int i, unsigned long long v) {
@@ -328,8 +328,7 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   bool out = F.out;
   using Idx = typename std::conditional<I32, uint32_t, int64_t>::type;
   Idx cs[K];
-  uint32_t ob[K];  // super-brick of step k (occupancy bit index)
-  R ts[K], ls[K], rh[K];
+  R ts[K + 1], rh[K];  // ts[k]: distance at the start of step k (ts[ns]: at its end)
   uint32_t mv = 0;  // exit axis of step k in bits 2k..2k+1
   int ns = 0;
 #pragma unroll
@@ -344,16 +343,12 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
                   : (b1 ? (tx < tz ? tx : tz) : (ty < tz ? ty : tz));
         if (t2 < m_inf<R>() && t2 > (R)0) upd_margin(P.mm, (double)((t2 - tn) / t2));
       }
-      R ell = tn - t;
-      if (ell < (R)0) ell = (R)0;
       if constexpr (I32) cs[k] = brick_index32(cx, cy, cz, X.nbx, X.nby);
       else cs[k] = brick_index(cx, cy, cz, X.nbx, X.nby);
-      ob[k] = __umul24(__umul24((uint32_t)(cz >> X.osh), (uint32_t)X.oby) +
-                           (uint32_t)(cy >> X.osh), (uint32_t)X.obx) + (uint32_t)(cx >> X.osh);
       ts[k] = t;
-      ls[k] = ell;
       ns = k + 1;
       if (tn > t) t = tn;
+      // the segment length max(tn - t, 0) is ts[k + 1] - ts[k]
       const bool mx = !(b1 || b2), my = b1 && !b2;
       mv |= (uint32_t)(b2 ? 2 : (b1 ? 1 : 0)) << (2 * k);
       cx += mx ? sx : 0;
@@ -386,13 +381,17 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   }
   F.tx = tx; F.ty = ty; F.tz = tz; F.ex = ex; F.ey = ey; F.ez = ez;
   F.t = t; F.cx = cx; F.cy = cy; F.cz = cz; F.out = out;
-  // a super-brick whose occupancy bit is clear holds only zero densities:
-  // its cells take rho = 0 without a load
+#pragma unroll
+  for (int k = 0; k <= K; ++k)
+    if (k == ns) ts[k] = t;
+  // a brick run whose occupancy bit is clear holds only zero densities: its
+  // cells take rho = 0 without a load
   uint32_t ow[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) ow[k] = (k < ns) ? X.occ[ob[k] >> 5] : 0u;
+  for (int k = 0; k < K; ++k) ow[k] = (k < ns) ? X.occ[(uint32_t)(cs[k] >> X.osh) >> 5] : 0u;
 #pragma unroll
-  for (int k = 0; k < K; ++k) rh[k] = ((ow[k] >> (ob[k] & 31u)) & 1u) ? gld(X.rho_b + cs[k]) : (R)0;
+  for (int k = 0; k < K; ++k)
+    rh[k] = ((ow[k] >> ((uint32_t)(cs[k] >> X.osh) & 31u)) & 1u) ? gld(X.rho_b + cs[k]) : (R)0;
   // cell of step k: the current cell with the moves of steps k .. ns-1 undone
   auto cell_of = [&](int k, int &ux, int &uy, int &uz) {
     ux = cx; uy = cy; uz = cz;
@@ -411,7 +410,8 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   for (int k = 0; k < K; ++k) {
     if (k < ns) {
       const R rho = rh[k];
-      const R dtau = rho * kx * ls[k];
+      const R ell = ts[k + 1] - ts[k];
+      const R dtau = rho * kx * ell;
       const bool thin = is_thin(X, rho);
       if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tau_star) / tau_star));
       if (tau + dtau > tau_star) {
@@ -430,7 +430,7 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
       if (thin) {
         int ux, uy, uz;
         cell_of(k, ux, uy, uz);
-        lucy_deposit(X, P, lin(ux, uy, uz), rho, ls[k]);
+        lucy_deposit(X, P, lin(ux, uy, uz), rho, ell);
       }
       tau += dtau;
       P.n_cross++;
@@ -883,7 +883,7 @@ __device__ void stage_model(Ctx<R> &X, const ModelDev &M, unsigned char *lds_raw
   X.nx = M.nx; X.ny = M.ny; X.nz = M.nz;
   X.rho_b = (const R *)M.rho_b;
   X.nbx = M.nbx; X.nby = M.nby;
-  X.osh = M.osh; X.obx = M.obx; X.oby = M.oby;
+  X.osh = M.osh;
   double *dt = (double *)lds_raw;
   R *rt = full ? (R *)(dt + X.o.dtotal) : (R *)lds_raw;
   int *im = (int *)(rt + X.o.r_total + (X.o.r_total & 1));
@@ -1113,7 +1113,7 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
 // entry. Lanes refill one by one from a wave-local chunk, so flights of
 // different lengths keep the wave busy.
 template <typename R, bool REC, bool I32>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ unsigned long long s_stat[NSTAT];
@@ -1393,48 +1393,39 @@ __global__ void k_brick(const R *__restrict__ rho, R *__restrict__ rb, int nx, i
   }
 }
 
-// Occupancy bit of each super-brick (2^osh cells a side, clipped at the
-// grid's far faces): set if any of its densities is non-zero. One lane per
-// super-brick; each wave writes the two words its 64 lanes cover.
+// Occupancy bit of each run of 2^(osh - 6) bricks, i.e. of bricked cells
+// [r << osh, (r + 1) << osh): set if any of its densities is non-zero. One
+// lane per run; each wave writes the two words its 64 lanes cover.
 template <typename R>
-__global__ void k_occ(const R *__restrict__ rho, uint32_t *__restrict__ occ, int nx, int ny,
-                      int nz, int osh, int obx, int oby, int obz) {
-  const uint64_t nsb = (uint64_t)obx * oby * obz;
-  const uint64_t lim = (nsb + 63) / 64 * 64;
+__global__ void k_occ(const R *__restrict__ rb, uint32_t *__restrict__ occ, uint64_t ncell_b,
+                      int osh) {
+  const uint64_t nrun = (ncell_b + (1ull << osh) - 1) >> osh;
+  const uint64_t lim = (nrun + 63) / 64 * 64;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < lim; t += stride) {
     bool any = false;
-    if (t < nsb) {
-      const int bx = (int)(t % (uint64_t)obx);
-      const uint64_t r = t / (uint64_t)obx;
-      const int by = (int)(r % (uint64_t)oby), bz = (int)(r / (uint64_t)oby);
-      const int x0 = bx << osh, y0 = by << osh, z0 = bz << osh;
-      const int x1 = min(x0 + (1 << osh), nx), y1 = min(y0 + (1 << osh), ny),
-                z1 = min(z0 + (1 << osh), nz);
-      for (int z = z0; z < z1 && !any; ++z)
-        for (int y = y0; y < y1 && !any; ++y) {
-          const R *row = rho + ((uint64_t)z * ny + y) * nx;
-          for (int x = x0; x < x1; ++x) any |= row[x] != (R)0;
-        }
+    if (t < nrun) {
+      const uint64_t b = t << osh, e = min(b + (1ull << osh), ncell_b);
+      for (uint64_t i = b; i < e; ++i) any |= rb[i] != (R)0;
     }
-    const uint64_t b = __ballot(any);
+    const uint64_t m = __ballot(any);
     const int lane = threadIdx.x & 63;
-    if (lane == 0) occ[t >> 5] = (uint32_t)b;
-    if (lane == 32) occ[t >> 5] = (uint32_t)(b >> 32);
+    if (lane == 0) occ[t >> 5] = (uint32_t)m;
+    if (lane == 32) occ[t >> 5] = (uint32_t)(m >> 32);
   }
 }
 
-hipError_t launch_occ(bool fp64, const void *rho, uint32_t *occ, int nx, int ny, int nz, int osh,
-                      int obx, int oby, int obz, hipStream_t st) {
-  const uint64_t nsb = (uint64_t)obx * oby * obz;
-  const uint64_t nb = (nsb + 255) / 256;
+hipError_t launch_occ(bool fp64, const void *rb, uint32_t *occ, uint64_t ncell_b, int osh,
+                      hipStream_t st) {
+  const uint64_t nrun = (ncell_b + (1ull << osh) - 1) >> osh;
+  const uint64_t nb = (nrun + 255) / 256;
   const unsigned g = (unsigned)(nb < 4096 ? nb : 4096);
   if (fp64)
-    hipLaunchKernelGGL(k_occ<double>, dim3(g), dim3(256), 0, st, (const double *)rho, occ, nx, ny,
-                       nz, osh, obx, oby, obz);
+    hipLaunchKernelGGL(k_occ<double>, dim3(g), dim3(256), 0, st, (const double *)rb, occ, ncell_b,
+                       osh);
   else
-    hipLaunchKernelGGL(k_occ<float>, dim3(g), dim3(256), 0, st, (const float *)rho, occ, nx, ny, nz,
-                       osh, obx, oby, obz);
+    hipLaunchKernelGGL(k_occ<float>, dim3(g), dim3(256), 0, st, (const float *)rb, occ, ncell_b,
+                       osh);
   return hipGetLastError();
 }
 

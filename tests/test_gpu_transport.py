@@ -237,3 +237,35 @@ def test_ticket_mode_statistics(orc):
     so, sg = o.sed.astype(float), g.sed()[1].astype(float)
     ok = (so + sg) > 50
     assert np.sum((so[ok] - sg[ok]) ** 2 / (so[ok] + sg[ok])) / ok.sum() < 1.5
+
+
+def test_fp32_walk_through_empty_bricks():
+    """FP32 walk across bricks with no dust: the walk skips their density
+    loads (occupancy bits) but must step through them exactly as through
+    dust-filled ones. Two grids differ only in 4^3 blocks that are empty in
+    one and hold a negligible density (tau ~ 1e-18 per cell) in the other; no
+    packet interacts, so the crossing totals and the escape SED must be
+    identical. The grid is not cubic and its sizes are not multiples of the
+    brick side."""
+    import dataclasses
+    m = mi.cube(n=8, n_packets=20_000)
+    nx, ny, nz = 37, 29, 45
+    dc = m.dcell
+    origin = -0.5 * dc * np.array([nx, ny, nz], dtype=np.float64) + 0.37 * dc
+    rng = np.random.default_rng(12)
+    box = rng.random(((nz + 3) // 4, (ny + 3) // 4, (nx + 3) // 4)) < 0.5
+    occ = np.repeat(np.repeat(np.repeat(box, 4, 0), 4, 1), 4, 2)[:nz, :ny, :nx]
+    tiny = 1e-35
+    rho_gaps = np.where(occ, tiny, 0.0)
+    rho_full = np.full((nz, ny, nx), tiny)
+    out = []
+    for rho in (rho_gaps, rho_full):
+        mm = dataclasses.replace(m, name="gaps", nx=nx, ny=ny, nz=nz, origin=origin, rho=rho)
+        g = gpu_context(mm, "fp32")
+        st = g.run_packets(0, mm.n_packets, mm.seed, mode="bw_ticket", n_total=mm.n_packets)
+        out.append((st, g.sed()[1].copy()))
+    (sa, ea), (sb, eb) = out
+    assert sa["escaped"] == sb["escaped"] == m.n_packets
+    assert sa["crossings"] == sb["crossings"]
+    assert sa["crossings"] > 15 * m.n_packets
+    np.testing.assert_array_equal(ea, eb)
