@@ -53,7 +53,7 @@ def main():
     ap.add_argument("--packets", type=int, default=100_000_000)
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--npix", type=int, default=512)
-    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--cpu-sample", type=int, default=600_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queue-depth", type=int, default=0,
                     help="packets per wavefront queue (0: the library default)")
@@ -152,9 +152,9 @@ def main():
     traffic = traffic_step = None
     if N == 100_000_000 and args.grid == 256 and not args.queue_depth:
         from paper_1203_2941_amd import profiling
-        traffic_step = profiling.read_traffic()
-        if traffic_step is not None:
-            traffic = traffic_step / n_walk
+        tr = profiling.read_traffic()
+        if tr is not None:
+            traffic, traffic_step = tr["per_launch"], tr["per_step"]
     out = {
         "metric": METRIC,
         "value": N / (ms / 1e3),
@@ -195,8 +195,8 @@ def main():
             "unit": "GB/s",
             "frac": b_alg / t_walk / HBM_PEAK,
             "traffic": traffic,
-            "traffic_unit": "bytes per launch (L2 <-> memory, rocprofv3 FETCH_SIZE + WRITE_SIZE "
-                            "per step over launches_per_step)",
+            "traffic_unit": "bytes per launch (L2 <-> memory, rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "each over the walk launches of its own counter run)",
             "traffic_per_step": traffic_step,
             "launches_per_step": n_walk,
             "avg_launch_ms": t_walk * 1e3 / n_walk,

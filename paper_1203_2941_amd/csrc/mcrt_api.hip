@@ -624,6 +624,11 @@ static uint64_t brick_cells(const mcrt_ctx *ctx) {
   return (uint64_t)ctx->nbx * ctx->nby * ctx->nbz * 64;
 }
 
+// The walk may use 32-bit brick indices (brick_index32).
+static bool idx32_ok(const mcrt_ctx *ctx) {
+  return brick_cells(ctx) < (1ull << 32) && (uint64_t)ctx->nby * ctx->nbz < (1ull << 24);
+}
+
 static mcrt_status build_brick(mcrt_ctx *ctx) {
   ctx->nbx = (ctx->nx + 3) / 4;
   ctx->nby = (ctx->ny + 3) / 4;
@@ -1119,7 +1124,7 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
     const int fcur = (int)(r & 1);
     const hipEvent_t *ev = phase_events(ctx);
     HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w,
-                           brick_cells(ctx) < (1ull << 32), ev, st));
+                           idx32_ok(ctx), ev, st));
     if ((r + 1) % every == 0) {
       HIPCHK(launch_wf_busy(ctx->d_model, 1, fcur, &ctx->d_ctl->busy, st));
       HIPCHK(hipMemcpyAsync(&ctx->h_ctl->busy, &ctx->d_ctl->busy, 4, hipMemcpyDeviceToHost, st));
@@ -1842,7 +1847,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   bool idx32 = true;
   for (int m = 0; m < n_models; ++m) {
     mcrt_ctx *c = models[m];
-    if (c && brick_cells(c) >= (1ull << 32)) idx32 = false;
+    if (c && !idx32_ok(c)) idx32 = false;
     if (!c || c->device != ctx->device || c->fp64 != ctx->fp64)
       return fail(ctx, MCRT_EINVAL, "model %d: same device and precision required", m);
     s = prepare_run(c, opts, n_packets[m], st);

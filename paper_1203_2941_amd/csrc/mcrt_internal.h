@@ -169,8 +169,12 @@ __host__ __device__ __forceinline__ int64_t brick_index(int cx, int cy, int cz, 
 }
 // The same in 32-bit arithmetic, for bricked grids of fewer than 2^32 cells
 // (cells in range, so every coordinate is >= 0).
+// 32-bit form with 24-bit multiplies (full rate; the 32-bit multiply is a
+// quarter-rate instruction): valid while the bricked grid has fewer than
+// 2^32 cells and nby * nbz < 2^24 (see idx32_ok).
 __device__ __forceinline__ uint32_t brick_index32(int cx, int cy, int cz, int nbx, int nby) {
-  const uint32_t b = ((uint32_t)(cz >> 2) * (uint32_t)nby + (uint32_t)(cy >> 2)) * (uint32_t)nbx +
+  const uint32_t b = __umul24(__umul24((uint32_t)(cz >> 2), (uint32_t)nby) + (uint32_t)(cy >> 2),
+                              (uint32_t)nbx) +
                      (uint32_t)(cx >> 2);
   return (b << 6) | (uint32_t)(((cz & 3) << 4) | ((cy & 3) << 2) | (cx & 3));
 }

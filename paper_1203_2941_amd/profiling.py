@@ -78,13 +78,16 @@ def traffic_md(fetch_db: str, write_db: str, calib_mib: int, cmd: str) -> str:
     cal_w = counter_values(write_db, "WRITE_SIZE", CALIB_KERNEL)
     fetch = counter_values(fetch_db, "FETCH_SIZE", TRANSPORT_KERNEL)
     write = counter_values(write_db, "WRITE_SIZE", TRANSPORT_KERNEL)
-    if not (cal_f and cal_w and fetch and write) or len(fetch) != len(write):
+    if not (cal_f and cal_w and fetch and write):
         raise SystemExit("counters missing from the databases")
     nbytes = calib_mib * (1 << 20)
     sf = nbytes / cal_f[0]   # bytes per counter unit, read side
     sw = nbytes / cal_w[0]   # write side
-    per = [f * sf + w * sw for f, w in zip(fetch, write)]
-    mean = sum(per) / len(per)
+    # the two runs are separate processes and need not take the same number
+    # of rounds: each side is summed over its own run's launches
+    rd, wr = sum(fetch) * sf, sum(write) * sw
+    per_launch = rd / len(fetch) + wr / len(write)
+    launches = 0.5 * (len(fetch) + len(write))
     lines = [
         "# HBM traffic of the walk kernel: 256^3 clumpy torus, 1e8 packets, FP32",
         "",
@@ -100,20 +103,14 @@ def traffic_md(fetch_db: str, write_db: str, calib_mib: int, cmd: str) -> str:
         cmd,
         "```",
         "",
-        "| launch | FETCH_SIZE | WRITE_SIZE | bytes read | bytes written | total bytes |",
-        "|---|---:|---:|---:|---:|---:|",
-    ]
-    for i, (f, w) in enumerate(zip(fetch, write)):
-        lines.append(f"| {i} | {f:.6g} | {w:.6g} | {f * sf:.6g} | {w * sw:.6g} | {per[i]:.6g} |")
-    if len(per) > 12:
-        lines = lines[:-len(per)] + [
-            f"| all {len(per)} | {sum(fetch):.6g} | {sum(write):.6g} | {sum(fetch) * sf:.6g} | "
-            f"{sum(write) * sw:.6g} | {sum(per):.6g} |"]
-    lines += [
+        "| run | walk launches | counter sum | bytes | bytes per launch |",
+        "|---|---:|---:|---:|---:|",
+        f"| FETCH_SIZE | {len(fetch)} | {sum(fetch):.6g} | {rd:.6g} | {rd / len(fetch):.6g} |",
+        f"| WRITE_SIZE | {len(write)} | {sum(write):.6g} | {wr:.6g} | {wr / len(write):.6g} |",
         "",
-        f"traffic_bytes_per_launch: {mean:.6g}",
-        f"traffic_bytes_per_step: {sum(per):.6g}",
-        f"launches_per_step: {len(per)}",
+        f"traffic_bytes_per_launch: {per_launch:.6g}",
+        f"traffic_bytes_per_step: {per_launch * launches:.6g}",
+        f"launches_per_step: {launches:g}",
         f"source_sha256: {source_digest()}",
         "",
     ]
@@ -121,19 +118,20 @@ def traffic_md(fetch_db: str, write_db: str, calib_mib: int, cmd: str) -> str:
 
 
 def read_traffic(path: str = TRAFFIC_FILE):
-    """Measured bytes of the walk kernel per bench step (all its launches),
-    or None when the summary is missing or was taken from other transport
-    sources."""
+    """Measured bytes of the walk kernel, {"per_launch": B, "per_step": B}
+    (a step being all launches of one bench step), or None when the summary
+    is missing or was taken from other transport sources."""
     try:
         with open(path) as f:
             text = f.read()
     except OSError:
         return None
-    m = re.search(r"^traffic_bytes_per_step: (\S+)$", text, re.M)
+    pl = re.search(r"^traffic_bytes_per_launch: (\S+)$", text, re.M)
+    ps = re.search(r"^traffic_bytes_per_step: (\S+)$", text, re.M)
     d = re.search(r"^source_sha256: (\S+)$", text, re.M)
-    if not m or not d or d.group(1) != source_digest():
+    if not pl or not ps or not d or d.group(1) != source_digest():
         return None
-    return float(m.group(1))
+    return {"per_launch": float(pl.group(1)), "per_step": float(ps.group(1))}
 
 
 def main(argv):

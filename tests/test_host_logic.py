@@ -46,3 +46,37 @@ def test_run_opts_modes():
     assert o.mode == _lib.BW_EPOCH and o.epoch_packets == 7 and o.record == 1
     with pytest.raises(KeyError):
         context.run_opts(mode="nonsense")
+
+
+def test_traffic_summary_round_trip(tmp_path):
+    """Counter summary for the walk's HBM traffic: each counter is scaled by
+    its reading of a copy of known size; the two runs may differ in launch
+    count; bench reads back per-launch and per-step bytes."""
+    import sqlite3
+    from paper_1203_2941_amd import profiling as pf
+
+    def db(path, counter, calib, walk):
+        con = sqlite3.connect(path)
+        con.execute("create table counters_collection (dispatch_id int, kernel_name text, "
+                    "counter_name text, value real)")
+        rows = [(0, "vectorized_elementwise_kernel<MulFunctor>", counter, calib)]
+        rows += [(i + 1, f"void mcrt::{pf.TRANSPORT_KERNEL}(args)", counter, v)
+                 for i, v in enumerate(walk)]
+        con.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+        con.commit()
+        con.close()
+
+    mib = 4
+    nbytes = mib << 20
+    db(tmp_path / "f.db", "FETCH_SIZE", nbytes / 2048.0, [100.0, 300.0])       # 2048 B per unit
+    db(tmp_path / "w.db", "WRITE_SIZE", nbytes / 1024.0, [10.0, 20.0, 30.0])   # 1024 B per unit
+    text = pf.traffic_md(str(tmp_path / "f.db"), str(tmp_path / "w.db"), mib, "cmd")
+    out = tmp_path / "t.md"
+    out.write_text(text)
+    got = pf.read_traffic(str(out))
+    per_launch = 200.0 * 2048 + 20.0 * 1024
+    assert abs(got["per_launch"] - per_launch) / per_launch < 1e-5
+    assert abs(got["per_step"] - per_launch * 2.5) / (per_launch * 2.5) < 1e-5
+    # a summary taken from other transport sources is not reported
+    out.write_text(text.replace(pf.source_digest(), "0" * 64))
+    assert pf.read_traffic(str(out)) is None
