@@ -1431,10 +1431,19 @@ __global__ void k_d2f(const double *a, float *b, uint64_t n) {
   uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) b[i] = (float)a[i];
 }
-__global__ void k_f2d(const float *a, double *b, uint64_t n) {
+// Scattering sums from the device layout [view][cell][img] (in units of
+// `unit`) to the API layout [view][img][cell] in erg/s/sr.
+template <typename R>
+__global__ void k_ssca_out(const R *a, double *b, double unit, int nview, uint64_t ncell,
+                           int nq) {
+  const uint64_t n = (uint64_t)nview * nq * ncell;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) b[i] = (double)a[i];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const uint64_t c = i % ncell, r = i / ncell;
+    const uint64_t q = r % (uint64_t)nq, v = r / (uint64_t)nq;
+    b[i] = (double)a[(v * ncell + c) * (uint64_t)nq + q] * unit;
+  }
 }
 
 extern "C" mcrt_status mcrt_set_scattering(mcrt_ctx *ctx, const double *ssca, int mem, void *stream) {
@@ -1459,14 +1468,21 @@ extern "C" mcrt_status mcrt_set_scattering(mcrt_ctx *ctx, const double *ssca, in
     if (!finite_nonneg(h[i])) return fail(ctx, MCRT_EINVAL, "scattering sums must be finite and >= 0");
     if (h[i] > mx) mx = h[i];
   }
-  // store in units that keep the largest value near 2^20
+  // store in units that keep the largest value near 2^20, in the device
+  // layout [view][cell][img]
   double unit = mx > 0.0 ? mx / 1048576.0 : 1.0;
+  const uint64_t nc = ctx->ncell, nq = (uint64_t)ctx->nimg;
+  auto dev_index = [&](uint64_t i) {  // API index [view][img][cell] -> device index
+    const uint64_t c = i % nc, r = i / nc;
+    return ((r / nq) * nc + c) * nq + r % nq;
+  };
   if (ctx->fp64) {
-    for (auto &v : h) v /= unit;
-    HIPCHK(hipMemcpy(ctx->d_ssca, h.data(), m * 8, hipMemcpyHostToDevice));
+    std::vector<double> d(m);
+    for (uint64_t i = 0; i < m; ++i) d[dev_index(i)] = h[i] / unit;
+    HIPCHK(hipMemcpy(ctx->d_ssca, d.data(), m * 8, hipMemcpyHostToDevice));
   } else {
     std::vector<float> f(m);
-    for (uint64_t i = 0; i < m; ++i) f[i] = (float)(h[i] / unit);
+    for (uint64_t i = 0; i < m; ++i) f[dev_index(i)] = (float)(h[i] / unit);
     HIPCHK(hipMemcpy(ctx->d_ssca, f.data(), m * 4, hipMemcpyHostToDevice));
   }
   ctx->ssca_unit = unit;
@@ -1593,13 +1609,14 @@ extern "C" mcrt_status mcrt_scattering(mcrt_ctx *ctx, double *ssca_out, int mem,
   if (m == 0 || !ssca_out) return MCRT_OK;
   double *tmp = nullptr;
   HIPCHK(hipMalloc((void **)&tmp, m * 8));
-  if (ctx->fp64) {
-    HIPCHK(hipMemcpyAsync(tmp, ctx->d_ssca, m * 8, hipMemcpyDeviceToDevice, st));
-  } else {
-    hipLaunchKernelGGL(k_f2d, dim3(4096), dim3(256), 0, st, (const float *)ctx->d_ssca, tmp, m);
-    HIPCHK(hipGetLastError());
-  }
-  hipLaunchKernelGGL(k_scale<double>, dim3(4096), dim3(256), 0, st, tmp, ctx->ssca_unit, m);
+  if (ctx->fp64)
+    hipLaunchKernelGGL(k_ssca_out<double>, dim3(4096), dim3(256), 0, st,
+                       (const double *)ctx->d_ssca, tmp, ctx->ssca_unit, ctx->nview, ctx->ncell,
+                       ctx->nimg);
+  else
+    hipLaunchKernelGGL(k_ssca_out<float>, dim3(4096), dim3(256), 0, st,
+                       (const float *)ctx->d_ssca, tmp, ctx->ssca_unit, ctx->nview, ctx->ncell,
+                       ctx->nimg);
   HIPCHK(hipGetLastError());
   s = to_caller(ctx, ssca_out, tmp, m * 8, mem, st);
   HIPCHK(hipStreamSynchronize(st));

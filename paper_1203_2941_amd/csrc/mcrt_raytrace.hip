@@ -142,17 +142,56 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
       }
     }
     for (int v = 0; v < M.nview; ++v) {
+      // the scattering sums and S share the layout [view][cell][img]
       R *out = S + ((uint64_t)v * M.ncell + c) * nq;
+      const R *sc = ss ? ss + ((uint64_t)v * M.ncell + c) * nq : nullptr;
+      R sv[MAX_IMG];
+#pragma unroll
+      for (int q = 0; q < MAX_IMG; ++q) sv[q] = (R)0;
+      if (sc && r > 0.0) {
+        bool vec = false;
+        if constexpr (sizeof(R) == 4 && MAX_IMG == 16) {
+          if (nq == 16) {
+            const float4 *s4 = reinterpret_cast<const float4 *>(sc);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const float4 w = s4[k];
+              sv[4 * k] = w.x; sv[4 * k + 1] = w.y; sv[4 * k + 2] = w.z; sv[4 * k + 3] = w.w;
+            }
+            vec = true;
+          }
+        }
+        if (!vec) {
+#pragma unroll
+          for (int q = 0; q < MAX_IMG; ++q)
+            if (q < nq) sv[q] = sc[q];
+        }
+      }
+      R vals[MAX_IMG];
+#pragma unroll
+      for (int q = 0; q < MAX_IMG; ++q) {
+        double val = em[q];
+        if (q < nq && sc && r > 0.0) {
+          int j = M.img_j[q];
+          val += (double)sv[q] * M.ssca_unit / (M.V * M.tab[o.w + j] * r * M.tab[o.kext + j]);
+        }
+        vals[q] = (R)val;
+      }
+      if constexpr (sizeof(R) == 4 && MAX_IMG == 16) {
+        // a cell's 16 values are 64 contiguous bytes (16-byte aligned): four
+        // 16-byte stores per lane instead of sixteen 4-byte ones
+        if (nq == 16) {
+          float4 *o4 = reinterpret_cast<float4 *>(out);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            o4[k] = make_float4(vals[4 * k], vals[4 * k + 1], vals[4 * k + 2], vals[4 * k + 3]);
+          continue;
+        }
+      }
 #pragma unroll
       for (int q = 0; q < MAX_IMG; ++q) {
         if (q >= nq) break;
-        double val = em[q];
-        if (ss && r > 0.0) {
-          int j = M.img_j[q];
-          val += (double)ss[((uint64_t)v * nq + q) * M.ncell + c] * M.ssca_unit /
-                 (M.V * M.tab[o.w + j] * r * M.tab[o.kext + j]);
-        }
-        out[q] = (R)val;
+        out[q] = vals[q];
       }
     }
   }

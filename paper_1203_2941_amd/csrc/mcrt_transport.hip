@@ -813,7 +813,7 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
         R cb = P.d[0] * (R)M.kv[v][0] + P.d[1] * (R)M.kv[v][1] + P.d[2] * (R)M.kv[v][2];
         // sums kept in units of ssca_unit (the packet energy): erg/s sums overflow FP32
         R add = (R)(M.xi / M.ssca_unit) * hg_phase<R>(g, cb);
-        gatomic_add((R *)M.ssca + ((int64_t)v * M.nimg + q) * X.nc + c, add);
+        gatomic_add((R *)M.ssca + ((int64_t)v * X.nc + c) * M.nimg + q, add);
       }
     }
     rotate_dir<R>(P.d, mu, (R)2 * (R)PI_D * uph);
