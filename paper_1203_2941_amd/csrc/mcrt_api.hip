@@ -89,6 +89,7 @@ struct mcrt_ctx {
   void *d_rtab = nullptr;
   int32_t *d_imgmap = nullptr;
   double *d_herm = nullptr;
+  double *d_mrw_ub = nullptr;  // MRW pre-test bound per herm node interval (FP32 walk)
   float *d_rej_pe = nullptr;   // FP32 re-emission proposal tables (alias prob, envelope)
   uint8_t *d_rej_al = nullptr;
   size_t tab_cap = 0, rtab_cap = 0;
@@ -245,7 +246,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_occ, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_rej_pe, ctx->d_rej_al, ctx->d_k, ctx->d_epath,
+  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_occ, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_mrw_ub, ctx->d_rej_pe, ctx->d_rej_al, ctx->d_k, ctx->d_epath,
                 ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
                 ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_ctl, ctx->d_q, ctx->d_stats,
                 ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
@@ -596,6 +597,40 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
   HIPCHK(dev_alloc((void **)&ctx->d_imgmap, (size_t)nl * 4));
   HIPCHK(dev_alloc((void **)&ctx->d_herm, herm.size() * 8));
   HIPCHK(hipMemcpy(ctx->d_herm, herm.data(), herm.size() * 8, hipMemcpyHostToDevice));
+  // MRW pre-test without the temperature: for node interval k of the first
+  // thermal species' table, the largest Rosseland bound (krmax) of every
+  // T-interval that ln T from nodes k-1 .. k+2 falls in. The Hermite value
+  // on interval k lies between nodes k and k+1 up to ~1e-10; the extra node
+  // on each side covers that and an interval index taken from an FP32 log.
+  {
+    int s0 = 0;
+    while (s0 < ns && s0 == ctx->pah) ++s0;
+    const double *hh = s0 < ns ? &herm[(size_t)s0 * HS] : nullptr;
+    if (hh && (int)hh[2] == NH_TAB) {
+      auto tidx = [&](double lnT) {  // T-interval of krmax as the MRW test takes it
+        const double xk = (lnT - lt0) / dlt;
+        return (xk >= 0.0 && xk < (double)(NT_TAB - 1)) ? (int)xk : NT_TAB - 1;
+      };
+      std::vector<double> ub(NH_TAB - 1);
+      for (int k = 0; k < NH_TAB - 1; ++k) {
+        const int a = k > 0 ? k - 1 : 0, b = k + 2 < NH_TAB ? k + 2 : NH_TAB - 1;
+        const double la = hh[3 + 2 * a] - 1e-9, lb = hh[3 + 2 * b] + 1e-9;
+        int ka = tidx(la), kb = tidx(lb);
+        double mx = 0.0;
+        if (ka > kb || la < lt0) mx = t[o.krmax + NT_TAB - 1];
+        if (ka <= kb)
+          for (int kk = ka; kk <= kb; ++kk) mx = std::max(mx, t[o.krmax + kk]);
+        else
+          for (int kk = 0; kk < NT_TAB; ++kk) mx = std::max(mx, t[o.krmax + kk]);
+        ub[k] = mx;
+      }
+      HIPCHK(dev_alloc((void **)&ctx->d_mrw_ub, ub.size() * 8));
+      HIPCHK(hipMemcpy(ctx->d_mrw_ub, ub.data(), ub.size() * 8, hipMemcpyHostToDevice));
+    } else if (ctx->d_mrw_ub) {
+      (void)hipFree(ctx->d_mrw_ub);
+      ctx->d_mrw_ub = nullptr;
+    }
+  }
   HIPCHK(dev_alloc((void **)&ctx->d_rej_pe, rej_pe.size() * 4));
   HIPCHK(dev_alloc((void **)&ctx->d_rej_al, rej_al.size()));
   if (!rej_pe.empty()) {
@@ -988,6 +1023,7 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.rtab = ctx->d_rtab;
   M.imgmap = ctx->d_imgmap;
   M.herm = ctx->d_herm;
+  M.mrw_ub = ctx->d_mrw_ub;
   M.rej_pe = ctx->d_rej_pe;
   M.rej_al = ctx->d_rej_al;
   for (int q = 0; q < ctx->nimg; ++q) M.img_j[q] = ctx->img_idx[q];

@@ -134,6 +134,8 @@ struct ModelDev {
   const void *rtab;           // packed R table
   const int32_t *imgmap;      // [nl] -> imaged index or -1
   const double *herm;         // [ns][3 + 2*NH_TAB]: u0, du, n, then (ln T, dlnT/dlnPhi) per node
+  const double *mrw_ub;       // [NH_TAB - 1] or null: Rosseland bound per node interval of the
+                              // first thermal species' herm table (see build_tables)
   const float *rej_pe;        // FP32 walk: [2 modes][ns][NK_REJ][nl] (alias prob, envelope) pairs
   const uint8_t *rej_al;      // FP32 walk: [2 modes][ns][NK_REJ][nl] alias bins
   int32_t img_j[MAX_IMG];     // wavelength index of each imaged wavelength

@@ -109,6 +109,25 @@ __device__ __forceinline__ void absorb_pair(float x, float &om, float &e) {
 // S[v][c][q] = sum_s f_s kabs_s B(T_s)/kext + Ssca/(V w rho kext): one lane
 // per cell evaluates the view-independent emission once and writes the
 // 16-wide source vector of every view.
+// One cell's S row (nq values, contiguous): four 16-byte loads for 16 FP32
+// values, else one load per value.
+template <typename R>
+__device__ __forceinline__ void load_row(const R *sc, int nq, R out[MAX_IMG]) {
+  if constexpr (sizeof(R) == 4 && MAX_IMG == 16) {
+    if (nq == 16) {
+      const float4 *s4 = reinterpret_cast<const float4 *>(sc);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4 w = s4[k];
+        out[4 * k] = w.x; out[4 * k + 1] = w.y; out[4 * k + 2] = w.z; out[4 * k + 3] = w.w;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MAX_IMG; ++q) out[q] = q < nq ? sc[q] : (R)0;
+}
+
 template <typename R>
 __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
   const ModelDev &M = *md;
@@ -222,7 +241,8 @@ __global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R
     walk(A, pe, dir, c, [&](int64_t cell, double ell) {
       R r = rho[cell];
       if (!(r > (R)0)) return;
-      const R *sc = S + (uint64_t)cell * nq;
+      R sc[MAX_IMG];
+      load_row(S + (uint64_t)cell * nq, nq, sc);
       R el = (R)ell;
 #pragma unroll
       for (int q = 0; q < MAX_IMG; ++q) {

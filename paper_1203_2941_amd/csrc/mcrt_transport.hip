@@ -527,6 +527,19 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
     const double rmin = M.xi / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * M.V);
     if (rmin >= 1.001 * M.phi_tmin && !(rho * M.kr_gmax * M.dcell > M.mrw_tau)) return false;
   }
+  if (!REC && M.mode == M_BW_TICKET && M.mrw_ub) {
+    // the table interval that Eq. 4 would take for this cell bounds kappa_R
+    // at its temperature (mrw_ub): one lookup may rule the step out before T
+    // is inverted. The right-hand side is mode_T's.
+    const int64_t q0 = (int64_t)s0 * X.nc + c;
+    const double e = (double)gld(&M.k[q0]) * M.xi + gld(&M.epath[q0]);
+    const double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * M.V);
+    const double *h = M.herm + (size_t)s0 * (3 + 2 * NH_TAB);
+    const float x = (__logf((float)rhs) - (float)h[0]) / (float)h[1];
+    if (x >= 1.0f && x < (float)(NH_TAB - 3)) {
+      if (!(rho * gld(M.mrw_ub + (int)x) * M.dcell > M.mrw_tau)) return false;
+    }
+  }
   double T0 = mode_T(X, s0, c, rho);
   if (!REC) {
     // rigorous upper bound of kappa_R(T) on its table interval: skip the
