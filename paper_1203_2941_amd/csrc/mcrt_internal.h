@@ -181,6 +181,28 @@ __device__ __forceinline__ uint32_t brick_index32(int cx, int cy, int cz, int nb
   return (b << 6) | (uint32_t)(((cz & 3) << 4) | ((cy & 3) << 2) | (cx & 3));
 }
 
+// Cell of bricked index i (the inverse of brick_index / brick_index32).
+template <typename Idx>
+__host__ __device__ __forceinline__ void unbrick(Idx i, int nbx, int nby, int &cx, int &cy,
+                                                 int &cz) {
+  const uint32_t w = (uint32_t)i & 63u;
+  if constexpr (sizeof(Idx) == 4) {
+    const uint32_t b = (uint32_t)i >> 6;
+    const uint32_t r = b / (uint32_t)nbx, bx = b - r * (uint32_t)nbx;
+    const uint32_t bz = r / (uint32_t)nby, by = r - bz * (uint32_t)nby;
+    cx = (int)(bx * 4u + (w & 3u));
+    cy = (int)(by * 4u + ((w >> 2) & 3u));
+    cz = (int)(bz * 4u + (w >> 4));
+  } else {
+    const uint64_t b = (uint64_t)i >> 6;
+    const uint64_t r = b / (uint64_t)nbx, bx = b - r * (uint64_t)nbx;
+    const uint64_t bz = r / (uint64_t)nby, by = r - bz * (uint64_t)nby;
+    cx = (int)(bx * 4u + (w & 3u));
+    cy = (int)(by * 4u + ((w >> 2) & 3u));
+    cz = (int)(bz * 4u + (w >> 4));
+  }
+}
+
 // ---------------------------------------------------------------- RNG
 // Philox4x32-10 (Salmon et al. 2011); key = seed, counter = (draw block,
 // packet id low word, packet id bits 32-47 | iteration << 16,

@@ -329,7 +329,6 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   using Idx = typename std::conditional<I32, uint32_t, int64_t>::type;
   Idx cs[K];
   R ts[K + 1], rh[K];  // ts[k]: distance at the start of step k (ts[ns]: at its end)
-  uint32_t mv = 0;  // exit axis of step k in bits 2k..2k+1
   int ns = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -350,7 +349,6 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
       if (tn > t) t = tn;
       // the segment length max(tn - t, 0) is ts[k + 1] - ts[k]
       const bool mx = !(b1 || b2), my = b1 && !b2;
-      mv |= (uint32_t)(b2 ? 2 : (b1 ? 1 : 0)) << (2 * k);
       cx += mx ? sx : 0;
       cy += my ? sy : 0;
       cz += b2 ? sz : 0;
@@ -392,51 +390,52 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
 #pragma unroll
   for (int k = 0; k < K; ++k)
     rh[k] = ((ow[k] >> ((uint32_t)(cs[k] >> X.osh) & 31u)) & 1u) ? gld(X.rho_b + cs[k]) : (R)0;
-  // cell of step k: the current cell with the moves of steps k .. ns-1 undone
-  auto cell_of = [&](int k, int &ux, int &uy, int &uz) {
-    ux = cx; uy = cy; uz = cz;
-#pragma unroll
-    for (int j = K - 1; j >= 0; --j) {
-      if (j >= k && j < ns) {
-        const uint32_t a = (mv >> (2 * j)) & 3u;
-        ux -= (a == 0) ? sx : 0;
-        uy -= (a == 1) ? sy : 0;
-        uz -= (a == 2) ? sz : 0;
-      }
-    }
+  // linear cell index of a bricked index (Lucy deposits)
+  auto lin = [&](Idx i) {
+    int ux, uy, uz;
+    unbrick(i, X.nbx, X.nby, ux, uy, uz);
+    return ((int64_t)uz * X.ny + uy) * X.nx + ux;
   };
-  auto lin = [&](int ux, int uy, int uz) { return ((int64_t)uz * X.ny + uy) * X.nx + ux; };
+  // segments in order; the flight stops in the first whose depth reaches
+  // tau_star (its slot is kept and its cell recovered from the bricked
+  // index once, after the loop)
+  int kint = -1;
+  R tint = (R)0, rint = (R)0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    if (k < ns) {
+    if (k < ns && kint < 0) {
       const R rho = rh[k];
       const R ell = ts[k + 1] - ts[k];
       const R dtau = rho * kx * ell;
       const bool thin = is_thin(X, rho);
       if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tau_star) / tau_star));
       if (tau + dtau > tau_star) {
-        const R tint = ts[k] + (tau_star - tau) / (rho * kx);
-        int ux, uy, uz;
-        cell_of(k, ux, uy, uz);
-        if (thin) lucy_deposit(X, P, lin(ux, uy, uz), rho, tint - ts[k]);
-        P.p[0] = p0x + tint * dx;
-        P.p[1] = p0y + tint * dy;
-        P.p[2] = p0z + tint * dz;
-        P.c[0] = ux; P.c[1] = uy; P.c[2] = uz;
-        P.rho = rho;
-        F.tau = tau;
-        return 1;
+        tint = ts[k] + (tau_star - tau) / (rho * kx);
+        rint = rho;
+        kint = k;
+        if (thin) lucy_deposit(X, P, lin(cs[k]), rho, tint - ts[k]);
+      } else {
+        if (thin) lucy_deposit(X, P, lin(cs[k]), rho, ell);
+        tau += dtau;
+        P.n_cross++;
       }
-      if (thin) {
-        int ux, uy, uz;
-        cell_of(k, ux, uy, uz);
-        lucy_deposit(X, P, lin(ux, uy, uz), rho, ell);
-      }
-      tau += dtau;
-      P.n_cross++;
     }
   }
   F.tau = tau;
+  if (kint >= 0) {
+    Idx ci = cs[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k)
+      if (k == kint) ci = cs[k];
+    int ux, uy, uz;
+    unbrick(ci, X.nbx, X.nby, ux, uy, uz);
+    P.p[0] = p0x + tint * dx;
+    P.p[1] = p0y + tint * dy;
+    P.p[2] = p0z + tint * dz;
+    P.c[0] = ux; P.c[1] = uy; P.c[2] = uz;
+    P.rho = rint;
+    return 1;
+  }
   if (!out) return 0;
   P.p[0] = p0x + t * dx;
   P.p[1] = p0y + t * dy;
