@@ -254,7 +254,7 @@ __device__ __forceinline__ void lucy_deposit(Ctx<R> &X, Pkt<R> &P, int64_t c, R 
 // on the density, only where the flight stops does, so each lane walks K
 // cells ahead, issues K independent loads, then consumes the segments in
 // order (same arithmetic and order as a one-cell-at-a-time walk).
-template <typename R> struct Ahead { static constexpr int K = 8; };
+template <typename R> struct Ahead { static constexpr int K = 16; };
 template <> struct Ahead<double> { static constexpr int K = 2; };
 
 // State of a flight in progress (kept per lane across event cycles). The
