@@ -330,22 +330,23 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
   const R *rho = (const R *)A.rho;
   const R *S = (const R *)A.S + (uint64_t)v * A.ncell * nq;
   const uint64_t plane = (uint64_t)A.npx * A.npy;
-  double W[MAX_IMG], I[MAX_IMG], tr[MAX_IMG], acc[MAX_IMG];
-  R kx[MAX_IMG];
+  // wk = W kext (the weight of dI in dL/drho per unit length); rem = the
+  // intensity that reaches the pixel from behind the current cell (I of the
+  // whole ray less what the cells up to here contribute)
+  double wk[MAX_IMG], rem[MAX_IMG], tr[MAX_IMG];
   bool any = false;
 #pragma unroll
   for (int q = 0; q < MAX_IMG; ++q) {
-    W[q] = 0.0;
+    double W = 0.0;
     if (q < nq) {
-      W[q] = (w_img ? (double)w_img[((uint64_t)v * nq + q) * plane + pix] : 0.0) +
-             (w_sed ? w_sed[v * nq + q] : 0.0);
-      W[q] *= V.apix_d2;
+      W = (w_img ? (double)w_img[((uint64_t)v * nq + q) * plane + pix] : 0.0) +
+          (w_sed ? w_sed[v * nq + q] : 0.0);
+      W *= V.apix_d2;
     }
-    any |= (W[q] != 0.0);
-    I[q] = 0.0;
+    any |= (W != 0.0);
+    wk[q] = q < nq ? W * A.kext[q] : 0.0;
+    rem[q] = 0.0;
     tr[q] = 1.0;
-    acc[q] = 0.0;
-    kx[q] = (R)A.kext[q];
   }
   if (!any) return;
   double pe[3], dir[3];
@@ -360,8 +361,8 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
     for (int q = 0; q < MAX_IMG; ++q) {
       if (q >= nq) break;
       R om, e;
-      absorb_pair(r * kx[q] * el, om, e);
-      I[q] += tr[q] * (double)sc[q] * (double)om;
+      absorb_pair(r * (R)A.kext[q] * el, om, e);
+      rem[q] += tr[q] * (double)sc[q] * (double)om;
       tr[q] *= (double)e;
     }
   });
@@ -377,11 +378,11 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
     for (int q = 0; q < MAX_IMG; ++q) {
       if (q >= nq) break;
       R om, e;
-      absorb_pair(r * kx[q] * el, om, e);
+      absorb_pair(r * (R)A.kext[q] * el, om, e);
       double Sq = (double)sc[q];
-      acc[q] += tr[q] * Sq * (double)om;
-      double dI = tr[q] * Sq * (double)e - (I[q] - acc[q]);
-      g += W[q] * A.kext[q] * ell * dI;
+      rem[q] -= tr[q] * Sq * (double)om;
+      double dI = tr[q] * Sq * (double)e - rem[q];
+      g += wk[q] * ell * dI;
       tr[q] *= (double)e;
     }
     if (g != 0.0) atomicAdd(&drho[cell], (R)g);
