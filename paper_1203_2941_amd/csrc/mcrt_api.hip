@@ -1086,7 +1086,7 @@ static mcrt_status set_range(mcrt_ctx *ctx, uint64_t first, uint64_t n, hipStrea
 // Wavefront queues: two queues of Q packets as structures of arrays,
 // carved from one allocation (256-byte aligned arrays).
 static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n) {
-  uint64_t want = (o && o->queue_depth > 0) ? (uint64_t)o->queue_depth : (1ull << 23);
+  uint64_t want = (o && o->queue_depth > 0) ? (uint64_t)o->queue_depth : (1ull << 25);
   if (want > (1ull << 26)) want = 1ull << 26;
   uint64_t need = (n + 4095) / 4096 * 4096;
   if (need < 4096) need = 4096;

@@ -28,14 +28,14 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-TRANSPORT_SOURCES = ("csrc/mcrt_transport.hip", "csrc/mcrt_internal.h")
+TRANSPORT_SOURCES = ("csrc/mcrt_transport.hip", "csrc/mcrt_internal.h", "csrc/mcrt_api.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_wf_walk_torus256_1e8_traffic.md")
 TRANSPORT_KERNEL = "k_wf_walk<float, false, true>"
 CALIB_KERNEL = "MulFunctor"
 
 
 def source_digest() -> str:
-    """sha256 over the sources of the transport kernel."""
+    """sha256 over the sources of the transport kernels and their round loop."""
     h = hashlib.sha256()
     for rel in TRANSPORT_SOURCES:
         with open(os.path.join(HERE, rel), "rb") as f:
