@@ -228,12 +228,10 @@ __global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R
   const R *rho = (const R *)A.rho;
   const R *S = (const R *)A.S + (uint64_t)v * A.ncell * nq;
   double I[MAX_IMG], tr[MAX_IMG];
-  R kx[MAX_IMG];
 #pragma unroll
   for (int q = 0; q < MAX_IMG; ++q) {
     I[q] = 0.0;
     tr[q] = 1.0;
-    kx[q] = (R)A.kext[q];
   }
   double pe[3], dir[3];
   int c[3];
@@ -247,7 +245,7 @@ __global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R
 #pragma unroll
       for (int q = 0; q < MAX_IMG; ++q) {
         if (q >= nq) break;
-        R dtau = r * kx[q] * el;
+        R dtau = r * (R)A.kext[q] * el;
         R om, e;
         absorb_pair(dtau, om, e);
         I[q] += tr[q] * (double)sc[q] * (double)om;
