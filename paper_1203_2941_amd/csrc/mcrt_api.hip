@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
@@ -34,7 +35,10 @@ hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, boo
 size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, int occ_words, bool fp64);
 hipError_t launch_occ(bool fp64, const void *rb, uint32_t *occ, uint64_t ncell_b, int osh,
                       hipStream_t st);
+hipError_t launch_wf_finish(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
+                            int grid, size_t lds, bool idx32, hipStream_t st);
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
+                          uint32_t *left,
                           hipStream_t st);
 hipError_t launch_sample_reem(const ModelDev *d, bool fp64, int s, double T, uint64_t n,
                               uint64_t seed, unsigned long long *counts, size_t lds,
@@ -1156,17 +1160,40 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
   const int gwalk = ctx->num_cu * ((o && o->walk_blocks_per_cu > 0) ? o->walk_blocks_per_cu : 4);
   const bool rec = o->record != 0;
   const int every = 4;
+  // the finishing kernel takes over once every packet has been started and
+  // the survivors fit one lane each at two blocks of 256 per CU
+  const size_t lds_f = lds + (size_t)ctx->ow * 4;
+  const uint32_t fin_max = (uint32_t)ctx->num_cu * 2u * 256u;
   for (uint64_t r = 0;; ++r) {
     const int fcur = (int)(r & 1);
     const hipEvent_t *ev = phase_events(ctx);
     HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w,
                            idx32_ok(ctx), ev, st));
     if ((r + 1) % every == 0) {
-      HIPCHK(launch_wf_busy(ctx->d_model, 1, fcur, &ctx->d_ctl->busy, st));
-      HIPCHK(hipMemcpyAsync(&ctx->h_ctl->busy, &ctx->d_ctl->busy, 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(launch_wf_busy(ctx->d_model, 1, fcur, &ctx->d_ctl->busy, &ctx->d_ctl->left, st));
+      // emitted .. left: the header of the counters
+      HIPCHK(hipMemcpyAsync(ctx->h_ctl, ctx->d_ctl, offsetof(WfCtl, pad), hipMemcpyDeviceToHost,
+                            st));
       HIPCHK(hipStreamSynchronize(st));
       phase_collect(ctx);
       if (ctx->h_ctl->busy == 0u) break;
+      if (ctx->h_ctl->emitted >= n && ctx->h_ctl->left <= fin_max && lds_f <= ctx->lds_max) {
+        // timed as one more round whose walk phase is the finishing kernel
+        const hipEvent_t *fe = phase_events(ctx);
+        if (fe) {
+          HIPCHK(hipEventRecord(fe[0], st));
+          HIPCHK(hipEventRecord(fe[1], st));
+        }
+        HIPCHK(launch_wf_finish(ctx->d_model, 1, ctx->fp64, rec, 1 - fcur, gfull, lds_f,
+                                idx32_ok(ctx), st));
+        if (fe) {
+          HIPCHK(hipEventRecord(fe[2], st));
+          HIPCHK(hipEventRecord(fe[3], st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        phase_collect(ctx);
+        break;
+      }
     }
     if (r > (1ull << 32)) return fail(ctx, MCRT_EDEVICE, "transport did not finish");
   }
@@ -1946,7 +1973,8 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   for (int r = 0; r < ROUNDS && le == hipSuccess; ++r)
     le = launch_wf_round(ctx->d_batch, n_models, ctx->fp64, false, r & 1, gfull, gwalk, lds, lds_w,
                          idx32, nullptr, cs_);
-  if (le == hipSuccess) le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, cs_);
+  if (le == hipSuccess)
+    le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, nullptr, cs_);
   hipError_t ce = hipStreamEndCapture(cs_, &graph);
   if (le != hipSuccess || ce != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);

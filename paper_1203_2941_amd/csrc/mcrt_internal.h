@@ -111,7 +111,8 @@ struct WfCtl {
   uint32_t take;     // packets emitted this round
   uint32_t busy;     // models with packets left (written by k_wf_busy)
   uint32_t inq;      // upper bound of this round's flight-ready packets (plan)
-  uint32_t pad[25];
+  uint32_t left;     // packets queued for the next round, all models (k_wf_busy)
+  uint32_t pad[24];
   uint32_t nseg[2][NSEG][CLINE];  // entries appended to segment g of queue f (clamp to capacity)
   uint32_t work[3][NSEG][CLINE];  // next entry of segment g handed out by emit, walk, interact
 };

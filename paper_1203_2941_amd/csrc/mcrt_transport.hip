@@ -884,7 +884,7 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
 // factors) and the SED; the other kernels take every table.
 template <typename R>
 __device__ void stage_model(Ctx<R> &X, const ModelDev &M, unsigned char *lds_raw,
-                            unsigned long long *s_stat, bool full) {
+                            unsigned long long *s_stat, bool full, bool with_occ = false) {
   X.M = &M;
   X.o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
   X.nc = (int64_t)M.ncell;
@@ -910,13 +910,13 @@ __device__ void stage_model(Ctx<R> &X, const ModelDev &M, unsigned char *lds_raw
   const int nsed = (M.ntheta > 0 ? M.ntheta : 1) * M.nl;
   for (int i = threadIdx.x; i < nsed; i += blockDim.x) sed[i] = 0u;
   uint32_t *occ = sed + nsed;
-  if (!full) {
+  if (!full || with_occ) {
 #pragma unroll 8
     for (int i = threadIdx.x; i < M.ow; i += blockDim.x) occ[i] = gld(M.occ + i);
   }
   if (threadIdx.x < NSTAT) s_stat[threadIdx.x] = 0ull;
   __syncthreads();
-  X.occ = full ? nullptr : occ;
+  X.occ = (!full || with_occ) ? occ : nullptr;
   X.dt = full ? dt : nullptr;
   X.rt = rt;
   X.imgmap = im;
@@ -1295,25 +1295,117 @@ hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, boo
 
 // Number of models with packets left after a round whose emptied queue
 // was fcur (one block; nmodels <= 1024).
+// (and, when `left` is not null, the packets queued for the next round)
 __global__ void k_wf_busy(const ModelDev *__restrict__ models, int nmodels, int fcur,
-                          uint32_t *busy) {
-  __shared__ uint32_t s_busy;
-  if (threadIdx.x == 0) s_busy = 0u;
+                          uint32_t *busy, uint32_t *left) {
+  __shared__ uint32_t s_busy, s_left;
+  if (threadIdx.x == 0) s_busy = s_left = 0u;
   __syncthreads();
   for (int m = threadIdx.x; m < nmodels; m += blockDim.x) {
     const ModelDev &M = models[m];
     const WfCtl *c = M.ctl;
     bool live = c->emitted < M.n;
-    for (int g = 0; g < NSEG && !live; ++g) live = seg_count(c, 1 - fcur, g, M.qseg) > 0u;
+    uint32_t q = 0u;
+    for (int g = 0; g < NSEG; ++g) q += seg_count(c, 1 - fcur, g, M.qseg);
+    live = live || q > 0u;
     if (live) atomicAdd(&s_busy, 1u);
+    atomicAdd(&s_left, q);
   }
   __syncthreads();
-  if (threadIdx.x == 0) *busy = s_busy;
+  if (threadIdx.x == 0) {
+    *busy = s_busy;
+    if (left) *left = s_left;
+  }
 }
 
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_wf_busy, dim3(1), dim3(256), 0, st, d_models, nmodels, fcur, busy);
+                          uint32_t *left, hipStream_t st) {
+  hipLaunchKernelGGL(k_wf_busy, dim3(1), dim3(256), 0, st, d_models, nmodels, fcur, busy, left);
+  return hipGetLastError();
+}
+
+// The last packets of a launch, once every packet has been started: each
+// lane takes a flight-ready entry of queue fcur and follows its packet
+// through every flight and interaction until it ends, with the device
+// functions and draw order of the rounds (so each packet's history is the
+// same). Late rounds hold few packets and are as long as their longest
+// flight; this replaces them by one launch. A packet still going after
+// FINISH_MAX_EVENTS flights in this kernel is ended as killed, so every lane
+// reaches the end (no physical packet comes near it).
+constexpr uint32_t FINISH_MAX_EVENTS = 1u << 22;
+
+template <typename R, bool REC, bool I32>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_wf_finish(const ModelDev *__restrict__ models, int nmodels, int fcur) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ unsigned long long s_stat[NSTAT];
+  const int lane = threadIdx.x & 63;
+  for (int mm = 0; mm < nmodels; ++mm) {
+    const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
+    WfCtl *c = M.ctl;
+    if (c->inq == 0u) continue;
+    Ctx<R> X;
+    stage_model<R>(X, M, lds_raw, s_stat, true, true);
+    const QBuf &qi = M.q[fcur];
+    const uint32_t S = M.qseg;
+    auto seg = [&](int s, uint32_t &beg, uint32_t &cnt) {
+      beg = (uint32_t)s * S;
+      cnt = seg_count(c, fcur, s, S);
+    };
+    int g = home_segment();
+    uint32_t lo, hi;
+    while (seg_grab(c, 1, g, lane, lo, hi, seg)) {
+      const uint32_t i = lo + (uint32_t)lane;
+      if (i >= hi) continue;
+      Pkt<R> P;
+      Flight<R> F;
+      R tau = q_load<R, REC>(M, qi, i, P);
+      for (uint32_t ev = 0;; ++ev) {
+        if (ev >= FINISH_MAX_EVENTS) {
+          P.status = ST_KILLED;
+          finish<R, REC>(X, P, true);
+          break;
+        }
+        flight_setup<R>(X, P, F, tau);
+        const uint32_t c0 = P.n_cross, l0 = P.n_lucy;
+        int r;
+        do {
+          r = flight_batch<R, REC, I32>(X, P, F);
+        } while (r == 0);
+        stat_add(X.st, 4, (unsigned long long)(P.n_cross - c0));
+        if (P.n_lucy != l0) stat_add(X.st, 8, (unsigned long long)(P.n_lucy - l0));
+        if (r == 2) {
+          P.status = ST_ESCAPED;
+          finish<R, REC>(X, P, true);
+          break;
+        }
+        interact<R, REC>(X, P);
+        if (P.status == ST_ALIVE) tau = flight_tau<R, REC>(X, P);
+        if (P.status != ST_ALIVE) {
+          finish<R, REC>(X, P, true);
+          break;
+        }
+      }
+    }
+    flush_block(X);
+  }
+}
+
+// Plan of the next round (no new packets remain) and the finishing kernel.
+hipError_t launch_wf_finish(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
+                            int grid, size_t lds, bool idx32, hipStream_t st) {
+  hipLaunchKernelGGL(k_wf_plan, dim3(nmodels), dim3(64), 0, st, d_models, nmodels, fcur);
+#define MCRT_FIN(RT, RC, IX)                                                                    \
+  hipLaunchKernelGGL((k_wf_finish<RT, RC, IX>), dim3(grid), dim3(256), lds, st, d_models, nmodels, \
+                     fcur)
+  if (fp64) {
+    if (rec) { if (idx32) MCRT_FIN(double, true, true); else MCRT_FIN(double, true, false); }
+    else { if (idx32) MCRT_FIN(double, false, true); else MCRT_FIN(double, false, false); }
+  } else {
+    if (rec) { if (idx32) MCRT_FIN(float, true, true); else MCRT_FIN(float, true, false); }
+    else { if (idx32) MCRT_FIN(float, false, true); else MCRT_FIN(float, false, false); }
+  }
+#undef MCRT_FIN
   return hipGetLastError();
 }
 
