@@ -1923,7 +1923,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device));
   std::vector<ModelDev> hm(n_models);
-  size_t lds = 0, lds_w = 0;
+  size_t lds = 0, lds_w = 0, lds_f = 0;
   bool idx32 = true;
   for (int m = 0; m < n_models; ++m) {
     mcrt_ctx *c = models[m];
@@ -1942,6 +1942,9 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
     if (b > lds) lds = b;
     b = walk_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->ow, c->fp64);
     if (b > lds_w) lds_w = b;
+    b = transport_lds_bytes(c->nl, c->ns, c->nsrc, c->nrows, c->ntheta, c->fp64) +
+        (size_t)c->ow * 4;
+    if (b > lds_f) lds_f = b;
   }
   if (lds > ctx->lds_max || lds_w > ctx->lds_max)
     return fail(ctx, MCRT_EINVAL, "batch tables need %zu bytes of LDS (limit %zu)", lds > lds_w ? lds : lds_w, ctx->lds_max);
@@ -1965,6 +1968,11 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   // replayed on the caller's until no model has packets left
   constexpr int ROUNDS = 8;
   uint32_t *d_busy = &ctx->d_ctl->busy;  // address arithmetic only
+  uint32_t *d_left = &ctx->d_ctl->left;
+  static_assert(offsetof(WfCtl, inq) == offsetof(WfCtl, busy) + 4 &&
+                    offsetof(WfCtl, left) == offsetof(WfCtl, busy) + 8,
+                "busy, inq and left are read back as one 12-byte copy");
+  const uint32_t fin_max = (uint32_t)ctx->num_cu * 2u * 256u;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cs_ = ctx->cap_stream;
@@ -1974,7 +1982,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
     le = launch_wf_round(ctx->d_batch, n_models, ctx->fp64, false, r & 1, gfull, gwalk, lds, lds_w,
                          idx32, nullptr, cs_);
   if (le == hipSuccess)
-    le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, nullptr, cs_);
+    le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, d_left, cs_);
   hipError_t ce = hipStreamEndCapture(cs_, &graph);
   if (le != hipSuccess || ce != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -1986,13 +1994,22 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   mcrt_status rs = MCRT_OK;
   for (uint64_t rep = 0;; ++rep) {
     hipError_t e = hipGraphLaunch(exec, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(&ctx->h_ctl->busy, d_busy, 4, hipMemcpyDeviceToHost, st);
+    // busy, inq, left
+    if (e == hipSuccess) e = hipMemcpyAsync(&ctx->h_ctl->busy, d_busy, 12, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
       rs = fail(ctx, MCRT_EDEVICE, "batch round: %s", hipGetErrorString(e));
       break;
     }
     if (ctx->h_ctl->busy == 0u) break;
+    if (ctx->h_ctl->left <= fin_max && lds_f <= ctx->lds_max) {
+      // every packet started and few left: the finishing kernel ends them
+      e = launch_wf_finish(ctx->d_batch, n_models, ctx->fp64, false, ROUNDS & 1, gfull, lds_f,
+                           idx32, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) rs = fail(ctx, MCRT_EDEVICE, "batch finish: %s", hipGetErrorString(e));
+      break;
+    }
     if (rep > (1ull << 30)) {
       rs = fail(ctx, MCRT_EDEVICE, "batch did not finish");
       break;

@@ -1295,26 +1295,28 @@ hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, boo
 
 // Number of models with packets left after a round whose emptied queue
 // was fcur (one block; nmodels <= 1024).
-// (and, when `left` is not null, the packets queued for the next round)
+// (and, when `left` is not null, the packets queued for the next round
+// over all models, or 0xFFFFFFFF while some model has packets not yet
+// started)
 __global__ void k_wf_busy(const ModelDev *__restrict__ models, int nmodels, int fcur,
                           uint32_t *busy, uint32_t *left) {
-  __shared__ uint32_t s_busy, s_left;
-  if (threadIdx.x == 0) s_busy = s_left = 0u;
+  __shared__ uint32_t s_busy, s_left, s_unstarted;
+  if (threadIdx.x == 0) s_busy = s_left = s_unstarted = 0u;
   __syncthreads();
   for (int m = threadIdx.x; m < nmodels; m += blockDim.x) {
     const ModelDev &M = models[m];
     const WfCtl *c = M.ctl;
-    bool live = c->emitted < M.n;
+    const bool unstarted = c->emitted < M.n;
     uint32_t q = 0u;
     for (int g = 0; g < NSEG; ++g) q += seg_count(c, 1 - fcur, g, M.qseg);
-    live = live || q > 0u;
-    if (live) atomicAdd(&s_busy, 1u);
+    if (unstarted || q > 0u) atomicAdd(&s_busy, 1u);
+    if (unstarted) atomicAdd(&s_unstarted, 1u);
     atomicAdd(&s_left, q);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     *busy = s_busy;
-    if (left) *left = s_left;
+    if (left) *left = s_unstarted ? 0xFFFFFFFFu : s_left;
   }
 }
 
