@@ -31,17 +31,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def walk_bytes(st, ns_thermal):
-    """Bytes the walk kernel must move for one run (FP32): 4 per cell
-    crossing (density gather), 64 per flight to read the queued packet
-    (positions, direction, density, depth: 8 x 4 B; cell and wavelength:
-    4 x 4 B; id 8 B; RNG position and interaction count 2 x 4 B), 64 per
-    flight ending in an interaction to write it back, 4 per escape to free
-    its entry, and 16 per Lucy deposit and thermal species (read-modify-
-    write of the FP64 path energy)."""
+def walk_bytes(st, ns_thermal, rs=4):
+    """Bytes the walk kernel must move for one run, for walk values of rs
+    bytes (4: FP32, 8: FP64): rs per cell crossing (density gather); per
+    flight the queued packet is read (positions, direction, density, depth:
+    8 x rs; cell and wavelength: 4 x 4 B; id 8 B; RNG position and
+    interaction count 2 x 4 B: 64 B in FP32) and, when it ends in an
+    interaction, written back; rs per escape to free its entry; 16 per Lucy
+    deposit and thermal species (read-modify-write of the FP64 path
+    energy)."""
     inter = st["scatters"] + st["absorptions"]
     flights = inter + st["escaped"]
-    return (4 * st["crossings"] + 64 * flights + 64 * inter + 4 * st["escaped"]
+    pk = 8 * rs + 32
+    return (rs * st["crossings"] + pk * flights + pk * inter + rs * st["escaped"]
             + 16 * ns_thermal * st["lucy_deposits"])
 
 
@@ -61,6 +63,8 @@ def main():
                     help="walk-kernel blocks per CU (0: the library default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0,
                     help="emission/interaction blocks per CU (0: the library default)")
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
+                    help="walk precision of the context (the benchmark line is fp32)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one elementwise copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -88,14 +92,16 @@ def main():
     views, idx = mi.image_views(n_views=8, n_img=16, nl=m.nl)
     D = 15.0 * mi.MPC_CM
     log(f"setup: torus {args.grid}^3, {N} packets, views {len(views)}, imaged {len(idx)}")
-    ctx = mc.Context(0, "fp32").from_inputs(m, views=views, img_idx=idx, distance=D)
+    fp64 = args.precision == "fp64"
+    ctx = mc.Context(0, args.precision).from_inputs(m, views=views, img_idx=idx, distance=D)
     npx = npy = args.npix
     rng = np.random.default_rng(5)
-    w_img = torch.tensor(rng.random((len(views), len(idx), npy, npx), dtype=np.float32),
+    fdt = torch.float64 if fp64 else torch.float32
+    w_img = torch.tensor(rng.random((len(views), len(idx), npy, npx)).astype(np.float64 if fp64 else np.float32),
                          device="cuda")
     img = torch.empty_like(w_img)
     sed = torch.empty((len(views), len(idx)), dtype=torch.float64, device="cuda")
-    grad = torch.empty(ctx.ncells, dtype=torch.float32, device="cuda")
+    grad = torch.empty(ctx.ncells, dtype=fdt, device="cuda")
     opts = dict(mode="bw_ticket", n_total=N, mrw_tau=50.0, mrw_gamma=2.0, lucy_tau=1e-2,
                 max_interactions=10_000_000, sed_theta_bins=10, queue_depth=args.queue_depth,
                 walk_blocks_per_cu=args.walk_blocks_per_cu, blocks_per_cu=args.blocks_per_cu)
@@ -142,7 +148,8 @@ def main():
     # roofline of the walk kernel (the largest share of the step): its
     # algorithmic bytes over its device time, both summed over the source
     # and PAH runs of a step; launches = rounds
-    b_alg = np.mean([walk_bytes(r[0], ns_th) + walk_bytes(r[1], ns_th) for r in rec])
+    rs = 8 if fp64 else 4
+    b_alg = np.mean([walk_bytes(r[0], ns_th, rs) + walk_bytes(r[1], ns_th, rs) for r in rec])
     t_walk = np.mean([r[4]["walk_ms"] for r in rec]) / 1e3
     t_emit = np.mean([r[4]["emit_ms"] for r in rec]) / 1e3
     t_int = np.mean([r[4]["interact_ms"] for r in rec]) / 1e3
@@ -150,7 +157,8 @@ def main():
     # bytes per launch measured by the committed counter runs, reported only
     # for the workload they were taken on and while the kernel is unchanged
     traffic = traffic_step = None
-    if N == 100_000_000 and args.grid == 256 and not args.queue_depth:
+    if (N == 100_000_000 and args.grid == 256 and not fp64 and not args.queue_depth
+            and not args.walk_blocks_per_cu and not args.blocks_per_cu):
         from paper_1203_2941_amd import profiling
         tr = profiling.read_traffic()
         if tr is not None:
@@ -166,14 +174,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if fp64 else "f32",
         "data": "synthetic",
         "config": {
             "workload": (f"clumpy AGN torus {args.grid}^3, 2000 clumps r=0.02 r_out, contrast 100, "
                          f"100 wavelengths, {N} packets, immediate B&W, MRW tau_R>50, PAH; "
                          f"ray-tracer {npx}x{npy} px x 16 wavelengths x 8 views fwd+adjoint"),
             "packets": N, "grid": args.grid, "wavelengths": int(m.nl), "views": len(views),
-            "imaged_wavelengths": len(idx), "pixels": [npx, npy], "precision": "fp32 walk, fp64 Eq. 4",
+            "imaged_wavelengths": len(idx), "pixels": [npx, npy],
+            "precision": ("fp64" if fp64 else "fp32 walk, fp64 Eq. 4"),
         },
         "cell_crossings_per_s": cross / (ms / 1e3),
         "transport_packets_per_s": N / t_tr,
@@ -189,7 +198,7 @@ def main():
                      "rounds": n_walk},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_wf_walk<float, false, true>",
+            "kernel": f"k_wf_walk<{'double' if fp64 else 'float'}, false, true>",
             "achieved": b_alg / t_walk / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
