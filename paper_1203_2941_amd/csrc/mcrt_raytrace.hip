@@ -427,8 +427,8 @@ __global__ void k_rt_star_adj(const RtArgs *__restrict__ Ap, const R *w_img, con
 }
 
 hipError_t launch_build_S(const ModelDev *d, bool fp64, void *S, hipStream_t st) {
-  if (fp64) hipLaunchKernelGGL(k_build_S<double>, dim3(8192), dim3(256), 0, st, d, (double *)S);
-  else hipLaunchKernelGGL(k_build_S<float>, dim3(8192), dim3(256), 0, st, d, (float *)S);
+  if (fp64) hipLaunchKernelGGL(k_build_S<double>, dim3(65536), dim3(256), 0, st, d, (double *)S);
+  else hipLaunchKernelGGL(k_build_S<float>, dim3(65536), dim3(256), 0, st, d, (float *)S);
   return hipGetLastError();
 }
 
