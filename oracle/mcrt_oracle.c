@@ -462,6 +462,13 @@ typedef struct {
   int pass;           /* 1: source + pass 1, 2: PAH re-emission pass */
   double *f;          /* scratch [nl] */
   double *fs;         /* scratch [ns] */
+  /* entries (s, cell) whose energy changed or whose epoch temperature was
+   * formed since the last epoch start: the only ones an epoch snapshot can
+   * change (bookkeeping only; the snapshot's values are those of a sweep
+   * over every entry) */
+  int64_t *touched;
+  uint8_t *is_touched;
+  int64_t n_touched;
 } run_t;
 
 typedef struct {
@@ -475,6 +482,13 @@ typedef struct {
 static int is_thin(const run_t *R, double rho) {
   return R->o->lucy_tau > 0.0 && rho > 0.0 &&
          rho * R->t.kext_max * R->m->dcell < R->o->lucy_tau;
+}
+
+static void touch(run_t *R, int64_t q) {
+  if (R->is_touched && !R->is_touched[q]) {
+    R->is_touched[q] = 1;
+    R->touched[R->n_touched++] = q;
+  }
 }
 
 static double e_cell(const run_t *R, int s, int64_t c) {
@@ -499,6 +513,7 @@ static double mode_T(run_t *R, int s, int64_t c) {
     R->st->tt[q] = invert_t(&R->t, s, rhs, &cl);
     if (cl) R->st->st.clamped_T++;
     R->st->tvalid[q] = 1;
+    touch(R, q);
   }
   return R->st->tt[q];
 }
@@ -512,6 +527,7 @@ static void lucy_deposit(run_t *R, pkt_t *P, int64_t c, double rho, double ell) 
   for (int s = 0; s < R->t.ns; s++) {
     if (s == R->m->pah_species) continue;
     R->st->epath[(int64_t)s * R->t.ncell + c] += R->xi * R->t.lucy_frac[s * nl + j] * em;
+    touch(R, (int64_t)s * R->t.ncell + c);
   }
   P->n_lucy++;
 }
@@ -587,6 +603,27 @@ static double planck_mean(const run_t *R, int s, double T) {
   return (den > 0.0) ? num / den : 0.0;
 }
 
+/* The two means above for a model, at temperature T (exported for tests). */
+double orc_rosseland(const orc_model *m, double T) {
+  run_t R;
+  memset(&R, 0, sizeof(R));
+  R.m = m;
+  tab_init(&R.t, m);
+  double r = rosseland(&R, T);
+  tab_free(&R.t);
+  return r;
+}
+
+double orc_planck_mean(const orc_model *m, int s, double T) {
+  run_t R;
+  memset(&R, 0, sizeof(R));
+  R.m = m;
+  tab_init(&R.t, m);
+  double r = planck_mean(&R, s, T);
+  tab_free(&R.t);
+  return r;
+}
+
 static int first_thermal(const run_t *R) {
   for (int s = 0; s < R->t.ns; s++)
     if (s != R->m->pah_species) return s;
@@ -641,6 +678,7 @@ static int mrw_step(run_t *R, pkt_t *P, rng_t *rg) {
     double Ts = mode_T(R, s, c);
     double kp = planck_mean(R, s, Ts);
     R->st->epath[(int64_t)s * R->t.ncell + c] += R->xi * rho * m->mass_frac[s] * kp * ell;
+    touch(R, (int64_t)s * R->t.ncell + c);
     for (int j = 0; j < nl; j++)
       R->f[j] += R->t.w[j] * m->mass_frac[s] * m->kabs[s * nl + j] * orc_planck(R->t.nu[j], Ts);
   }
@@ -790,7 +828,10 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
         P.j = pick_pah_lambda(R, pah_row(R, c), ul, &P.mm);
         iso_dir(uph, umu, P.d);
       } else {
-        if (!is_thin(R, m->rho[c])) R->st->k[(int64_t)s * t->ncell + c] += 1;
+        if (!is_thin(R, m->rho[c])) {
+          R->st->k[(int64_t)s * t->ncell + c] += 1;
+          touch(R, (int64_t)s * t->ncell + c);
+        }
         double T = mode_T(R, s, c);
         for (int q = 0; q < nl; q++) {
           double b = (R->o->mode == ORC_FROZEN) ? orc_planck(t->nu[q], T)
@@ -824,18 +865,28 @@ static void zero_tallies(const run_t *R) {
 }
 
 /* Start of an epoch: cells whose energy changed get a fresh snapshot and
- * lose their cached epoch temperature. */
-static void epoch_snapshot(run_t *R) {
+ * lose their cached epoch temperature. The first snapshot of a run visits
+ * every entry; later ones visit the touched entries, the only ones whose
+ * energy or cached temperature can have changed since. */
+static void snap_entry(run_t *R, int64_t q) {
+  double e = (double)R->st->k[q] * R->xi + R->st->epath[q];  /* E of Eq. 4 */
+  if (e != R->st->esnap[q] || !R->st->tvalid[q]) {
+    R->st->esnap[q] = e;
+    R->st->tvalid[q] = 0;
+  }
+}
+
+static void epoch_snapshot(run_t *R, int full) {
   int64_t nc = R->t.ncell;
-  for (int s = 0; s < R->t.ns; s++)
-    for (int64_t c = 0; c < nc; c++) {
-      int64_t q = s * nc + c;
-      double e = e_cell(R, s, c);
-      if (e != R->st->esnap[q] || !R->st->tvalid[q]) {
-        R->st->esnap[q] = e;
-        R->st->tvalid[q] = 0;
-      }
-    }
+  if (full || !R->is_touched) {
+    for (int64_t q = 0; q < (int64_t)R->t.ns * nc; q++) snap_entry(R, q);
+  } else {
+    for (int64_t i = 0; i < R->n_touched; i++) snap_entry(R, R->touched[i]);
+  }
+  if (R->is_touched) {
+    for (int64_t i = 0; i < R->n_touched; i++) R->is_touched[R->touched[i]] = 0;
+    R->n_touched = 0;
+  }
 }
 
 static void run_init(run_t *R, const orc_model *m, const orc_opts *o, uint64_t seed,
@@ -849,12 +900,19 @@ static void run_init(run_t *R, const orc_model *m, const orc_opts *o, uint64_t s
   R->xi = R->t.ltot / (double)o->n_total;
   R->f = malloc(sizeof(double) * m->nl);
   R->fs = malloc(sizeof(double) * m->ns);
+  if (o->mode == ORC_BW_EPOCH) {
+    int64_t nq = (int64_t)m->ns * R->t.ncell;
+    R->touched = malloc(sizeof(int64_t) * (size_t)nq);
+    R->is_touched = calloc((size_t)nq, 1);
+  }
 }
 
 static void run_free(run_t *R) {
   tab_free(&R->t);
   free(R->f);
   free(R->fs);
+  free(R->touched);
+  free(R->is_touched);
 }
 
 void orc_finalize_T(const orc_model *m, const orc_opts *o, orc_state *st) {
@@ -894,7 +952,7 @@ int orc_run(const orc_model *m, const orc_opts *o, uint64_t first, uint64_t n,
     uint64_t P = o->epoch > 0 ? o->epoch : 1;
     for (uint64_t i = 0; i < n; i++) {
       uint64_t pid = first + i;
-      if (i == 0 || pid % P == 0) epoch_snapshot(&R);
+      if (i == 0 || pid % P == 0) epoch_snapshot(&R, i == 0);
       run_packet(&R, pid, -1, i);
     }
   }
@@ -917,7 +975,7 @@ int orc_pah_pass(const orc_model *m, const orc_opts *o, uint64_t seed, orc_state
   uint64_t idx = 0;
   for (int64_t c = 0; c < nc; c++) {
     for (uint32_t r = 0; r < k1[c]; r++, idx++) {
-      if (o->mode == ORC_BW_EPOCH && (idx == 0 || idx % P == 0)) epoch_snapshot(&R);
+      if (o->mode == ORC_BW_EPOCH && (idx == 0 || idx % P == 0)) epoch_snapshot(&R, idx == 0);
       run_packet(&R, o->n_total + idx, c, idx);
     }
   }

@@ -100,6 +100,10 @@ double orc_planck(double nu, double T);
 double orc_dplanck_dT(double nu, double T);
 double orc_phi(const orc_model *m, int s, double T);            /* sum w kabs B */
 double orc_invert_T(const orc_model *m, int s, double rhs);     /* Eq. 4 */
+/* Rosseland mean of the mixture extinction and Planck mean of species s
+ * absorption at T (sect. 3.2 diffusion step), on the model's quadrature. */
+double orc_rosseland(const orc_model *m, double T);
+double orc_planck_mean(const orc_model *m, int s, double T);
 double orc_hg_mu(double g, double u);                           /* Eq. 15 CDF */
 double orc_hg_phase(double g, double mu);                       /* Eq. 15 */
 double orc_mrw_survival(double y);

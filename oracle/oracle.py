@@ -111,6 +111,10 @@ def lib():
         L.orc_phi.argtypes = [C.POINTER(Model), C.c_int, C.c_double]; L.orc_phi.restype = C.c_double
         L.orc_invert_T.argtypes = [C.POINTER(Model), C.c_int, C.c_double]
         L.orc_invert_T.restype = C.c_double
+        L.orc_rosseland.argtypes = [C.POINTER(Model), C.c_double]
+        L.orc_rosseland.restype = C.c_double
+        L.orc_planck_mean.argtypes = [C.POINTER(Model), C.c_int, C.c_double]
+        L.orc_planck_mean.restype = C.c_double
         L.orc_dda.argtypes = [C.POINTER(Model), _dp, _dp, C.c_int, C.POINTER(C.c_int64), _dp]
         L.orc_init_T.argtypes = [C.POINTER(Model), _dp]
         L.orc_run.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint64, C.c_uint64,
@@ -355,6 +359,14 @@ class Oracle:
 
     def invert_T(self, s, rhs):
         return lib().orc_invert_T(C.byref(self.m), s, rhs)
+
+    def rosseland(self, T):
+        """Rosseland mean of the mixture extinction at T [cm^2/g]."""
+        return lib().orc_rosseland(C.byref(self.m), T)
+
+    def planck_mean(self, s, T):
+        """Planck mean of species s absorption at T [cm^2/g]."""
+        return lib().orc_planck_mean(C.byref(self.m), s, T)
 
     def dda(self, p0, d, maxseg=10000):
         p0 = _f64(p0)
