@@ -183,7 +183,11 @@ static hipError_t dev_alloc(void **p, size_t bytes) {
     *p = nullptr;
   }
   if (bytes == 0) return hipSuccess;
-  return hipMalloc(p, bytes);
+  hipError_t e = hipMalloc(p, bytes);
+  // a failed allocation must not linger as the runtime's last error (a
+  // later hipGetLastError check would report it against another call)
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
 }
 
 template <typename T>
@@ -308,6 +312,7 @@ static mcrt_status ensure_ssca(mcrt_ctx *ctx) {
   size_t need = (size_t)ctx->nview * ctx->nimg * ctx->ncell * rsize(ctx);
   if (need == 0) return MCRT_OK;
   if (ctx->ssca_cap == need && ctx->d_ssca) return MCRT_OK;
+  ctx->ssca_cap = 0;
   HIPCHK(dev_alloc(&ctx->d_ssca, need));
   ctx->ssca_cap = need;
   HIPCHK(hipMemset(ctx->d_ssca, 0, need));
@@ -318,6 +323,7 @@ static mcrt_status ensure_ssca(mcrt_ctx *ctx) {
 static mcrt_status ensure_sed(mcrt_ctx *ctx, int ntheta) {
   int need = ntheta * ctx->nl;
   if (ctx->sed_cap == need && ctx->d_sed) return MCRT_OK;
+  ctx->sed_cap = 0;
   HIPCHK(dev_alloc((void **)&ctx->d_sed, (size_t)need * 8));
   ctx->sed_cap = need;
   HIPCHK(hipMemset(ctx->d_sed, 0, (size_t)need * 8));
@@ -452,12 +458,17 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
       for (int j = nl - 1; j >= 0; --j) ph += t[o.wk + s * nl + j] * h_planck(nu[j], T);
       t[o.logphi + s * NT_TAB + k] = std::log(ph);  // -inf where Phi underflows
     }
-  // per-interval upper bound of the mixture Rosseland mean on the ln T grid
+  // Upper bound of the mixture Rosseland mean on each interval [T_k, T_k+1]
+  // of the ln T grid. kappa_R = num/den with num = sum_j w_j dB_j/dT and
+  // den = sum_j w_j (dB_j/dT)/kext_j; at fixed nu, dB/dT grows with T
+  // (x^2 e^x/(e^x - 1)^2 falls with x = h nu/kT), so on the interval
+  // num(T) <= num(T_k+1) and den(T) >= den(T_k), hence
+  // kappa_R(T) <= num(T_k+1)/den(T_k). The factor 1 + 1e-9 covers the
+  // rounding of the sums here and in the device's exact mean.
   {
-    auto kross = [&](double T) {
-      double num = 0.0, den = 0.0;
+    auto sums = [&](double T, double &num, double &den) {
+      num = den = 0.0;
       for (int j = nl - 1; j >= 0; --j) {
-        if (!(kext[j] > 0.0)) return 0.0;
         double x = H_PL * nu[j] / (K_BO * T);
         if (x > 700.0) continue;
         double em = std::expm1(x);
@@ -466,20 +477,23 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
         num += db;
         den += db / kext[j];
       }
-      return den > 0.0 ? num / den : 0.0;
     };
+    bool pos = true;
+    for (int j = 0; j < nl; ++j) pos = pos && kext[j] > 0.0;
     double gmax = 0.0;
     for (int k = 0; k < NT_TAB - 1; ++k) {
-      double mx = 0.0;
-      for (int q = 0; q <= 8; ++q) {
-        double v = kross(std::exp(lt0 + (k + q / 8.0) * dlt));
-        if (v > mx) mx = v;
-      }
-      t[o.krmax + k] = 1.02 * mx;
-      if (mx > gmax) gmax = mx;
+      double nlo, dlo, nhi, dhi;
+      sums(std::exp(lt0 + k * dlt), nlo, dlo);
+      sums(std::exp(lt0 + (k + 1) * dlt), nhi, dhi);
+      // a zero extinction anywhere makes the exact mean 0 (no diffusion);
+      // an empty lower sum leaves only the hard bound kext_max
+      double b = !pos ? 0.0 : (dlo > 0.0 ? (1.0 + 1e-9) * nhi / dlo : ctx->kext_max);
+      if (b > ctx->kext_max) b = ctx->kext_max;
+      t[o.krmax + k] = b;
+      if (b > gmax) gmax = b;
     }
     t[o.krmax + NT_TAB - 1] = ctx->kext_max;  // outside the grid: the hard bound
-    ctx->kr_gmax = 1.02 * gmax;
+    ctx->kr_gmax = gmax;
   }
   {
     int s0 = 0;
@@ -591,10 +605,12 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
   mcrt_ctx *c = ctx;
   size_t tb = (size_t)o.dtotal * 8, rb = (size_t)o.r_total * rsize(c);
   if (tb > ctx->tab_cap) {
+    ctx->tab_cap = 0;
     HIPCHK(dev_alloc((void **)&ctx->d_tab, tb));
     ctx->tab_cap = tb;
   }
   if (rb > ctx->rtab_cap) {
+    ctx->rtab_cap = 0;
     HIPCHK(dev_alloc(&ctx->d_rtab, rb));
     ctx->rtab_cap = rb;
   }
@@ -1271,6 +1287,7 @@ static mcrt_status prepare_run(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n
 static mcrt_status ensure_records(mcrt_ctx *ctx, uint64_t n) {
   size_t need = (size_t)n * sizeof(mcrt_packet_record);
   if (ctx->rec_cap < need) {
+    ctx->rec_cap = 0;
     HIPCHK(dev_alloc(&ctx->d_rec, need));
     ctx->rec_cap = need;
   }
@@ -1370,6 +1387,7 @@ extern "C" mcrt_status mcrt_run_pah(mcrt_ctx *ctx, uint64_t seed, const mcrt_run
   size_t tb = 0;
   HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, (uint64_t *)ctx->d_tmp, ctx->d_prefix, (int)nc, st));
   if (tb > ctx->temp_cap) {
+    ctx->temp_cap = 0;
     HIPCHK(dev_alloc(&ctx->d_temp, tb));
     ctx->temp_cap = tb;
   }
@@ -1650,6 +1668,7 @@ extern "C" mcrt_status mcrt_sed(mcrt_ctx *ctx, double *sed_out, uint64_t *counts
   int n = ctx->ntheta * ctx->nl;
   if (sed_out) {
     if (ctx->sed_tmp_cap < (size_t)n * 8) {
+      ctx->sed_tmp_cap = 0;
       HIPCHK(dev_alloc((void **)&ctx->d_sed_tmp, (size_t)n * 8));
       ctx->sed_tmp_cap = (size_t)n * 8;
     }
@@ -1715,6 +1734,7 @@ static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_r
   if (!ctx->S_ok) {
     size_t need = (size_t)ctx->nview * ctx->ncell * nq * rsize(ctx);
     if (need > ctx->S_cap) {
+      ctx->S_cap = 0;
       HIPCHK(dev_alloc(&ctx->d_S, need));
       ctx->S_cap = need;
     }
@@ -1772,6 +1792,7 @@ extern "C" mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, cons
   void *img = img_out;
   if (!img_out || mem != MCRT_DEVICE) {
     if (ib > ctx->img_cap) {
+      ctx->img_cap = 0;
       HIPCHK(dev_alloc(&ctx->d_img_tmp, ib));
       ctx->img_cap = ib;
     }
@@ -1781,6 +1802,7 @@ extern "C" mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, cons
   size_t sb = (size_t)ctx->nview * ctx->nimg * 8;
   if (sed_out) {
     if (ctx->sed_tmp_cap < sb) {
+      ctx->sed_tmp_cap = 0;
       HIPCHK(dev_alloc((void **)&ctx->d_sed_tmp, sb));
       ctx->sed_tmp_cap = sb;
     }
@@ -1949,6 +1971,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   if (lds > ctx->lds_max || lds_w > ctx->lds_max)
     return fail(ctx, MCRT_EINVAL, "batch tables need %zu bytes of LDS (limit %zu)", lds > lds_w ? lds : lds_w, ctx->lds_max);
   if (n_models > ctx->batch_cap) {
+    ctx->batch_cap = 0;
     HIPCHK(dev_alloc((void **)&ctx->d_batch, sizeof(ModelDev) * n_models));
     ctx->batch_cap = n_models;
   }

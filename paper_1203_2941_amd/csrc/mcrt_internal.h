@@ -498,20 +498,6 @@ static __device__ __noinline__ double mrw_solve(double u) {
   return y;
 }
 
-// Henyey-Greenstein inverse CDF of cos(beta) and phase function (Eq. 15).
-template <typename R> __device__ __forceinline__ R hg_mu(R g, R u) {
-  if (m_fabs(g) < (R)1e-6) return (R)2 * u - (R)1;
-  R q = ((R)1 - g * g) / ((R)1 - g + (R)2 * g * u);
-  R mu = ((R)1 + g * g - q * q) / ((R)2 * g);
-  if (mu > (R)1) mu = (R)1;
-  if (mu < (R)-1) mu = (R)-1;
-  return mu;
-}
-template <typename R> __device__ __forceinline__ R hg_phase(R g, R mu) {
-  R den = (R)1 + g * g - (R)2 * g * mu;
-  return ((R)1 - g * g) / ((R)4 * (R)PI_D * den * m_sqrt(den));
-}
-
 // Device fill (kept as a kernel so that graph captures record no memsets).
 template <typename T> __global__ void k_fill(T *p, T v, uint64_t n) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

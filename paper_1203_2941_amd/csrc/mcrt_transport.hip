@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "mcrt_internal.h"
+#include "mcrt_scatter.h"
 
 namespace mcrt {
 
@@ -78,28 +79,6 @@ __device__ __forceinline__ void iso_dir(double uphi, double umu, R d[3]) {
   d[0] = (R)(s * cos(phi));
   d[1] = (R)(s * sin(phi));
   d[2] = (R)mu;
-}
-
-template <typename R>
-__device__ __forceinline__ void rotate_dir(R d[3], R mu, R phi) {
-  R t = (R)1 - mu * mu;
-  R st = m_sqrt(t > (R)0 ? t : (R)0);
-  R cp = m_cos(phi), sp = m_sin(phi);
-  R nx, ny, nz;
-  if (m_fabs(d[2]) > (R)1 - (R)1e-10) {
-    nx = st * cp;
-    ny = st * sp;
-    nz = (d[2] > (R)0) ? mu : -mu;
-  } else {
-    R s = m_sqrt((R)1 - d[2] * d[2]);
-    nx = st * (d[0] * d[2] * cp - d[1] * sp) / s + d[0] * mu;
-    ny = st * (d[1] * d[2] * cp + d[0] * sp) / s + d[1] * mu;
-    nz = -st * cp * s + d[2] * mu;
-  }
-  R nn = m_sqrt(nx * nx + ny * ny + nz * nz);
-  d[0] = nx / nn;
-  d[1] = ny / nn;
-  d[2] = nz / nn;
 }
 
 // Smallest index whose ascending running sum of f[q*stride] reaches u times
@@ -244,7 +223,12 @@ __device__ __forceinline__ void lucy_deposit(Ctx<R> &X, Pkt<R> &P, int64_t c, R 
   for (int s = 0; s < M.ns; ++s) {
     R f = X.rt[X.o.r_lucy + s * nl + j];
     if (f == (R)0) continue;
-    gatomic_add(&M.epath[(int64_t)s * X.nc + c], (double)((R)M.xi * f * em));
+    // FP32: the absorbed fraction in the walk precision, the packet energy
+    // (up to ~1e40 erg/s, beyond FLT_MAX) applied in FP64
+    double dep;
+    if constexpr (sizeof(R) == 8) dep = M.xi * f * em;
+    else dep = (double)(f * em) * M.xi;
+    gatomic_add(&M.epath[(int64_t)s * X.nc + c], dep);
   }
   if (M.mode == M_BW_EPOCH) M.dirty[c] = 1;
   P.n_lucy++;
@@ -541,8 +525,8 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
   }
   double T0 = mode_T(X, s0, c, rho);
   if (!REC) {
-    // rigorous upper bound of kappa_R(T) on its table interval: skip the
-    // exact mean when even the bound cannot reach the threshold
+    // upper bound of kappa_R(T) on its table interval (build_tables proves
+    // it): skip the exact mean when even the bound cannot reach the threshold
     const double lt0 = log(T_TAB_MIN), dlt = (log(T_MAX) - lt0) / (NT_TAB - 1);
     double xk = (log(T0) - lt0) / dlt;
     int k = (xk >= 0.0 && xk < (double)(NT_TAB - 1)) ? (int)xk : NT_TAB - 1;

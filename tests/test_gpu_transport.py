@@ -68,7 +68,7 @@ def test_cube_fp64_per_packet(orc, mode):
     To = o.finalize() if mode == "bw_epoch" else o.T
     np.testing.assert_allclose(g.temperatures(), To, rtol=1e-4, atol=0)
     for key in ("escaped", "killed", "scatters", "absorptions", "crossings"):
-        assert st[key] == o.stats[key] or mode == "frozen", key
+        assert st[key] == o.stats[key], key
 
 
 def test_init_temperatures(orc):
@@ -195,7 +195,9 @@ def test_voxelize_torus_and_shell_match(orc):
 
 def test_fp32_first_flight_and_aggregates(orc):
     """FP32 walk: the first emission draws give the same direction and
-    wavelength; aggregates agree with the FP64 oracle within MC noise."""
+    wavelength as the FP64 oracle at the same seed. Aggregates are compared
+    with an oracle run at an independent seed, so the two noises are
+    independent and the chi^2 / z normalisations hold."""
     m = mi.cube(n=32, n_packets=200_000, tau_v=1.0)
     o = orc.Oracle(m)
     o.run(mode=orc.BW_EPOCH, epoch=4096, record=True)
@@ -208,35 +210,41 @@ def test_fp32_first_flight_and_aggregates(orc):
     assert free.mean() > 0.2
     np.testing.assert_allclose(rg["dir"][free], o.records["dir"][free], atol=2e-6)
     assert np.mean(rg["j"][free] == o.records["j"][free]) > 0.9999
-    # SED per theta bin and wavelength: chi^2 of two independent-noise counts
-    so, sg = o.sed.astype(float), g.sed()[1].astype(float)
+    # aggregates against an independent oracle sample
+    oi = orc.Oracle(m)
+    oi.run(mode=orc.BW_EPOCH, epoch=4096, seed=m.seed + 1000)
+    so, sg = oi.sed.astype(float), g.sed()[1].astype(float)
     ok = (so + sg) > 50
     chi = np.sum((so[ok] - sg[ok]) ** 2 / (so[ok] + sg[ok])) / ok.sum()
-    assert chi < 1.5
+    assert chi < 1.4, chi
     T = g.temperatures()[0]
-    To = o.finalize()[0]
-    k = o.k[0]
-    sel = k > 200
-    rel = np.abs(T[sel] / To[sel] - 1)
-    assert np.median(rel) < 0.01
+    To = oi.finalize()[0]
+    k, kg = oi.k[0].astype(float), g.tallies()[0][0].astype(float)
+    sel = (k > 200) & (kg > 200)
+    assert sel.sum() > 100
+    z = (T[sel] / To[sel] - 1) / (np.sqrt(1 / k[sel] + 1 / kg[sel]) / 5.5)
+    assert np.mean(np.abs(z) < 4) > 0.97
+    assert abs(np.median(z)) < 0.5
 
 
 def test_ticket_mode_statistics(orc):
-    """Immediate B&W (GPU order) against the oracle's serial B&W."""
+    """Immediate B&W (GPU order) against the oracle's serial B&W at an
+    independent seed."""
     m = mi.cube(n=8, n_packets=100_000, tau_v=3.0)
-    o = orc.Oracle(m).run(mode=orc.BW_EPOCH, epoch=1)
+    o = orc.Oracle(m).run(mode=orc.BW_EPOCH, epoch=1, seed=m.seed + 777)
     g = gpu_context(m)
     g.run_packets(0, m.n_packets, m.seed, mode="bw_ticket", n_total=m.n_packets)
     To = o.finalize()[0]
     T = g.temperatures()[0]
-    k = o.k[0]
-    sel = k > 100
+    k, kg = o.k[0].astype(float), g.tallies()[0][0].astype(float)
+    sel = (k > 100) & (kg > 100)
     assert sel.sum() > 50
-    z = (T[sel] / To[sel] - 1) / (np.sqrt(2.0 / k[sel]) / 5.5)
+    z = (T[sel] / To[sel] - 1) / (np.sqrt(1 / k[sel] + 1 / kg[sel]) / 5.5)
     assert np.mean(np.abs(z) < 4) > 0.97
+    assert abs(np.median(z)) < 0.5
     so, sg = o.sed.astype(float), g.sed()[1].astype(float)
     ok = (so + sg) > 50
-    assert np.sum((so[ok] - sg[ok]) ** 2 / (so[ok] + sg[ok])) / ok.sum() < 1.5
+    assert np.sum((so[ok] - sg[ok]) ** 2 / (so[ok] + sg[ok])) / ok.sum() < 1.4
 
 
 def test_fp32_walk_through_empty_bricks():
