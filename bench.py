@@ -6,16 +6,21 @@ clumps, 100 wavelengths, 1e8 packets, FP32 walk): packet transport with
 immediate Bjorkman & Wood re-emission, Lucy estimator, modified random walk
 in cells with Rosseland depth > 50, HG scattering events for 8 views, the
 PAH second stage, Eq. 4 temperatures (FP64), then the ray-tracer forward
-(512x512 pixels, 16 wavelengths, 8 views) and its adjoint. Inputs are
-resident on the GPU before the timed region.
+(source functions, 512x512 pixels, 16 wavelengths, 8 views) and its adjoint.
+Inputs are resident on the GPU before the timed region.
 
-Prints one JSON line (see the keys below); the CPU oracle is timed on a
-bounded sample of the same model as the reference baseline.
+Prints one JSON line. Besides throughput it reports the roofline of the walk
+kernel (algorithmic bytes: 4 B of density per cell crossing plus 16 B per
+Lucy deposit and thermal species), rooflines of the ray-tracer kernels, the
+FP64 path's rate and the FP32 path's difference from it per output, and the
+CPU oracle timed on a bounded sample of the same model.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -31,20 +36,119 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def walk_bytes(st, ns_thermal, rs=4):
-    """Bytes the walk kernel must move for one run, for walk values of rs
-    bytes (4: FP32, 8: FP64): rs per cell crossing (density gather); per
-    flight the queued packet is read (positions, direction, density, depth:
-    8 x rs; cell and wavelength: 4 x 4 B; id 8 B; RNG position and
-    interaction count 2 x 4 B: 64 B in FP32) and, when it ends in an
-    interaction, written back; rs per escape to free its entry; 16 per Lucy
-    deposit and thermal species (read-modify-write of the FP64 path
-    energy)."""
+def walk_alg_bytes(st, ns_thermal, rs=4):
+    """Bytes the method must move in the voxel walk: rs (4 FP32, 8 FP64) of
+    density per cell crossing, and a 16-byte read-modify-write of the FP64
+    path energy per Lucy deposit and thermal species."""
+    return rs * st["crossings"] + 16 * ns_thermal * st["lucy_deposits"]
+
+
+def walk_queue_bytes(st, rs=4):
+    """Packet-state traffic of the wavefront design around the walk (not part
+    of the method): per flight the queued packet is read (positions,
+    direction, density, depth: 8 x rs; cell and wavelength 16 B; id 8 B; RNG
+    position and interaction count 8 B) and written back when the flight
+    ends in an interaction; an escape frees its entry (rs)."""
     inter = st["scatters"] + st["absorptions"]
     flights = inter + st["escaped"]
     pk = 8 * rs + 32
-    return (rs * st["crossings"] + pk * flights + pk * inter + rs * st["escaped"]
-            + 16 * ns_thermal * st["lucy_deposits"])
+    return pk * flights + pk * inter + rs * st["escaped"]
+
+
+def cpu_worker(args):
+    """One oracle process on a packet range (used by the CPU baseline)."""
+    first, n, lib_path, rho_path, n_total = args.cpu_worker
+    from oracle import oracle
+    import mcrt_inputs as mi
+    oracle.use_library(lib_path)
+    m = mi.torus(n=args.grid, n_packets=int(n_total))
+    rho = np.load(rho_path, mmap_mode="r")
+    o = oracle.Oracle(m, rho=rho)
+    t0 = time.perf_counter()
+    o.run(first=int(first), n=int(n), mode=oracle.BW_EPOCH, epoch=1 << 40, mrw_tau=50.0,
+          n_total=int(n_total))
+    dt = time.perf_counter() - t0
+    print(json.dumps({"packets": int(n), "crossings": int(o.stats["crossings"]), "seconds": dt}))
+
+
+def cpu_baseline(args, N):
+    """The FP64 oracle on the same torus: one process on a single core for
+    each of two builds (-O2; -O3 -march=native for this host), then one
+    process per core of the share (at most 16) with the faster build on
+    disjoint packet ranges. With a single B&W epoch
+    every packet sees the same (initial) temperatures, so packets are
+    independent and the ranges add up to one run."""
+    from oracle import oracle
+    import mcrt_inputs as mi
+    tmp = tempfile.mkdtemp(prefix="mcrt_cpu_")
+    libs = {"gcc -O2": oracle.build(force=True, out=os.path.join(tmp, "liboracle_o2.so")),
+            "gcc -O3 -march=native": oracle.build(force=True, out=os.path.join(tmp, "liboracle_native.so"),
+                                                  native=True)}
+    m = mi.torus(n=args.grid, n_packets=N)
+    rho_path = os.path.join(tmp, "rho.npy")
+    np.save(rho_path, oracle.density(m))
+    try:
+        cores = min(16, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        cores = min(16, os.cpu_count() or 1)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+
+    def launch(first, n, lib):
+        cmd = [sys.executable, os.path.abspath(__file__), "--grid", str(args.grid),
+               "--cpu-worker", str(first), str(n), lib, rho_path, str(N)]
+        return subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True)
+
+    def collect(procs):
+        out = []
+        for p in procs:
+            so, _ = p.communicate()
+            if p.returncode != 0:
+                raise RuntimeError("cpu baseline worker failed")
+            out.append(json.loads(so.strip().splitlines()[-1]))
+        return out
+
+    n1 = args.cpu_sample
+    single = {}
+    for name, lib in libs.items():
+        log(f"cpu baseline: oracle ({name}) on {n1} packets, one core")
+        single[name] = collect([launch(0, n1, lib)])[0]
+    # the all-core run uses the faster of the two builds on this host
+    best = min(single, key=lambda k: single[k]["seconds"])
+    r1 = single[best]
+    per = args.cpu_sample_per_core
+    log(f"cpu baseline: {cores} processes x {per} packets ({best})")
+    t0 = time.perf_counter()
+    rs = collect([launch(n1 + i * per, per, libs[best]) for i in range(cores)])
+    wall_all = time.perf_counter() - t0
+    # the processes start together; the longest transport loop bounds the
+    # time all of them ran side by side (interpreter start-up left out)
+    wall = max(r["seconds"] for r in rs)
+    pk = sum(r["packets"] for r in rs)
+    cr = sum(r["crossings"] for r in rs)
+    return {
+        "value": pk / wall, "unit": "packets/s", "cores": cores, "kind": "oracle",
+        "sample": (f"{pk} source packets of the {args.grid}^3 torus in {cores} processes on "
+                   f"disjoint id ranges ({per} each; FP64 Bjorkman & Wood, one epoch, MRW armed; "
+                   f"no PAH stage, no ray-tracing), {cr} crossings; longest process loop "
+                   f"{wall:.1f} s ({wall_all:.1f} s with interpreter start-up)"),
+        "crossings_per_s": cr / wall,
+        "single_core_packets_per_s": r1["packets"] / r1["seconds"],
+        "single_core_crossings_per_s": r1["crossings"] / r1["seconds"],
+        "single_core_sample": f"{n1} packets, {r1['crossings']} crossings in {r1['seconds']:.1f} s",
+        "single_core_packets_per_s_by_build": {k: v["packets"] / v["seconds"]
+                                               for k, v in single.items()},
+        "build": f"{best} -ffp-contract=off -fno-fast-math (faster of -O2 and -O3 -march=native "
+                 f"on this host)",
+        "cpu_model": model, "nproc": os.cpu_count(),
+    }
 
 
 def main():
@@ -55,8 +159,13 @@ def main():
     ap.add_argument("--packets", type=int, default=100_000_000)
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--npix", type=int, default=512)
-    ap.add_argument("--cpu-sample", type=int, default=600_000)
+    ap.add_argument("--cpu-sample", type=int, default=150_000,
+                    help="packets of the single-core oracle run")
+    ap.add_argument("--cpu-sample-per-core", type=int, default=150_000,
+                    help="packets per process of the all-core oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy-packets", type=int, default=10_000_000,
+                    help="packets of the FP32-against-FP64 comparison (0: skip it)")
     ap.add_argument("--queue-depth", type=int, default=0,
                     help="packets per wavefront queue (0: the library default)")
     ap.add_argument("--walk-blocks-per-cu", type=int, default=0,
@@ -67,7 +176,11 @@ def main():
                     help="walk precision of the context (the benchmark line is fp32)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one elementwise copy of this many MiB first (counter calibration)")
+    ap.add_argument("--cpu-worker", nargs=5, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the method is not sharded here); use --gpus 1",
               file=sys.stderr)
@@ -105,6 +218,7 @@ def main():
     opts = dict(mode="bw_ticket", n_total=N, mrw_tau=50.0, mrw_gamma=2.0, lucy_tau=1e-2,
                 max_interactions=10_000_000, sed_theta_bins=10, queue_depth=args.queue_depth,
                 walk_blocks_per_cu=args.walk_blocks_per_cu, blocks_per_cu=args.blocks_per_cu)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
     def step(seed):
         ctx.reset()
@@ -113,12 +227,24 @@ def main():
         sp = ctx.run_pah(seed, **opts)
         ph2 = ctx.phase_timings()
         ctx.finalize_temperatures()
+        # the library launches on torch's current stream: these events
+        # bracket the forward call (source functions, pixel rays, SED, point
+        # sources) and the adjoint call
+        ev[0].record()
         ctx.raytrace_device(npx, npy, img=img, sed=sed)
+        ev[1].record()
         t = ctx.timings()
         ctx.raytrace_adjoint_device(npx, npy, w_img=w_img, out=grad)
+        ev[2].record()
         t2 = ctx.timings()
         phases = {k: ph[k] + ph2[k] for k in ("emit_ms", "walk_ms", "interact_ms", "rounds")}
-        return st, sp, t["rt_fwd_ms"], t2["rt_adj_ms"], phases
+        rt = {"fwd_kernel_ms": t["rt_fwd_ms"], "adj_kernel_ms": t2["rt_adj_ms"],
+              "build_S_ms": t["build_S_ms"]}
+        return st, sp, rt, phases
+
+    def rt_calls_ms():
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
 
     for w in range(args.warmup):
         t0 = time.perf_counter()
@@ -129,40 +255,66 @@ def main():
     for k in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, sp, fwd_ms, adj_ms, phases = step(k)
+        st, sp, rt, phases = step(k)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        rt["fwd_call_ms"], rt["adj_call_ms"] = rt_calls_ms()
         times.append(dt)
-        rec.append((st, sp, fwd_ms, adj_ms, phases))
+        rec.append((st, sp, rt, phases))
         log(f"step {k}: {dt:.3f} s, transport {st['kernel_ms']:.1f} ms, pah {sp['kernel_ms']:.1f} ms,"
-            f" rt fwd {fwd_ms:.2f} ms, adj {adj_ms:.2f} ms, crossings {st['crossings']}")
+            f" rt S {rt['build_S_ms']:.2f} ms fwd {rt['fwd_call_ms']:.2f} ms"
+            f" (kernel {rt['fwd_kernel_ms']:.2f}), adj {rt['adj_call_ms']:.2f} ms"
+            f" (kernel {rt['adj_kernel_ms']:.2f}), crossings {st['crossings']}")
     ms = 1000.0 * float(np.mean(times))
     st0 = rec[-1][0]
     cross = np.mean([r[0]["crossings"] + r[1]["crossings"] for r in rec])
     t_tr = np.mean([r[0]["kernel_ms"] for r in rec]) / 1e3
     t_pah = np.mean([r[1]["kernel_ms"] for r in rec]) / 1e3
-    fwd = np.mean([r[2] for r in rec]) / 1e3
-    adj = np.mean([r[3] for r in rec]) / 1e3
+
+    def rtm(key):
+        return float(np.mean([r[2][key] for r in rec])) / 1e3
+
+    fwd_call, adj_call = rtm("fwd_call_ms"), rtm("adj_call_ms")
+    t_S, t_fk, t_ak = rtm("build_S_ms"), rtm("fwd_kernel_ms"), rtm("adj_kernel_ms")
     rays = len(views) * npx * npy
     ns_th = m.ns - (1 if m.pah_species >= 0 else 0)
-    # roofline of the walk kernel (the largest share of the step): its
-    # algorithmic bytes over its device time, both summed over the source
-    # and PAH runs of a step; launches = rounds
+    # roofline of the walk kernel (the largest share of the step): the
+    # method's bytes over its device time, both summed over the source and
+    # PAH runs of a step (the finishing kernel's flights included in both)
     rs = 8 if fp64 else 4
-    b_alg = np.mean([walk_bytes(r[0], ns_th, rs) + walk_bytes(r[1], ns_th, rs) for r in rec])
-    t_walk = np.mean([r[4]["walk_ms"] for r in rec]) / 1e3
-    t_emit = np.mean([r[4]["emit_ms"] for r in rec]) / 1e3
-    t_int = np.mean([r[4]["interact_ms"] for r in rec]) / 1e3
-    n_walk = float(np.mean([r[4]["rounds"] for r in rec]))
+    b_alg = np.mean([walk_alg_bytes(r[0], ns_th, rs) + walk_alg_bytes(r[1], ns_th, rs) for r in rec])
+    b_q = np.mean([walk_queue_bytes(r[0], rs) + walk_queue_bytes(r[1], rs) for r in rec])
+    t_walk = np.mean([r[3]["walk_ms"] for r in rec]) / 1e3
+    t_emit = np.mean([r[3]["emit_ms"] for r in rec]) / 1e3
+    t_int = np.mean([r[3]["interact_ms"] for r in rec]) / 1e3
+    n_walk = float(np.mean([r[3]["rounds"] for r in rec]))
     # bytes per launch measured by the committed counter runs, reported only
     # for the workload they were taken on and while the kernel is unchanged
     traffic = traffic_step = None
-    if (N == 100_000_000 and args.grid == 256 and not fp64 and not args.queue_depth
-            and not args.walk_blocks_per_cu and not args.blocks_per_cu):
-        from paper_1203_2941_amd import profiling
+    default_shape = (N == 100_000_000 and args.grid == 256 and not args.queue_depth
+                     and not args.walk_blocks_per_cu and not args.blocks_per_cu)
+    from paper_1203_2941_amd import profiling
+    if default_shape and not fp64:
         tr = profiling.read_traffic()
         if tr is not None:
             traffic, traffic_step = tr["per_launch"], tr["per_step"]
+    # ray-tracer: compulsory bytes per call (each array once)
+    nc, nv, nq = ctx.ncells, len(views), len(idx)
+    img_b = nv * nq * npx * npy * rs
+    b_fwd = nv * nc * (rs + nq * rs) + img_b          # density and S per view, image out
+    b_adj = nv * nc * (rs + nq * rs) + img_b + nc * rs  # the same, weights in, gradient out
+    b_S = nc * (8 * ns_th + rs) + 2 * nv * nc * nq * rs  # T, density, sums in; S out
+    rt_traffic = profiling.read_rt_traffic() if (default_shape and not fp64) else None
+
+    def roof(kernel, b, t, key):
+        d = {"kernel": kernel, "bound": "hbm", "achieved": b / t / 1e9, "peak": HBM_PEAK / 1e9,
+             "unit": "GB/s", "frac": b / t / HBM_PEAK, "bytes_per_launch": b, "launch_ms": t * 1e3,
+             "traffic": None}
+        if rt_traffic and key in rt_traffic:
+            d["traffic"] = rt_traffic[key]
+        return d
+
+    tn = "double" if fp64 else "float"
     out = {
         "metric": METRIC,
         "value": N / (ms / 1e3),
@@ -187,10 +339,13 @@ def main():
         "cell_crossings_per_s": cross / (ms / 1e3),
         "transport_packets_per_s": N / t_tr,
         "transport_crossings_per_s": st0["crossings"] / t_tr,
-        "raytrace_px_per_s_fwd_bwd": rays / (fwd + adj),
-        "raytrace_px_per_s_fwd": rays / fwd,
-        "raytrace_fwd_ms": fwd * 1e3,
-        "raytrace_adj_ms": adj * 1e3,
+        "raytrace_px_per_s_fwd_bwd": rays / (fwd_call + adj_call),
+        "raytrace_px_per_s_fwd": rays / fwd_call,
+        "raytrace_fwd_ms": fwd_call * 1e3,
+        "raytrace_adj_ms": adj_call * 1e3,
+        "raytrace_build_S_ms": t_S * 1e3,
+        "raytrace_fwd_kernel_ms": t_fk * 1e3,
+        "raytrace_adj_kernel_ms": t_ak * 1e3,
         "transport_ms": t_tr * 1e3,
         "pah_pass_ms": t_pah * 1e3,
         "events_per_step": {k: int(v) for k, v in st0.items() if k != "kernel_ms"},
@@ -198,7 +353,7 @@ def main():
                      "rounds": n_walk},
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_wf_walk<{'double' if fp64 else 'float'}, false, true>",
+            "kernel": f"k_wf_walk<{tn}, false, true>",
             "achieved": b_alg / t_walk / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
@@ -211,24 +366,102 @@ def main():
             "avg_launch_ms": t_walk * 1e3 / n_walk,
             "algorithmic_bytes_per_step": b_alg,
             "algorithmic_bytes_per_launch": b_alg / n_walk,
+            "algorithmic_bytes_rule": f"{rs} B per cell crossing + 16 B per Lucy deposit and "
+                                      f"thermal species",
+            "design_overhead_bytes_per_launch": b_q / n_walk,
+            "design_overhead_rule": "queued packet state read per flight and written back per "
+                                    "interaction (wavefront queues; not the method's bytes)",
+        },
+        "roofline_raytrace": {
+            "build_S": roof(f"k_build_S<{tn}>", b_S, t_S, "k_build_S"),
+            "forward": roof(f"k_rt_fwd<{tn}>", b_fwd, t_fk, "k_rt_fwd"),
+            "adjoint": roof(f"k_rt_adj<{tn}>", b_adj, t_ak, "k_rt_adj"),
+            "bytes_rule": "compulsory: each array once per launch (density and source "
+                          "functions per view, images, weights, gradient; for S: temperatures, "
+                          "density, scattering sums in and S out)",
         },
     }
+    if args.accuracy_packets and not fp64:
+        out["fp64_path"], out["fp32_vs_fp64"] = accuracy(args, m, views, idx, D, ctx, opts)
     if not args.no_cpu_baseline:
-        from oracle import oracle
-        oracle.build(force=False)
-        n = args.cpu_sample
-        log(f"cpu baseline: oracle on {n} packets of the same torus (FP64, one core)")
-        o = oracle.Oracle(m)
-        t0 = time.perf_counter()
-        o.run(n=n, mode=oracle.BW_EPOCH, epoch=1 << 30, mrw_tau=50.0, n_total=N)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {
-            "value": n / dt, "unit": "packets/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} source packets of the 256^3 torus (no PAH stage, no ray-tracing), "
-                      f"FP64 Bjorkman & Wood with one epoch, {o.stats['crossings']} crossings in {dt:.1f} s",
-            "crossings_per_s": o.stats["crossings"] / dt,
-        }
+        out["cpu_baseline"] = cpu_baseline(args, N)
     print(json.dumps(out), flush=True)
+
+
+def accuracy(args, m, views, idx, D, ctx32, opts):
+    """FP64 path's rate on the same torus, and the FP32 path's outputs against
+    it at args.accuracy_packets packets. Trajectories diverge chaotically
+    between precisions after a few events, so each difference is stated
+    beside the same quantity between two FP64 runs with different seeds (the
+    Monte Carlo noise at this packet count)."""
+    import ctypes as C
+
+    import torch
+
+    import paper_1203_2941_amd as mc
+    from paper_1203_2941_amd import _lib as L
+    n = args.accuracy_packets
+    npx = npy = args.npix
+    o = dict(opts, n_total=n)
+    log(f"accuracy: FP64 context, {n} packets")
+    c64 = mc.Context(0, "fp64").from_inputs(m, views=views, img_idx=idx, distance=D)
+
+    def run(c, seed):
+        c.reset()
+        st = c.run_packets(0, n, seed, **o)
+        sp = c.run_pah(seed, **o)
+        T, E = c.temperatures(with_energy=True)
+        f, cnt = c.sed()
+        im, sd = c.raytrace_device(npx, npy)
+        full = torch.empty((len(views), len(idx), c.ncells), dtype=torch.float64, device="cuda")
+        c._chk(c.lib.mcrt_scattering(c.h, C.c_void_p(full.data_ptr()), L.DEVICE, None))
+        ss = full.sum(dim=2)
+        del full
+        torch.cuda.synchronize()
+        return {"st": st, "sp": sp, "T": T, "E": E, "sed": cnt.astype(np.float64),
+                "img": im.double().cpu().numpy(), "ssca": ss.cpu().numpy()}
+
+    r64 = run(c64, 11)
+    t64 = r64["st"]["kernel_ms"] / 1e3
+    r64b = run(c64, 12)
+    r32 = run(ctx32, 11)
+    t32 = r32["st"]["kernel_ms"] / 1e3
+    del c64
+    torch.cuda.empty_cache()
+
+    def diffs(a, b):
+        k = (a["E"][:2] > 0) & (b["E"][:2] > 0)
+        w = a["E"][:2][k]
+        dT = np.abs(a["T"][:2][k] / b["T"][:2][k] - 1.0)
+        sed_a, sed_b = a["sed"], b["sed"]
+        ok = (sed_a + sed_b) > 50
+        chi = float(np.sum((sed_a[ok] - sed_b[ok]) ** 2 / (sed_a[ok] + sed_b[ok])) / ok.sum())
+        ia, ib = a["img"], b["img"]
+        rel_img = [float(np.linalg.norm(ia[v, q] - ib[v, q]) / max(np.linalg.norm(ib[v, q]), 1e-300))
+                   for v in range(ia.shape[0]) for q in range(ia.shape[1])]
+        sa, sb = a["ssca"], b["ssca"]
+        ok2 = sb > 0
+        return {
+            "T_rel_energy_weighted": float(np.sum(w * dT) / np.sum(w)),
+            "T_rel_median": float(np.median(dT)),
+            "E_total_rel": [float(a["E"][s].sum() / b["E"][s].sum() - 1.0) for s in range(2)],
+            "sed_counts_chi2_per_bin": chi,
+            "sed_total_rel": float(sed_a.sum() / sed_b.sum() - 1.0),
+            "scattering_totals_rel_rms": float(np.sqrt(np.mean((sa[ok2] / sb[ok2] - 1.0) ** 2))),
+            "image_rel_l2_median": float(np.median(rel_img)),
+            "image_rel_l2_max": float(np.max(rel_img)),
+            "crossings_per_packet_rel": float(a["st"]["crossings"] / b["st"]["crossings"] - 1.0),
+        }
+
+    fp64_path = {"packets": n, "transport_ms": t64 * 1e3, "transport_packets_per_s": n / t64,
+                 "fp32_transport_ms_same_packets": t32 * 1e3,
+                 "fp32_speedup_transport": t64 / t32}
+    err = {"packets": n, "seed": 11,
+           "fp32_vs_fp64_same_seed": diffs(r32, r64),
+           "fp64_vs_fp64_other_seed": diffs(r64b, r64),
+           "note": "per output: FP32 path against the FP64 path on the benchmark torus; the "
+                   "second block is the Monte Carlo noise at this packet count"}
+    return fp64_path, err
 
 
 if __name__ == "__main__":

@@ -129,9 +129,13 @@ mcrt_status mcrt_set_dust(mcrt_ctx *ctx, int n_lambda, const double *lambda_um, 
                           const double *mass_frac, const double *kabs, const double *ksca,
                           const double *g, int pah_species, int n_pah_rows,
                           const double *pah_emis, const double *pah_row_edges);
-/* Point sources (host): positions [n][3] cm inside the grid, luminosities
- * erg/s, spectral shape ~L_nu [n][nl] or NULL with blackbody temperatures
- * t_bb [n]. 1 <= n <= 8. */
+/* Point sources of sect. 2 (host arrays): positions [n][3] cm inside the
+ * grid, luminosities erg/s, spectral shape ~L_nu [n][nl] or NULL with
+ * blackbody temperatures t_bb [n]; 1 <= n <= 8. Each packet of Eq. 1 leaves
+ * a source chosen in proportion to its luminosity, with a frequency bin
+ * drawn from that source's w_j L_nu,j. Shapes are normalised to sum_j w_j
+ * L_nu,j = L. ESTATE before set_dust and the grid; EINVAL for a source
+ * outside the grid, a negative luminosity or an empty spectrum. */
 mcrt_status mcrt_set_sources(mcrt_ctx *ctx, int n_src, const double *pos_cm, const double *lum,
                              const double *lnu_shape, const double *t_bb);
 /* Observer views for scattering events and the ray-tracer (sect. 4):
@@ -150,13 +154,20 @@ mcrt_status mcrt_set_temperatures(mcrt_ctx *ctx, const double *T, int mem, void 
 /* Replace the HG-weighted scattering sums [views][n_img][cells] (FP64, erg/s/sr). */
 mcrt_status mcrt_set_scattering(mcrt_ctx *ctx, const double *ssca, int mem, void *stream);
 
-/* Transport packets first .. first+n-1 with the counter-based stream of
- * `seed` (Philox4x32-10 keyed by seed, counter = draw block, packet id,
- * iteration, model and stream tag). Tallies accumulate across calls, so a
- * run split into consecutive ranges equals the whole run (FROZEN resets per
- * pass). `stats` (nullable) receives counters after the call completes
- * (the call then synchronises the stream). ESTATE before grid, dust and
- * sources are set; EINVAL for bad options. */
+/* Transport of sect. 2-3 for packets first .. first+n-1: emission (Eq. 1),
+ * optical depth per cell against -ln(zeta) (Eqs. 2-3), albedo split, HG
+ * scattering (Eq. 15) with the scattering sums of the views (Eq. 16 source
+ * term), absorption with re-emission by Eq. 5 or Eq. 10 (mode), Lucy's
+ * estimator in thin cells (sect. 3.1, Eq. 9), the diffusion step of
+ * sect. 3.2 in very thick cells, photon counting of escapes (sect. 4).
+ * Random numbers: the counter-based stream of `seed` (Philox4x32-10 keyed
+ * by seed, counter = draw block, packet id, iteration, model and stream
+ * tag). Tallies accumulate across calls, so a run split into consecutive
+ * ranges equals the whole run (FROZEN resets per pass). `stats` (nullable)
+ * receives counters after the call completes (the call then synchronises
+ * the stream). ESTATE before grid, dust and sources are set; EINVAL for bad
+ * options or packet ids beyond 2^48; ENOMEM when queues or records do not
+ * fit on the device (the context stays usable). */
 mcrt_status mcrt_run_packets(mcrt_ctx *ctx, uint64_t first, uint64_t n, uint64_t seed,
                              const mcrt_run_opts *opts, mcrt_run_stats *stats, void *stream);
 /* Second PAH stage (sect. 2.1): every cell re-emits its pass-1 PAH
@@ -192,7 +203,10 @@ mcrt_status mcrt_sed(mcrt_ctx *ctx, double *sed_out, uint64_t *counts_out, int m
 /* HG-weighted scattering sums [views][n_img][cells] FP64. */
 mcrt_status mcrt_scattering(mcrt_ctx *ctx, double *ssca_out, int mem, void *stream);
 /* Copy min(n, recorded) packet records of the last run_packets/run_pah
- * call with record = 1 (host or device destination). */
+ * call with record = 1 (host or device destination): each packet's end
+ * state (escape point and direction for the photon counting of sect. 4,
+ * wavelength bin, packet energy xi of Eq. 1) and its event counts. ESTATE
+ * when the last run kept no records. */
 mcrt_status mcrt_packet_records(mcrt_ctx *ctx, mcrt_packet_record *out, uint64_t n, int mem);
 
 /* Ray-tracer (sect. 4, Eqs. 11-17): npx*npy parallel rays per view over a
@@ -228,10 +242,17 @@ mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models, const uint64_t
                            const uint64_t *seeds, const mcrt_run_opts *opts,
                            mcrt_run_stats *stats, void *stream);
 
-/* Device time in ms of the last ray-tracer forward / adjoint kernel and of
- * the last transport launch sequence (HIP events on the call's stream). */
+/* Device time in ms of the last ray-tracer forward / adjoint pixel-ray
+ * kernel (without the SED reduction and point-source terms) and of the last
+ * transport launch sequence (HIP events on the call's stream). */
 mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_ms, double *rt_fwd_ms,
                               double *rt_adj_ms);
+/* Device time in ms of the last build of the ray-tracer's source functions
+ * S (sect. 4, Eq. 14 emission plus the Eq. 16 scattering term, per view,
+ * cell and imaged wavelength), which mcrt_raytrace_image runs whenever the
+ * temperatures or scattering sums changed since the last build; 0 before
+ * any build. EINVAL for NULL arguments. */
+mcrt_status mcrt_last_source_build_ms(const mcrt_ctx *ctx, double *ms);
 
 /* n draws of the wavelength bin that species `species` (thermal) re-emits
  * at temperature T (K) after an absorption, taken exactly as the transport

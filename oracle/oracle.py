@@ -22,13 +22,24 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no contraction)."""
-    if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-o", LIB_PATH, SRC, "-lm"]
+def build(force: bool = True, out: str = None, native: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, no value-changing
+    optimisation). native=True adds -O3 -march=native for timing on the
+    machine that runs it (same IEEE arithmetic, written to `out`)."""
+    path = out or LIB_PATH
+    if force or not os.path.exists(path):
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
+        cmd = ["gcc", *opt, "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-o", path, SRC, "-lm"]
         subprocess.check_call(cmd, cwd=HERE)
-    return LIB_PATH
+    return path
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (see build)."""
+    global LIB_PATH, _lib
+    LIB_PATH = path
+    _lib = None
 
 
 class Model(C.Structure):

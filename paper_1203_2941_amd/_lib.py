@@ -86,6 +86,7 @@ SIGNATURES = {
                                  C.POINTER(C.c_uint64), C.POINTER(RunOpts), C.POINTER(RunStats),
                                  _vp]),
     "mcrt_last_timings": (C.c_int, [_ctxp, _dp, _dp, _dp]),
+    "mcrt_last_source_build_ms": (C.c_int, [_ctxp, _dp]),
     "mcrt_phase_timings": (C.c_int, [_ctxp, _dp, _dp, _dp, C.POINTER(C.c_uint64)]),
     "mcrt_sample_reemission": (C.c_int, [_ctxp, C.c_int, C.c_int, C.c_double, C.c_uint64,
                                          C.c_uint64, C.POINTER(C.c_uint64)]),

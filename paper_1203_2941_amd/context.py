@@ -306,7 +306,10 @@ class Context:
     def timings(self):
         t = (C.c_double(), C.c_double(), C.c_double())
         self._chk(self.lib.mcrt_last_timings(self.h, C.byref(t[0]), C.byref(t[1]), C.byref(t[2])))
-        return {"transport_ms": t[0].value, "rt_fwd_ms": t[1].value, "rt_adj_ms": t[2].value}
+        b = C.c_double()
+        self._chk(self.lib.mcrt_last_source_build_ms(self.h, C.byref(b)))
+        return {"transport_ms": t[0].value, "rt_fwd_ms": t[1].value, "rt_adj_ms": t[2].value,
+                "build_S_ms": b.value}
 
     def sample_reemission(self, species, T, n, seed=0, mode="bw_ticket"):
         """Histogram [n_lambda] of n re-emission bins at temperature T (see

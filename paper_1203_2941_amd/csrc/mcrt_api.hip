@@ -51,9 +51,9 @@ hipError_t launch_vox_shell(bool fp64, int nx, int ny, int nz, const double o[3]
                             double rho0, double r_in, double r_out, int ng, const double *dgx,
                             const double *dgw, void *rho, hipStream_t st);
 hipError_t launch_rt_fwd(const RtArgs *dA, const RtArgs &hA, bool fp64, void *img, double *sed,
-                         hipStream_t st);
+                         hipEvent_t ev_main, hipStream_t st);
 hipError_t launch_rt_adj(const RtArgs *dA, const RtArgs &hA, bool fp64, const void *w_img,
-                         const double *w_sed, void *drho, hipStream_t st);
+                         const double *w_sed, void *drho, hipEvent_t ev_main, hipStream_t st);
 }  // namespace mcrt
 
 using namespace mcrt;
@@ -144,6 +144,8 @@ struct mcrt_ctx {
   void *h_stage = nullptr;
   hipEvent_t ev_stage = nullptr, ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evf0 = nullptr, evf1 = nullptr, eva0 = nullptr, eva1 = nullptr;
+  hipEvent_t evs0 = nullptr, evs1 = nullptr;  // around the last source-function build
+  bool have_s = false;
   hipStream_t cap_stream = nullptr;  // graph capture (the caller's stream may be the legacy one)
   bool have_f = false, have_a = false;
   double t_transport = 0.0;
@@ -235,7 +237,8 @@ extern "C" mcrt_status mcrt_create(mcrt_ctx **out, int device, int precision) {
       hipEventCreate(&ctx->ev_stage) != hipSuccess || hipEventCreate(&ctx->ev0) != hipSuccess ||
       hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->evf0) != hipSuccess ||
       hipEventCreate(&ctx->evf1) != hipSuccess || hipEventCreate(&ctx->eva0) != hipSuccess ||
-      hipEventCreate(&ctx->eva1) != hipSuccess ||
+      hipEventCreate(&ctx->eva1) != hipSuccess || hipEventCreate(&ctx->evs0) != hipSuccess ||
+      hipEventCreate(&ctx->evs1) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void **)&ctx->d_ctl, sizeof(WfCtl)) != hipSuccess ||
       hipHostMalloc((void **)&ctx->h_ctl, sizeof(WfCtl), hipHostMallocDefault) != hipSuccess ||
@@ -268,7 +271,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-  hipEvent_t evs[] = {ctx->evf0, ctx->evf1, ctx->eva0, ctx->eva1};
+  hipEvent_t evs[] = {ctx->evf0, ctx->evf1, ctx->eva0, ctx->eva1, ctx->evs0, ctx->evs1};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
   delete ctx;
@@ -1740,7 +1743,10 @@ static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_r
     }
     s = upload_model_only(ctx, st);
     if (s) return s;
+    HIPCHK(hipEventRecord(ctx->evs0, st));
     HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, ctx->d_S, st));
+    HIPCHK(hipEventRecord(ctx->evs1, st));
+    ctx->have_s = true;
     ctx->S_ok = true;
   }
   memset(&A, 0, sizeof A);
@@ -1809,8 +1815,7 @@ extern "C" mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, cons
     sed = (mem == MCRT_DEVICE) ? sed_out : ctx->d_sed_tmp;
   }
   HIPCHK(hipEventRecord(ctx->evf0, st));
-  HIPCHK(launch_rt_fwd(ctx->d_rt, A, ctx->fp64, img, sed, st));
-  HIPCHK(hipEventRecord(ctx->evf1, st));
+  HIPCHK(launch_rt_fwd(ctx->d_rt, A, ctx->fp64, img, sed, ctx->evf1, st));
   ctx->have_f = true;
   if (mem != MCRT_DEVICE) {
     if (img_out) HIPCHK(hipMemcpyAsync(img_out, img, ib, hipMemcpyDeviceToHost, st));
@@ -1853,8 +1858,7 @@ extern "C" mcrt_status mcrt_raytrace_adjoint(mcrt_ctx *ctx, int npx, int npy, co
   if (ctx->fp64) HIPCHK(fill<double>((double *)grad, 0.0, ctx->ncell, st));
   else HIPCHK(fill<float>((float *)grad, 0.0f, ctx->ncell, st));
   HIPCHK(hipEventRecord(ctx->eva0, st));
-  HIPCHK(launch_rt_adj(ctx->d_rt, A, ctx->fp64, wimg, wsed, grad, st));
-  HIPCHK(hipEventRecord(ctx->eva1, st));
+  HIPCHK(launch_rt_adj(ctx->d_rt, A, ctx->fp64, wimg, wsed, grad, ctx->eva1, st));
   ctx->have_a = true;
   if (mem != MCRT_DEVICE) {
     HIPCHK(hipMemcpyAsync(dL_drho, grad, gb, hipMemcpyDeviceToHost, st));
@@ -1879,6 +1883,12 @@ extern "C" mcrt_status mcrt_last_timings(const mcrt_ctx *ctx, double *transport_
   if (transport_ms) *transport_ms = ctx->t_transport;
   if (rt_fwd_ms) *rt_fwd_ms = ctx->have_f ? event_ms(ctx->evf0, ctx->evf1) : 0.0;
   if (rt_adj_ms) *rt_adj_ms = ctx->have_a ? event_ms(ctx->eva0, ctx->eva1) : 0.0;
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_last_source_build_ms(const mcrt_ctx *ctx, double *ms) {
+  if (!ctx || !ms) return MCRT_EINVAL;
+  *ms = ctx->have_s ? event_ms(ctx->evs0, ctx->evs1) : 0.0;
   return MCRT_OK;
 }
 

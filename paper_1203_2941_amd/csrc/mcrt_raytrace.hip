@@ -432,18 +432,22 @@ hipError_t launch_build_S(const ModelDev *d, bool fp64, void *S, hipStream_t st)
   return hipGetLastError();
 }
 
+// ev_main (nullable) is recorded right after the pixel-ray kernel, before
+// the SED reduction and the point-source terms.
 hipError_t launch_rt_fwd(const RtArgs *dA, const RtArgs &hA, bool fp64, void *img, double *sed,
-                         hipStream_t st) {
+                         hipEvent_t ev_main, hipStream_t st) {
   dim3 grid((hA.npx * hA.npy + 255) / 256, hA.nview);
   int nstar = hA.nview * hA.nsrc * hA.nimg;
   if (fp64) {
     hipLaunchKernelGGL(k_rt_fwd<double>, grid, dim3(256), 0, st, dA, (double *)img);
+    if (ev_main) (void)hipEventRecord(ev_main, st);
     if (sed) hipLaunchKernelGGL(k_rt_sed<double>, dim3(hA.nview * hA.nimg), dim3(256), 0, st, dA,
                                 (const double *)img, sed);
     if (nstar) hipLaunchKernelGGL(k_rt_star<double>, dim3((nstar + 63) / 64), dim3(64), 0, st, dA,
                                   (double *)img, sed);
   } else {
     hipLaunchKernelGGL(k_rt_fwd<float>, grid, dim3(256), 0, st, dA, (float *)img);
+    if (ev_main) (void)hipEventRecord(ev_main, st);
     if (sed) hipLaunchKernelGGL(k_rt_sed<float>, dim3(hA.nview * hA.nimg), dim3(256), 0, st, dA,
                                 (const float *)img, sed);
     if (nstar) hipLaunchKernelGGL(k_rt_star<float>, dim3((nstar + 63) / 64), dim3(64), 0, st, dA,
@@ -453,17 +457,19 @@ hipError_t launch_rt_fwd(const RtArgs *dA, const RtArgs &hA, bool fp64, void *im
 }
 
 hipError_t launch_rt_adj(const RtArgs *dA, const RtArgs &hA, bool fp64, const void *w_img,
-                         const double *w_sed, void *drho, hipStream_t st) {
+                         const double *w_sed, void *drho, hipEvent_t ev_main, hipStream_t st) {
   dim3 grid((hA.npx * hA.npy + 255) / 256, hA.nview);
   int nstar = hA.nview * hA.nsrc * hA.nimg;
   if (fp64) {
     hipLaunchKernelGGL(k_rt_adj<double>, grid, dim3(256), 0, st, dA, (const double *)w_img, w_sed,
                        (double *)drho);
+    if (ev_main) (void)hipEventRecord(ev_main, st);
     if (nstar) hipLaunchKernelGGL(k_rt_star_adj<double>, dim3((nstar + 63) / 64), dim3(64), 0, st,
                                   dA, (const double *)w_img, w_sed, (double *)drho);
   } else {
     hipLaunchKernelGGL(k_rt_adj<float>, grid, dim3(256), 0, st, dA, (const float *)w_img, w_sed,
                        (float *)drho);
+    if (ev_main) (void)hipEventRecord(ev_main, st);
     if (nstar) hipLaunchKernelGGL(k_rt_star_adj<float>, dim3((nstar + 63) / 64), dim3(64), 0, st,
                                   dA, (const float *)w_img, w_sed, (float *)drho);
   }

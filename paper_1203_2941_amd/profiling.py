@@ -17,6 +17,7 @@ Usage (from the repository root)::
 
     python -m paper_1203_2941_amd.profiling trace DB TITLE COMMAND > profiles/x.md
     python -m paper_1203_2941_amd.profiling traffic FETCH_DB WRITE_DB CALIB_MIB COMMAND > profiles/y.md
+    python -m paper_1203_2941_amd.profiling rt-traffic FETCH_DB WRITE_DB CALIB_MIB COMMAND > profiles/z.md
 """
 from __future__ import annotations
 
@@ -28,16 +29,21 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-TRANSPORT_SOURCES = ("csrc/mcrt_transport.hip", "csrc/mcrt_internal.h", "csrc/mcrt_api.hip")
+TRANSPORT_SOURCES = ("csrc/mcrt_transport.hip", "csrc/mcrt_internal.h", "csrc/mcrt_api.hip",
+                     "csrc/mcrt_scatter.h")
+RT_SOURCES = ("csrc/mcrt_raytrace.hip", "csrc/mcrt_rtargs.h", "csrc/mcrt_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_wf_walk_torus256_1e8_traffic.md")
+RT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raytrace_torus256_512px_traffic.md")
+RT_KERNELS = ("k_build_S", "k_rt_fwd", "k_rt_adj")
 TRANSPORT_KERNEL = "k_wf_walk<float, false, true>"
 CALIB_KERNEL = "MulFunctor"
 
 
-def source_digest() -> str:
-    """sha256 over the sources of the transport kernels and their round loop."""
+def source_digest(sources=TRANSPORT_SOURCES) -> str:
+    """sha256 over the sources of the transport kernels and their round loop
+    (or of another kernel group)."""
     h = hashlib.sha256()
-    for rel in TRANSPORT_SOURCES:
+    for rel in sources:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -134,11 +140,71 @@ def read_traffic(path: str = TRAFFIC_FILE):
     return {"per_launch": float(pl.group(1)), "per_step": float(ps.group(1))}
 
 
+def rt_traffic_md(fetch_db: str, write_db: str, calib_mib: int, cmd: str) -> str:
+    """Bytes per launch of the ray-tracer kernels (source functions, forward,
+    adjoint) from a FETCH_SIZE run and a WRITE_SIZE run, calibrated as in
+    traffic_md."""
+    cal_f = counter_values(fetch_db, "FETCH_SIZE", CALIB_KERNEL)
+    cal_w = counter_values(write_db, "WRITE_SIZE", CALIB_KERNEL)
+    if not (cal_f and cal_w):
+        raise SystemExit("calibration counters missing from the databases")
+    nbytes = calib_mib * (1 << 20)
+    sf, sw = nbytes / cal_f[0], nbytes / cal_w[0]
+    lines = [
+        "# HBM traffic of the ray-tracer kernels: 256^3 torus, 512^2 px, 16 wavelengths, 8 views, FP32",
+        "",
+        "FETCH_SIZE and WRITE_SIZE in separate runs of one bench step each; a",
+        f"{calib_mib} MiB elementwise copy in the same process calibrates each counter",
+        f"(one unit = {sf:.6g} B read / {sw:.6g} B written).",
+        "",
+        "Commands (from the repository root, one MI355X; R = repository root):",
+        "",
+        "```",
+        cmd,
+        "```",
+        "",
+        "| kernel | launches | read bytes per launch | written bytes per launch | total per launch |",
+        "|---|---:|---:|---:|---:|",
+    ]
+    vals = {}
+    for k in RT_KERNELS:
+        f = counter_values(fetch_db, "FETCH_SIZE", k + "<")
+        w = counter_values(write_db, "WRITE_SIZE", k + "<")
+        if not f or not w:
+            continue
+        rd, wr = sum(f) * sf / len(f), sum(w) * sw / len(w)
+        vals[k] = rd + wr
+        lines.append(f"| `{k}` | {len(f)} | {rd:.6g} | {wr:.6g} | {rd + wr:.6g} |")
+    lines.append("")
+    for k, v in vals.items():
+        lines.append(f"traffic_{k}: {v:.6g}")
+    lines.append(f"source_sha256: {source_digest(RT_SOURCES)}")
+    lines.append("")
+    return "\n".join(lines)
+
+
+def read_rt_traffic(path: str = RT_TRAFFIC_FILE):
+    """{kernel: measured bytes per launch} of the ray-tracer kernels, or None
+    when the summary is missing or was taken from other sources."""
+    try:
+        with open(path) as f:
+            text = f.read()
+    except OSError:
+        return None
+    d = re.search(r"^source_sha256: (\S+)$", text, re.M)
+    if not d or d.group(1) != source_digest(RT_SOURCES):
+        return None
+    return {m.group(1): float(m.group(2))
+            for m in re.finditer(r"^traffic_(\w+): (\S+)$", text, re.M)}
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "trace":
         sys.stdout.write(trace_md(argv[1], argv[2], argv[3]))
     elif len(argv) >= 5 and argv[0] == "traffic":
         sys.stdout.write(traffic_md(argv[1], argv[2], int(argv[3]), argv[4]))
+    elif len(argv) >= 5 and argv[0] == "rt-traffic":
+        sys.stdout.write(rt_traffic_md(argv[1], argv[2], int(argv[3]), argv[4]))
     else:
         sys.stderr.write(__doc__)
         return 2
