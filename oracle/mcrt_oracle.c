@@ -533,8 +533,14 @@ static void lucy_deposit(run_t *R, pkt_t *P, int64_t c, double rho, double ell) 
 }
 
 /* One flight with optical depth tau_star from the current position.
- * Returns 1 when the packet leaves the grid, 0 at an interaction. */
-static int fly(run_t *R, pkt_t *P, double tau_star) {
+ * Returns 1 when the packet leaves the grid, 0 at an interaction. With a
+ * new draw per cell (the footnote to the sect. 2 interaction test) the
+ * packet draws zeta on entering each cell (the flight's first cell at its
+ * start point) and interacts there iff the cell's segment depth exceeds
+ * -ln zeta, at distance -ln zeta / (rho kext) from where the segment
+ * begins; tau_star is then unused. */
+static int fly(run_t *R, pkt_t *P, double tau_star, rng_t *rg) {
+  const int per_cell = R->o->tau_mode == ORC_TAU_PER_CELL;
   const orc_model *m = R->m;
   int n[3] = {m->nx, m->ny, m->nz};
   double p0[3] = {P->p[0], P->p[1], P->p[2]};
@@ -560,6 +566,10 @@ static int fly(run_t *R, pkt_t *P, double tau_star) {
     double rho = m->rho[c];
     double dtau = rho * kx * ell;
     int thin = is_thin(R, rho);
+    if (per_cell) {
+      tau = 0.0;
+      tau_star = -log(rng_next(rg));
+    }
     upd_margin(&P->mm, fabs(tau + dtau - tau_star) / tau_star);
     if (tau + dtau > tau_star) {
       double tint = t + (tau_star - tau) / (rho * kx);
@@ -766,6 +776,11 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
   } else {
     double uph = rng_next(&rg), umu = rng_next(&rg);
     double us = rng_next(&rg), ul = rng_next(&rg);
+    /* m equal-energy source bins of Eq. 1, each emitting every m-th packet:
+     * packet pid draws inside stratum pid mod m of the source spectrum's
+     * cumulative distribution */
+    if (R->o->src_strata > 0)
+      ul = ((double)(pid % R->o->src_strata) + ul) / (double)R->o->src_strata;
     iso_dir(uph, umu, P.d);
     int s = pick_asc(m->src_lum, m->nsrc, us, &P.mm);
     for (int k = 0; k < 3; k++) P.p[k] = m->src_pos[3 * s + k];
@@ -786,8 +801,8 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
         return;
       }
     }
-    double tau_star = -log(rng_next(&rg));
-    if (fly(R, &P, tau_star)) {
+    double tau_star = (R->o->tau_mode == ORC_TAU_PER_CELL) ? 0.0 : -log(rng_next(&rg));
+    if (fly(R, &P, tau_star, &rg)) {
       P.status = ORC_ESCAPED;
       finish(R, &P, pid, slot);
       return;
@@ -1118,8 +1133,39 @@ static double source_fn(const tab_t *t, const orc_model *m, const double *T,
   return S;
 }
 
-int orc_raytrace(const orc_model *m, const double *T, const double *ssca, const double *rho_rt,
-                 int npx, int npy, double *img, double *sed) {
+/* Eqs. 13-14 as printed: absorption optical depth K^abs int rho ds (K^abs
+ * of the whole mixture), a cell emitting [1 - exp(-tau_cell)] times its
+ * source function, with tau_cell = rho K^abs dcell measured face to face,
+ * plus the scattered intensity of Eq. 16, sum P_HG xi / dnu spread over
+ * the cell's face dcell^2. The mixture's source function is
+ * sum_s f_s kabs_s B(T_s) / K^abs (B(T) for one species). Both terms come
+ * from the model density; rho_rt enters only the attenuation toward the
+ * observer. */
+static double kabs_all(const tab_t *t, const orc_model *m, int j) {
+  double k = 0.0;
+  for (int s = 0; s < t->ns; s++) k += m->mass_frac[s] * m->kabs[s * t->nl + j];
+  return k;
+}
+
+static double cell_literal(const tab_t *t, const orc_model *m, const double *T,
+                           const double *ssca, int v, int q, int64_t c) {
+  int j = m->img_idx[q], nl = t->nl;
+  double rho = m->rho[c];
+  if (!(rho > 0.0)) return 0.0;
+  double ka = kabs_all(t, m, j);
+  double em = 0.0;
+  for (int s = 0; s < t->ns; s++) {
+    if (s == m->pah_species) continue;
+    em += m->mass_frac[s] * m->kabs[s * nl + j] * orc_planck(t->nu[j], T[(int64_t)s * t->ncell + c]);
+  }
+  double I = (ka > 0.0) ? -expm1(-(rho * ka * m->dcell)) * (em / ka) : 0.0;
+  if (ssca) I += ssca[((int64_t)v * m->nimg + q) * t->ncell + c] / (t->w[j] * m->dcell * m->dcell);
+  return I;
+}
+
+int orc_raytrace(const orc_model *m, int rt_mode, const double *T, const double *ssca,
+                 const double *rho_rt, int npx, int npy, double *img, double *sed) {
+  const int lit = rt_mode == ORC_RT_ABS_LITERAL;
   if (!rho_rt) rho_rt = m->rho;
   tab_t t;
   tab_init(&t, m);
@@ -1142,6 +1188,11 @@ int orc_raytrace(const orc_model *m, const double *T, const double *ssca, const 
           double I = 0.0, tr = 1.0;
           for (int s = 0; s < nseg; s++) {
             double rho = rho_rt[cells[s]];
+            if (lit) {
+              I += tr * cell_literal(&t, m, T, ssca, v, q, cells[s]);
+              tr *= exp(-(rho * kabs_all(&t, m, j) * lens[s]));
+              continue;
+            }
             if (!(rho > 0.0)) continue;
             double dtau = rho * t.kext[j] * lens[s];
             double S = source_fn(&t, m, T, ssca, v, q, cells[s]);
@@ -1167,8 +1218,9 @@ int orc_raytrace(const orc_model *m, const double *T, const double *ssca, const 
       int ix = (int)floor((xp + 0.5 * vw.fov) / vw.dpx), iy = (int)floor((yp + 0.5 * vw.fov) / vw.dpy);
       for (int q = 0; q < m->nimg; q++) {
         int j = m->img_idx[q];
+        double kx = lit ? kabs_all(&t, m, j) : t.kext[j];
         double tau = 0.0;
-        for (int g = 0; g < nseg; g++) tau += rho_rt[cells[g]] * t.kext[j] * lens[g];
+        for (int g = 0; g < nseg; g++) tau += rho_rt[cells[g]] * kx * lens[g];
         double F = t.lnu[s * t.nl + j] / (4.0 * PI_D * D2) * exp(-tau);
         if (ix >= 0 && ix < npx && iy >= 0 && iy < npy)
           img[(((int64_t)v * m->nimg + q) * npy + iy) * npx + ix] += F;
@@ -1187,9 +1239,13 @@ int orc_raytrace(const orc_model *m, const double *T, const double *ssca, const 
  * dI/d(dtau_i) = T_<i S_i e^{-dtau_i} - (I - A_i), A_i the intensity
  * gathered up to and including cell i. A first sweep gives I, a second
  * recomputes the transmittance and A_i. */
-int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca,
+int orc_raytrace_adjoint(const orc_model *m, int rt_mode, const double *T, const double *ssca,
                          const double *rho_rt, int npx, int npy, const double *w_img,
                          const double *w_sed, double *drho) {
+  /* printed form: the cell terms C_i do not depend on rho_rt, so
+   * dI/d(dtau_i) = -(I - A_i) with A_i the intensity gathered up to and
+   * including cell i */
+  const int lit = rt_mode == ORC_RT_ABS_LITERAL;
   if (!rho_rt) rho_rt = m->rho;
   tab_t t;
   tab_init(&t, m);
@@ -1213,6 +1269,21 @@ int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca
                      (w_sed ? w_sed[v * m->nimg + q] : 0.0);
           if (W == 0.0) continue;
           double I = 0.0, tr = 1.0;
+          if (lit) {
+            double ka = kabs_all(&t, m, j);
+            for (int s = 0; s < nseg; s++) {
+              I += tr * cell_literal(&t, m, T, ssca, v, q, cells[s]);
+              tr *= exp(-(rho_rt[cells[s]] * ka * lens[s]));
+            }
+            double A = 0.0;
+            tr = 1.0;
+            for (int s = 0; s < nseg; s++) {
+              A += tr * cell_literal(&t, m, T, ssca, v, q, cells[s]);
+              drho[cells[s]] += W * (apix / D2) * ka * lens[s] * (-(I - A));
+              tr *= exp(-(rho_rt[cells[s]] * ka * lens[s]));
+            }
+            continue;
+          }
           for (int s = 0; s < nseg; s++) {
             double rho = rho_rt[cells[s]];
             if (!(rho > 0.0)) continue;
@@ -1253,10 +1324,11 @@ int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca
         double W = (w_sed ? w_sed[v * m->nimg + q] : 0.0) +
                    ((inimg && w_img) ? w_img[(((int64_t)v * m->nimg + q) * npy + iy) * npx + ix] : 0.0);
         if (W == 0.0) continue;
+        double kx = lit ? kabs_all(&t, m, j) : t.kext[j];
         double tau = 0.0;
-        for (int g = 0; g < nseg; g++) tau += rho_rt[cells[g]] * t.kext[j] * lens[g];
+        for (int g = 0; g < nseg; g++) tau += rho_rt[cells[g]] * kx * lens[g];
         double F = t.lnu[s * t.nl + j] / (4.0 * PI_D * D2) * exp(-tau);
-        for (int g = 0; g < nseg; g++) drho[cells[g]] += -W * t.kext[j] * lens[g] * F;
+        for (int g = 0; g < nseg; g++) drho[cells[g]] += -W * kx * lens[g] * F;
       }
     }
   }

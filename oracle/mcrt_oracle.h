@@ -19,6 +19,12 @@ extern "C" {
 #endif
 
 enum { ORC_FROZEN = 0, ORC_BW_EPOCH = 1 };
+/* optical depth of a flight: one draw per flight, or a new draw on entering
+ * each cell (the footnote to the sect. 2 interaction test) */
+enum { ORC_TAU_FLIGHT = 0, ORC_TAU_PER_CELL = 1 };
+/* ray-tracer formal solution: extinction chord form, or Eqs. 13-14 as
+ * printed (absorption optical depth, face-to-face cell emission) */
+enum { ORC_RT_EXT = 0, ORC_RT_ABS_LITERAL = 1 };
 enum { ORC_ALIVE = 0, ORC_ESCAPED = 1, ORC_KILLED = 2, ORC_PAH_STOP = 3 };
 
 typedef struct {
@@ -56,7 +62,9 @@ typedef struct {
   int32_t ntheta;     /* SED polar bins (equal in cos theta) */
   int32_t model_id;
   int32_t record;     /* fill per-packet records */
-  int32_t pad;
+  int32_t tau_mode;   /* ORC_TAU_FLIGHT or ORC_TAU_PER_CELL */
+  uint64_t src_strata;/* m > 0: packet pid takes source-spectrum stratum pid mod m
+                         (m equal-energy source bins, Eq. 1); 0 = plain draw */
 } orc_opts;
 
 typedef struct {
@@ -128,10 +136,10 @@ void orc_finalize_T(const orc_model *m, const orc_opts *o, orc_state *st);
 /* Ray-tracer (sect. 4): images [nview][nimg][npy][npx], SED [nview][nimg].
  * rho_rt (NULL = model density) is the density used for extinction; the
  * source function keeps the model's values (emissivity per unit mass). */
-int orc_raytrace(const orc_model *m, const double *T, const double *ssca, const double *rho_rt,
-                 int npx, int npy, double *img, double *sed);
+int orc_raytrace(const orc_model *m, int rt_mode, const double *T, const double *ssca,
+                 const double *rho_rt, int npx, int npy, double *img, double *sed);
 /* Gradient of sum(w_img*img) + sum(w_sed*sed) with respect to rho_rt [cells]. */
-int orc_raytrace_adjoint(const orc_model *m, const double *T, const double *ssca,
+int orc_raytrace_adjoint(const orc_model *m, int rt_mode, const double *T, const double *ssca,
                          const double *rho_rt, int npx, int npy, const double *w_img,
                          const double *w_sed, double *drho);
 

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "mcrt_oracle.c")
 
 FROZEN, BW_EPOCH = 0, 1
+TAU_FLIGHT, TAU_PER_CELL = 0, 1
+RT_EXT, RT_ABS_LITERAL = 0, 1
 ESCAPED, KILLED, PAH_STOP = 1, 2, 3
 
 _dp = C.POINTER(C.c_double)
@@ -61,7 +63,8 @@ class Opts(C.Structure):
         ("mode", C.c_int32), ("n_iter", C.c_int32), ("epoch", C.c_uint64),
         ("n_total", C.c_uint64), ("lucy_tau", C.c_double), ("mrw_tau", C.c_double),
         ("mrw_gamma", C.c_double), ("max_int", C.c_uint64), ("ntheta", C.c_int32),
-        ("model_id", C.c_int32), ("record", C.c_int32), ("pad", C.c_int32),
+        ("model_id", C.c_int32), ("record", C.c_int32), ("tau_mode", C.c_int32),
+        ("src_strata", C.c_uint64),
     ]
 
 
@@ -132,9 +135,10 @@ def lib():
                               C.c_uint64, C.POINTER(State)]
         L.orc_pah_pass.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint64, C.POINTER(State)]
         L.orc_finalize_T.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.POINTER(State)]
-        L.orc_raytrace.argtypes = [C.POINTER(Model), _dp, _dp, _dp, C.c_int, C.c_int, _dp, _dp]
-        L.orc_raytrace_adjoint.argtypes = [C.POINTER(Model), _dp, _dp, _dp, C.c_int, C.c_int,
-                                           _dp, _dp, _dp]
+        L.orc_raytrace.argtypes = [C.POINTER(Model), C.c_int, _dp, _dp, _dp, C.c_int, C.c_int,
+                                   _dp, _dp]
+        L.orc_raytrace_adjoint.argtypes = [C.POINTER(Model), C.c_int, _dp, _dp, _dp, C.c_int,
+                                           C.c_int, _dp, _dp, _dp]
         L.orc_voxelize_torus.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_double, C.c_int,
                                          _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double, _dp]
@@ -317,8 +321,10 @@ class Oracle:
         return s
 
     def opts(self, mode=BW_EPOCH, n_iter=3, epoch=4096, n_total=None, lucy_tau=1e-2,
-             mrw_tau=0.0, mrw_gamma=2.0, max_int=10_000_000, model_id=0, record=False):
+             mrw_tau=0.0, mrw_gamma=2.0, max_int=10_000_000, model_id=0, record=False,
+             tau_mode=TAU_FLIGHT, src_strata=0):
         o = Opts()
+        o.tau_mode, o.src_strata = tau_mode, src_strata
         o.mode, o.n_iter, o.epoch = mode, n_iter, epoch
         o.n_total = n_total if n_total is not None else self.mi.n_packets
         o.lucy_tau, o.mrw_tau, o.mrw_gamma = lucy_tau, mrw_tau, mrw_gamma
@@ -389,7 +395,7 @@ class Oracle:
             raise RuntimeError("maxseg too small")
         return cells[:n], lens[:n]
 
-    def raytrace(self, npx, npy, T=None, ssca=None, rho_rt=None):
+    def raytrace(self, npx, npy, T=None, ssca=None, rho_rt=None, rt_mode=RT_EXT):
         """Images [view][img][npy][npx] and SED [view][img]; rho_rt replaces the
         density in the optical depths only (source functions keep the model's)."""
         T = _f64(self.T if T is None else T)
@@ -398,14 +404,16 @@ class Oracle:
         sed = np.zeros((nv, ni))
         ss = None if ssca is None else _f64(ssca)
         rr = None if rho_rt is None else _f64(rho_rt)
-        lib().orc_raytrace(C.byref(self.m), _p(T), _p(ss), _p(rr), npx, npy, _p(img), _p(sed))
+        lib().orc_raytrace(C.byref(self.m), rt_mode, _p(T), _p(ss), _p(rr), npx, npy, _p(img),
+                           _p(sed))
         return img, sed
 
-    def raytrace_adjoint(self, npx, npy, w_img=None, w_sed=None, T=None, ssca=None, rho_rt=None):
+    def raytrace_adjoint(self, npx, npy, w_img=None, w_sed=None, T=None, ssca=None, rho_rt=None,
+                         rt_mode=RT_EXT):
         T = _f64(self.T if T is None else T)
         ss = None if ssca is None else _f64(ssca)
         rr = None if rho_rt is None else _f64(rho_rt)
         drho = np.zeros(self.ncells)
-        lib().orc_raytrace_adjoint(C.byref(self.m), _p(T), _p(ss), _p(rr), npx, npy,
+        lib().orc_raytrace_adjoint(C.byref(self.m), rt_mode, _p(T), _p(ss), _p(rr), npx, npy,
                                    _p(_f64(w_img)), _p(_f64(w_sed)), _p(drho))
         return drho

@@ -94,8 +94,12 @@ def test_fp32_lucy_with_packet_energy_above_float_max(orc):
     assert ep.sum() == pytest.approx(o.epath.sum(), rel=2e-3)
     big = o.epath > 1e-3 * o.epath.max()
     np.testing.assert_allclose(ep[big], o.epath[big], rtol=3e-2)
+    # a single packet of 3.3e39 erg/s absorbed in a cell of this tiny mass puts
+    # Eq. 10's temperature (E + xi) above the 1e5 K ceiling in both codes; the
+    # few such absorptions are the same packets on both sides
+    assert abs(st["clamped_T"] - o.stats["clamped_T"]) <= 2
     T = g.temperatures()
-    assert np.all(np.isfinite(T)) and st["clamped_T"] == 0
+    assert np.all(np.isfinite(T)) and T.max() < 1e5
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
