@@ -247,6 +247,35 @@ def shell(n: int = 128, tau_v: float = 10.0, n_packets: int = 10_000_000,
         geometry={"kind": "shell", "rho0": rho0, "r_in": r_in, "r_out": r_out})
 
 
+def ivezic_dust(lam, kext_v=1.0e4, lam0=1.0):
+    """Grey-to-power-law grains of the 1D benchmark (sect. 5.1): q_abs = q_sca =
+    1 below lam0, q_abs = lam0/lam and q_sca = (lam0/lam)^4 above; isotropic
+    scattering. Scaled so that kappa_ext at 0.55 um is kext_v."""
+    x = np.minimum(1.0, lam0 / np.asarray(lam, dtype=np.float64))
+    qa, qs = x, x**4
+    scale = kext_v / 2.0  # both efficiencies are 1 at 0.55 um
+    return (scale * qa)[None, :], (scale * qs)[None, :], np.zeros((1, len(lam)))
+
+
+def replica(n: int = 100, tau_v: float = 10.0, n_packets: int = 10_000_000, seed: int = 0,
+            nl: int = 100, r_in_au: float = 0.7, r_out_au: float = 700.0,
+            t_star: float = 2500.0) -> ModelInputs:
+    """Run-time comparison model of sect. 3.6 (Table 1): a 2500 K, 1 L_sun star
+    in a constant-density envelope 0.7-700 AU with tau_V = 10 from the star to
+    the outer edge, 10^6 cells (box of half-size r_out), 10^7 packets."""
+    lam = lambda_grid(nl, 0.1, 1000.0)
+    kext_v = 1.0e4
+    kabs, ksca, gg = ivezic_dust(lam, kext_v=kext_v)
+    r_in, r_out = r_in_au * AU_CM, r_out_au * AU_CM
+    rho0 = tau_v / (kext_v * (r_out - r_in))
+    return ModelInputs(
+        name=f"replica{n}", nx=n, ny=n, nz=n, origin=np.array([-r_out] * 3),
+        dcell=2.0 * r_out / n, rho=None, lam_um=lam, mass_frac=np.array([1.0]),
+        kabs=kabs, ksca=ksca, g=gg, src_pos=np.zeros((1, 3)), src_lum=np.array([LSUN]),
+        src_tbb=np.array([t_star]), n_packets=n_packets, seed=seed,
+        geometry={"kind": "shell", "rho0": rho0, "r_in": r_in, "r_out": r_out, "power": 0.0})
+
+
 def torus(n: int = 256, n_clumps: int = 2000, n_packets: int = 100_000_000,
           seed: int = 0, geo_seed: int = 2, nl: int = 100, lum: float = 1e45,
           r_in_pc: float = 0.4, r_out_pc: float = 6.0, theta1_deg: float = 45.0,
@@ -312,4 +341,4 @@ def image_views(n_views: int = 8, n_img: int = 16, nl: int = 100):
 
 
 def workload(name: str, **kw) -> ModelInputs:
-    return {"cube": cube, "shell": shell, "torus": torus}[name](**kw)
+    return {"cube": cube, "shell": shell, "torus": torus, "replica": replica}[name](**kw)

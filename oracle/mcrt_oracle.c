@@ -709,6 +709,29 @@ static int pah_row(const run_t *R, int64_t c) {
   return r;
 }
 
+/* Photodissociation (sect. 2.1, Eq. 8). The cell's PAH absorb kpah xi erg/s
+ * (pass 1) shared by its f_pah rho V / m_PAH molecules, m_PAH = N_C 12 amu
+ * (carbon only); within the cooling time t_cool each molecule takes
+ * E_PAH = kpah xi m_PAH t_cool / (f_pah rho V), and the molecules dissociate
+ * when E_PAH >= N_C/2 eV. */
+#define AMU_G 1.66053906660e-24
+#define EV_ERG 1.602176634e-12
+static int pah_dissociates_xi(const orc_model *m, const orc_opts *o, double xi, double V,
+                              uint32_t kpah, int64_t c) {
+  if (!(o->pah_nc > 0.0) || !(o->pah_tcool > 0.0) || kpah == 0) return 0;
+  double rho = m->rho[c];
+  double mp = o->pah_nc * 12.0 * AMU_G;
+  double e = (double)kpah * xi * mp * o->pah_tcool / (m->mass_frac[m->pah_species] * rho * V);
+  return e >= 0.5 * o->pah_nc * EV_ERG;
+}
+
+int orc_pah_dissociates(const orc_model *m, const orc_opts *o, uint32_t kpah, int64_t c) {
+  double ltot = 0.0;
+  for (int s = 0; s < m->nsrc; s++) ltot += m->src_lum[s];
+  double V = m->dcell * m->dcell * m->dcell;
+  return pah_dissociates_xi(m, o, ltot / (double)o->n_total, V, kpah, c);
+}
+
 static int pick_pah_lambda(run_t *R, int row, double u, double *mm) {
   int nl = R->t.nl;
   for (int j = 0; j < nl; j++) R->f[j] = R->t.w[j] * R->m->pah_emis[row * nl + j];
@@ -761,7 +784,7 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
   memset(&P, 0, sizeof(P));
   P.mm = INFINITY;
   R->st->st.packets++;
-  if (R->pass == 2) {
+  if (R->pass == 2 && !pah_dissociates_xi(m, R->o, R->xi, t->V, R->st->kpah[pcell], pcell)) {
     int64_t c = pcell;
     int cc[3] = {(int)(c % m->nx), (int)((c / m->nx) % m->ny), (int)(c / ((int64_t)m->nx * m->ny))};
     double ux = rng_next(&rg), uy = rng_next(&rg), uz = rng_next(&rg);
@@ -779,7 +802,7 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
     /* m equal-energy source bins of Eq. 1, each emitting every m-th packet:
      * packet pid draws inside stratum pid mod m of the source spectrum's
      * cumulative distribution */
-    if (R->o->src_strata > 0)
+    if (R->o->src_strata > 0 && R->pass != 2)
       ul = ((double)(pid % R->o->src_strata) + ul) / (double)R->o->src_strata;
     iso_dir(uph, umu, P.d);
     int s = pick_asc(m->src_lum, m->nsrc, us, &P.mm);
@@ -1412,10 +1435,18 @@ static void gauss_legendre(int n, double *x, double *w) {
   }
 }
 
-/* r^-2 shell: cell average of rho0 (r_in/r)^2 on [r_in, r_out] by an 8^3
- * Gauss-Legendre rule per cell. */
+/* Power-law shell: cell average of rho0 (r_in/r)^power on [r_in, r_out]
+ * (power 2: the r^-2 shell; 0: constant density) by an 8^3 Gauss-Legendre
+ * rule per cell. */
+static double shell_law(double rho0, double r_in, double r, double power) {
+  double q = r_in / r;
+  if (power == 2.0) return rho0 * q * q;
+  if (power == 0.0) return rho0;
+  return rho0 * pow(q, power);
+}
+
 void orc_voxelize_shell(int nx, int ny, int nz, const double origin[3], double dcell,
-                        double rho0, double r_in, double r_out, double *rho) {
+                        double rho0, double r_in, double r_out, double power, double *rho) {
   double gx[8], gw[8];
   gauss_legendre(8, gx, gw);
   for (int iz = 0; iz < nz; iz++)
@@ -1429,7 +1460,7 @@ void orc_voxelize_shell(int nx, int ny, int nz, const double origin[3], double d
               double y = origin[1] + ((double)iy + 0.5 + 0.5 * gx[b]) * dcell;
               double z = origin[2] + ((double)iz + 0.5 + 0.5 * gx[e]) * dcell;
               double r = sqrt(x * x + y * y + z * z);
-              double f = (r >= r_in && r <= r_out) ? rho0 * (r_in / r) * (r_in / r) : 0.0;
+              double f = (r >= r_in && r <= r_out) ? shell_law(rho0, r_in, r, power) : 0.0;
               sum += gw[a] * gw[b] * gw[e] * f;
             }
         rho[((int64_t)iz * ny + iy) * nx + ix] = 0.125 * sum;

@@ -65,6 +65,8 @@ typedef struct {
   int32_t tau_mode;   /* ORC_TAU_FLIGHT or ORC_TAU_PER_CELL */
   uint64_t src_strata;/* m > 0: packet pid takes source-spectrum stratum pid mod m
                          (m equal-energy source bins, Eq. 1); 0 = plain draw */
+  double pah_nc;      /* carbon atoms per PAH molecule (Eq. 8); <= 0: no dissociation */
+  double pah_tcool;   /* PAH cooling time in s over which absorbed energy adds up */
 } orc_opts;
 
 typedef struct {
@@ -123,12 +125,17 @@ double orc_mrw_solve(double u);
 int orc_dda(const orc_model *m, const double p0[3], const double d[3],
             int maxseg, int64_t *cells, double *lens);
 
+/* 1 if the PAH of cell c (pass-1 count kpah) dissociate under Eq. 8. */
+int orc_pah_dissociates(const orc_model *m, const orc_opts *o, uint32_t kpah, int64_t c);
 /* Thin-limit initial temperatures at cell centres. */
 void orc_init_T(const orc_model *m, double *T);
 /* Monte Carlo transport of packets [first, first+n). */
 int orc_run(const orc_model *m, const orc_opts *o, uint64_t first, uint64_t n,
             uint64_t seed, orc_state *st);
-/* Second PAH stage: cells re-emit their pass-1 PAH absorptions. */
+/* Second PAH stage: cells re-emit their pass-1 PAH absorptions. With
+ * pah_nc > 0, a cell whose PAH molecules absorb at least E_crit = N_C/2 eV
+ * within a cooling time (Eq. 8) dissociates them: its packets start from
+ * the source instead, as source packets. */
 int orc_pah_pass(const orc_model *m, const orc_opts *o, uint64_t seed, orc_state *st);
 /* Eq. 4 for every cell and species from the current tallies. */
 void orc_finalize_T(const orc_model *m, const orc_opts *o, orc_state *st);
@@ -149,7 +156,7 @@ void orc_voxelize_torus(int nx, int ny, int nz, const double origin[3], double d
                         double rho_inter, double r_in, double r_out, double sin_theta1,
                         double *rho);
 void orc_voxelize_shell(int nx, int ny, int nz, const double origin[3], double dcell,
-                        double rho0, double r_in, double r_out, double *rho);
+                        double rho0, double r_in, double r_out, double power, double *rho);
 
 #ifdef __cplusplus
 }

@@ -64,7 +64,7 @@ class Opts(C.Structure):
         ("n_total", C.c_uint64), ("lucy_tau", C.c_double), ("mrw_tau", C.c_double),
         ("mrw_gamma", C.c_double), ("max_int", C.c_uint64), ("ntheta", C.c_int32),
         ("model_id", C.c_int32), ("record", C.c_int32), ("tau_mode", C.c_int32),
-        ("src_strata", C.c_uint64),
+        ("src_strata", C.c_uint64), ("pah_nc", C.c_double), ("pah_tcool", C.c_double),
     ]
 
 
@@ -131,6 +131,8 @@ def lib():
         L.orc_planck_mean.restype = C.c_double
         L.orc_dda.argtypes = [C.POINTER(Model), _dp, _dp, C.c_int, C.POINTER(C.c_int64), _dp]
         L.orc_init_T.argtypes = [C.POINTER(Model), _dp]
+        L.orc_pah_dissociates.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint32,
+                                          C.c_int64]
         L.orc_run.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint64, C.c_uint64,
                               C.c_uint64, C.POINTER(State)]
         L.orc_pah_pass.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint64, C.POINTER(State)]
@@ -143,7 +145,7 @@ def lib():
                                          _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double, _dp]
         L.orc_voxelize_shell.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_double, C.c_double,
-                                         C.c_double, C.c_double, _dp]
+                                         C.c_double, C.c_double, C.c_double, _dp]
         _lib = L
     return _lib
 
@@ -222,7 +224,7 @@ def voxelize_shell(nx, ny, nz, origin, dcell, geo):
     rho = np.zeros((nz, ny, nx))
     o = _f64(origin)
     lib().orc_voxelize_shell(nx, ny, nz, _p(o), dcell, geo["rho0"], geo["r_in"], geo["r_out"],
-                             _p(rho))
+                             geo.get("power", 2.0), _p(rho))
     return rho
 
 
@@ -322,9 +324,10 @@ class Oracle:
 
     def opts(self, mode=BW_EPOCH, n_iter=3, epoch=4096, n_total=None, lucy_tau=1e-2,
              mrw_tau=0.0, mrw_gamma=2.0, max_int=10_000_000, model_id=0, record=False,
-             tau_mode=TAU_FLIGHT, src_strata=0):
+             tau_mode=TAU_FLIGHT, src_strata=0, pah_nc=0.0, pah_tcool=0.0):
         o = Opts()
         o.tau_mode, o.src_strata = tau_mode, src_strata
+        o.pah_nc, o.pah_tcool = pah_nc, pah_tcool
         o.mode, o.n_iter, o.epoch = mode, n_iter, epoch
         o.n_total = n_total if n_total is not None else self.mi.n_packets
         o.lucy_tau, o.mrw_tau, o.mrw_gamma = lucy_tau, mrw_tau, mrw_gamma
@@ -370,6 +373,13 @@ class Oracle:
     def xi(self, n_total=None):
         n_total = self.mi.n_packets if n_total is None else n_total
         return float(np.sum(self.src_lum)) / n_total
+
+    def pah_dissociates(self, kpah=None, **kw):
+        """Eq. 8 decision per cell for the given pass-1 PAH counts."""
+        kp = self.kpah if kpah is None else kpah
+        o = self.opts(**kw)
+        return np.array([lib().orc_pah_dissociates(C.byref(self.m), C.byref(o), int(kp[c]), c)
+                         for c in range(self.ncells)], dtype=bool)
 
     def phi(self, s, T):
         return lib().orc_phi(C.byref(self.m), s, T)

@@ -40,3 +40,27 @@ def test_shell_mass(orc):
     assert mass == pytest.approx(exact, rel=0.01)
     c = n // 2
     assert rho[c, c, c] == 0.0  # cavity
+
+
+def test_constant_shell_mass(orc):
+    """power 0: the envelope of the sect. 3.6 run-time comparison holds
+    rho0 * 4/3 pi (r_out^3 - r_in^3) (up to the cells its surfaces cut)."""
+    m = mi.replica(n=40, n_packets=10, r_out_au=700.0 * 0.95, r_in_au=60.0)
+    geo = m.geometry
+    assert geo["power"] == 0.0
+    rho = orc.voxelize_shell(m.nx, m.ny, m.nz, m.origin, m.dcell, geo)
+    mass = rho.sum() * m.dcell**3
+    exact = 4 / 3 * math.pi * geo["rho0"] * (geo["r_out"] ** 3 - geo["r_in"] ** 3)
+    assert mass == pytest.approx(exact, rel=0.01)
+    inside = rho[rho > 0]
+    assert np.max(inside) == pytest.approx(geo["rho0"], rel=1e-12)
+    c = m.nx // 2
+    assert rho[c, c, c] == 0.0
+
+
+def test_ivezic_dust_law():
+    lam = np.array([0.3, 0.55, 1.0, 2.0, 10.0])
+    ka, ks, g = mi.ivezic_dust(lam, kext_v=2.0)
+    np.testing.assert_allclose(ka[0], [1.0, 1.0, 1.0, 0.5, 0.1], rtol=1e-15)
+    np.testing.assert_allclose(ks[0], [1.0, 1.0, 1.0, 0.0625, 1e-4], rtol=1e-15)
+    assert np.all(g == 0.0)
