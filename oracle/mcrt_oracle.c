@@ -134,6 +134,9 @@ typedef struct {
   double V;
   double *nu, *w;
   double *kabs_mix, *ksca_mix, *kext, *alb, kext_max;
+  double *ksca_eff, *g_eff; /* [ns][nl] scattering opacity and asymmetry as transported:
+                               the model's, or (1 - g) kappa_sca and 0 under the
+                               g-factor approximation */
   double *lucy_frac;  /* [ns][nl] f_s kabs_s / kabs_mix */
   double *lnu;        /* [nsrc][nl] L_nu,s,j erg/s/Hz */
   double *src_f;      /* [nsrc][nl] w_j L_nu,s,j */
@@ -167,13 +170,19 @@ static int tab_init(tab_t *t, const orc_model *m) {
   t->src_f = malloc(sizeof(double) * nl * (m->nsrc > 0 ? m->nsrc : 1));
   t->imgmap = malloc(sizeof(int) * nl);
   t->kv = malloc(sizeof(double[3]) * (m->nview > 0 ? m->nview : 1));
+  t->ksca_eff = malloc(sizeof(double) * nl * ns);
+  t->g_eff = malloc(sizeof(double) * nl * ns);
+  for (int i = 0; i < nl * ns; i++) {
+    t->ksca_eff[i] = m->scat_law == 1 ? (1.0 - m->g[i]) * m->ksca[i] : m->ksca[i];
+    t->g_eff[i] = m->scat_law == 1 ? 0.0 : m->g[i];
+  }
   orc_freq_grid(nl, m->lam_um, t->nu, t->w);
   t->kext_max = 0.0;
   for (int j = 0; j < nl; j++) {
     double a = 0.0, s = 0.0;
     for (int q = 0; q < ns; q++) {
       a += m->mass_frac[q] * m->kabs[q * nl + j];
-      s += m->mass_frac[q] * m->ksca[q * nl + j];
+      s += m->mass_frac[q] * t->ksca_eff[q * nl + j];
     }
     t->kabs_mix[j] = a;
     t->ksca_mix[j] = s;
@@ -213,6 +222,7 @@ static int tab_init(tab_t *t, const orc_model *m) {
 static void tab_free(tab_t *t) {
   free(t->nu); free(t->w); free(t->kabs_mix); free(t->ksca_mix); free(t->kext);
   free(t->alb); free(t->lucy_frac); free(t->lnu); free(t->src_f); free(t->imgmap);
+  free(t->ksca_eff); free(t->g_eff);
   free(t->kv);
 }
 
@@ -272,6 +282,63 @@ double orc_hg_mu(double g, double u) {
 double orc_hg_phase(double g, double mu) {
   double den = 1.0 + g * g - 2.0 * g * mu;
   return (1.0 - g * g) / (4.0 * PI_D * den * sqrt(den));
+}
+
+/* Real orthonormal spherical harmonics by the associated-Legendre recurrence
+ * in x = cos(theta) without the sin^m factor (Q_l^m), the azimuthal terms
+ * from (d_x + i d_y)^m = sin^m(theta) e^{i m phi}:
+ *   Q_m^m = (2m-1)!!, Q_{m+1}^m = (2m+1) x Q_m^m,
+ *   (l-m) Q_l^m = (2l-1) x Q_{l-1}^m - (l+m-1) Q_{l-2}^m,
+ *   Y_l0 = N_l0 Q_l^0, Y_l,+-m = sqrt(2) N_lm Q_l^m (Re, Im)(d_x + i d_y)^m,
+ *   N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!). */
+void orc_ylm(int lmax, const double d[3], double *y) {
+  double x = d[2];
+  double cr = 1.0, ci = 0.0; /* (d_x + i d_y)^m */
+  double qmm = 1.0;          /* Q_m^m */
+  for (int m = 0; m <= lmax; m++) {
+    if (m > 0) {
+      double nr = cr * d[0] - ci * d[1], ni = cr * d[1] + ci * d[0];
+      cr = nr;
+      ci = ni;
+      qmm *= (double)(2 * m - 1);
+    }
+    double q2 = 0.0, q1 = qmm; /* Q_{l-2}^m, Q_{l-1}^m */
+    for (int l = m; l <= lmax; l++) {
+      double q;
+      if (l == m) q = qmm;
+      else if (l == m + 1) q = (double)(2 * m + 1) * x * qmm;
+      else q = ((double)(2 * l - 1) * x * q1 - (double)(l + m - 1) * q2) / (double)(l - m);
+      if (l > m) {
+        q2 = q1;
+        q1 = q;
+      }
+      /* (l-m)!/(l+m)! */
+      double ratio = 1.0;
+      for (int k = l - m + 1; k <= l + m; k++) ratio /= (double)k;
+      double n = sqrt((2.0 * l + 1.0) / (4.0 * PI_D) * ratio);
+      if (m == 0) {
+        y[l * l + l] = n * q;
+      } else {
+        y[l * l + l + m] = sqrt(2.0) * n * q * cr;
+        y[l * l + l - m] = sqrt(2.0) * n * q * ci;
+      }
+    }
+  }
+}
+
+void orc_sh_view_sums(const orc_model *m, int sh_order, const double *sh, const double k[3],
+                      double *out) {
+  int lmax = sh_order - 1, nlm = sh_order * sh_order;
+  int64_t nc = (int64_t)m->nx * m->ny * m->nz;
+  double *y = malloc(sizeof(double) * nlm);
+  orc_ylm(lmax, k, y);
+  for (int q = 0; q < m->nimg; q++)
+    for (int64_t c = 0; c < nc; c++) {
+      double s = 0.0;
+      for (int i = 0; i < nlm; i++) s += y[i] * sh[((int64_t)q * nlm + i) * nc + c];
+      out[(int64_t)q * nc + c] = s;
+    }
+  free(y);
 }
 
 /* Survival probability of a diffusing packet started at the centre of a
@@ -835,9 +902,9 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
     int j = P.j;
     upd_margin(&P.mm, fabs(ualb - t->alb[j]));
     if (ualb < t->alb[j]) {
-      for (int s = 0; s < ns; s++) R->fs[s] = m->mass_frac[s] * m->ksca[s * nl + j];
+      for (int s = 0; s < ns; s++) R->fs[s] = m->mass_frac[s] * t->ksca_eff[s * nl + j];
       int s = pick_asc(R->fs, ns, usp, &P.mm);
-      double gg = m->g[s * nl + j];
+      double gg = t->g_eff[s * nl + j];
       double umu = rng_next(&rg), uph = rng_next(&rg);
       double mu = orc_hg_mu(gg, umu);
       int q = t->imgmap[j];
@@ -845,6 +912,20 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
         for (int v = 0; v < m->nview; v++) {
           double cb = P.d[0] * t->kv[v][0] + P.d[1] * t->kv[v][1] + P.d[2] * t->kv[v][2];
           R->st->ssca[((int64_t)v * m->nimg + q) * t->ncell + c] += R->xi * orc_hg_phase(gg, cb);
+        }
+        /* event stored for any observer: P_HG(d.k) = sum_l g^l sum_m Y_lm(d) Y_lm(k) */
+        if (R->o->sh_order > 0 && R->st->sh) {
+          int L1 = R->o->sh_order, nlm = L1 * L1;
+          double y[256];
+          orc_ylm(L1 - 1, P.d, y);
+          double gl = 1.0;
+          for (int l = 0; l < L1; l++) {
+            for (int mm = -l; mm <= l; mm++) {
+              int i = l * l + l + mm;
+              R->st->sh[((int64_t)q * nlm + i) * t->ncell + c] += R->xi * gl * y[i];
+            }
+            gl *= gg;
+          }
         }
       }
       rotate_dir(P.d, mu, 2.0 * PI_D * uph);
@@ -900,6 +981,9 @@ static void zero_tallies(const run_t *R) {
   memset(R->st->sed, 0, sizeof(uint64_t) * nt * R->t.nl);
   if (m->nview > 0 && m->nimg > 0 && R->st->ssca)
     memset(R->st->ssca, 0, sizeof(double) * nc * m->nview * m->nimg);
+  if (R->o->sh_order > 0 && m->nimg > 0 && R->st->sh)
+    memset(R->st->sh, 0,
+           sizeof(double) * nc * m->nimg * (size_t)R->o->sh_order * (size_t)R->o->sh_order);
 }
 
 /* Start of an epoch: cells whose energy changed get a fresh snapshot and

@@ -39,7 +39,9 @@ typedef struct {
   int32_t pah_species, n_pah_rows;
   const double *pah_emis;        /* [rows][nl] */
   const double *pah_edges;       /* [rows-1] */
-  int32_t nsrc, pad1;
+  int32_t nsrc;
+  int32_t scat_law;              /* 0: Henyey-Greenstein (Eq. 15); 1: g-factor approximation,
+                                    isotropic scattering with kappa_sca (1 - g) (sect. 4) */
   const double *src_pos;         /* [nsrc][3] */
   const double *src_lum;         /* [nsrc] erg/s */
   const double *src_shape;       /* [nsrc][nl] ~ L_nu, or NULL */
@@ -67,6 +69,10 @@ typedef struct {
                          (m equal-energy source bins, Eq. 1); 0 = plain draw */
   double pah_nc;      /* carbon atoms per PAH molecule (Eq. 8); <= 0: no dissociation */
   double pah_tcool;   /* PAH cooling time in s over which absorbed energy adds up */
+  int32_t sh_order;   /* L + 1 > 0: keep the scattering events of the imaged wavelengths
+                         as spherical-harmonic moments up to degree L (sect. 4: scattered
+                         light toward any observer after the run); 0 = off */
+  int32_t pad2;
 } orc_opts;
 
 typedef struct {
@@ -93,6 +99,8 @@ typedef struct {
   uint32_t *kpah;     /* [cells] PAH absorptions of pass 1 */
   uint64_t *sed;      /* [ntheta][nl] escaped packet counts */
   double *ssca;       /* [nview][nimg][cells] HG-weighted scattering, erg/s/sr */
+  double *sh;         /* [nimg][(L+1)^2][cells] moments sum xi g^l Y_lm(d_in), erg/s
+                         (sh_order = L + 1 > 0) */
   orc_record *rec;    /* [n] when record */
   orc_stats st;
 } orc_state;
@@ -118,6 +126,15 @@ double orc_hg_mu(double g, double u);                           /* Eq. 15 CDF */
 double orc_hg_phase(double g, double mu);                       /* Eq. 15 */
 double orc_mrw_survival(double y);
 double orc_mrw_solve(double u);
+
+/* Real orthonormal spherical harmonics Y_lm(d) for l <= lmax, m = -l..l,
+ * at index l^2 + l + m (m > 0: cos(m phi) terms, m < 0: sin(|m| phi)). */
+void orc_ylm(int lmax, const double d[3], double *y);
+/* Scattered-light sums toward direction k from the moments of an order
+ * sh_order run: out[q][c] = sum_lm Y_lm(k) sh[q][lm][c] (erg/s/sr), the
+ * Henyey-Greenstein phase function expanded in Legendre terms g^l. */
+void orc_sh_view_sums(const orc_model *m, int sh_order, const double *sh, const double k[3],
+                      double *out);
 
 /* Voxel walk from p0 along d starting in cell c (face rule applied by the
  * caller or by passing c[0] < 0). Writes up to maxseg (cell, length) pairs;

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "mcrt_oracle.c")
 
 FROZEN, BW_EPOCH = 0, 1
+SCAT_HG, SCAT_GFACTOR = 0, 1
 TAU_FLIGHT, TAU_PER_CELL = 0, 1
 RT_EXT, RT_ABS_LITERAL = 0, 1
 ESCAPED, KILLED, PAH_STOP = 1, 2, 3
@@ -51,7 +52,7 @@ class Model(C.Structure):
         ("nl", C.c_int32), ("ns", C.c_int32), ("lam_um", _dp), ("mass_frac", _dp),
         ("kabs", _dp), ("ksca", _dp), ("g", _dp),
         ("pah_species", C.c_int32), ("n_pah_rows", C.c_int32), ("pah_emis", _dp),
-        ("pah_edges", _dp), ("nsrc", C.c_int32), ("pad1", C.c_int32), ("src_pos", _dp),
+        ("pah_edges", _dp), ("nsrc", C.c_int32), ("scat_law", C.c_int32), ("src_pos", _dp),
         ("src_lum", _dp), ("src_shape", _dp), ("src_tbb", _dp),
         ("nview", C.c_int32), ("nimg", C.c_int32), ("view_deg", _dp), ("img_idx", _ip),
         ("distance", C.c_double),
@@ -65,6 +66,7 @@ class Opts(C.Structure):
         ("mrw_gamma", C.c_double), ("max_int", C.c_uint64), ("ntheta", C.c_int32),
         ("model_id", C.c_int32), ("record", C.c_int32), ("tau_mode", C.c_int32),
         ("src_strata", C.c_uint64), ("pah_nc", C.c_double), ("pah_tcool", C.c_double),
+        ("sh_order", C.c_int32), ("pad2", C.c_int32),
     ]
 
 
@@ -96,7 +98,7 @@ class State(C.Structure):
     _fields_ = [
         ("k", C.POINTER(C.c_uint64)), ("epath", _dp), ("T", _dp), ("esnap", _dp),
         ("tt", _dp), ("tvalid", C.POINTER(C.c_uint8)), ("kpah", C.POINTER(C.c_uint32)),
-        ("sed", C.POINTER(C.c_uint64)), ("ssca", _dp), ("rec", C.POINTER(Record)),
+        ("sed", C.POINTER(C.c_uint64)), ("ssca", _dp), ("sh", _dp), ("rec", C.POINTER(Record)),
         ("st", Stats),
     ]
 
@@ -131,6 +133,8 @@ def lib():
         L.orc_planck_mean.restype = C.c_double
         L.orc_dda.argtypes = [C.POINTER(Model), _dp, _dp, C.c_int, C.POINTER(C.c_int64), _dp]
         L.orc_init_T.argtypes = [C.POINTER(Model), _dp]
+        L.orc_ylm.argtypes = [C.c_int, _dp, _dp]
+        L.orc_sh_view_sums.argtypes = [C.POINTER(Model), C.c_int, _dp, _dp, _dp]
         L.orc_pah_dissociates.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint32,
                                           C.c_int64]
         L.orc_run.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint64, C.c_uint64,
@@ -210,6 +214,13 @@ def mrw_solve(u):
     return lib().orc_mrw_solve(u)
 
 
+def ylm(lmax, d):
+    """Real orthonormal spherical harmonics at unit vector d, index l^2 + l + m."""
+    y = np.zeros((lmax + 1) ** 2)
+    lib().orc_ylm(lmax, _p(_f64(d)), _p(y))
+    return y
+
+
 def voxelize_torus(nx, ny, nz, origin, dcell, geo):
     rho = np.zeros((nz, ny, nx))
     cen = _f64(geo["centres"])
@@ -245,7 +256,8 @@ def density(mi):
 class Oracle:
     """One model held as C structs plus the numpy arrays they point into."""
 
-    def __init__(self, mi, rho=None, views=None, img_idx=None, distance=1.0, ntheta=10):
+    def __init__(self, mi, rho=None, views=None, img_idx=None, distance=1.0, ntheta=10,
+                 scat_law=0):
         self.mi = mi
         self.rho = _f64(rho) if rho is not None else density(mi)
         self.lam = _f64(mi.lam_um)
@@ -282,6 +294,7 @@ class Oracle:
         m.view_deg = _p(self.views)
         m.img_idx = _p(self.img_idx, C.c_int32)
         m.distance = float(distance)
+        m.scat_law = scat_law
         self.m = m
         self.reset()
 
@@ -302,6 +315,7 @@ class Oracle:
         nv, ni = self.views.shape[0], self.img_idx.size
         self.ssca = np.zeros((nv, ni, nc)) if nv * ni > 0 else np.zeros(1)
         self.records = None
+        self.sh = None
         self.stats = {n: 0 for n in STAT_NAMES}
 
     def _state(self, nrec):
@@ -315,6 +329,7 @@ class Oracle:
         s.kpah = _p(self.kpah, C.c_uint32)
         s.sed = _p(self.sed, C.c_uint64)
         s.ssca = _p(self.ssca)
+        s.sh = _p(self.sh)
         if nrec:
             self.records = np.zeros(nrec, dtype=RECORD_DTYPE)
             s.rec = C.cast(self.records.ctypes.data, C.POINTER(Record))
@@ -324,10 +339,16 @@ class Oracle:
 
     def opts(self, mode=BW_EPOCH, n_iter=3, epoch=4096, n_total=None, lucy_tau=1e-2,
              mrw_tau=0.0, mrw_gamma=2.0, max_int=10_000_000, model_id=0, record=False,
-             tau_mode=TAU_FLIGHT, src_strata=0, pah_nc=0.0, pah_tcool=0.0):
+             tau_mode=TAU_FLIGHT, src_strata=0, pah_nc=0.0, pah_tcool=0.0, sh_order=0):
         o = Opts()
         o.tau_mode, o.src_strata = tau_mode, src_strata
         o.pah_nc, o.pah_tcool = pah_nc, pah_tcool
+        if not 0 <= sh_order <= 16:
+            raise ValueError("sh_order must be 0..16")
+        o.sh_order = sh_order
+        ni = self.img_idx.size
+        if sh_order > 0 and (self.sh is None or self.sh.shape[1] != sh_order**2):
+            self.sh = np.zeros((ni, sh_order**2, self.ncells))
         o.mode, o.n_iter, o.epoch = mode, n_iter, epoch
         o.n_total = n_total if n_total is not None else self.mi.n_packets
         o.lucy_tau, o.mrw_tau, o.mrw_gamma = lucy_tau, mrw_tau, mrw_gamma
@@ -373,6 +394,15 @@ class Oracle:
     def xi(self, n_total=None):
         n_total = self.mi.n_packets if n_total is None else n_total
         return float(np.sum(self.src_lum)) / n_total
+
+    def sh_view_sums(self, k, sh=None):
+        """Scattered-light sums [img][cells] toward unit vector k from the
+        moments of the last run with sh_order > 0."""
+        sh = self.sh if sh is None else _f64(sh)
+        out = np.zeros((self.img_idx.size, self.ncells))
+        lib().orc_sh_view_sums(C.byref(self.m), int(round(np.sqrt(sh.shape[1]))), _p(sh),
+                               _p(_f64(k)), _p(out))
+        return out
 
     def pah_dissociates(self, kpah=None, **kw):
         """Eq. 8 decision per cell for the given pass-1 PAH counts."""
