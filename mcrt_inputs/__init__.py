@@ -79,10 +79,19 @@ class ModelInputs:
     geometry: Optional[dict] = None
     n_packets: int = 0
     seed: int = 0
+    # one level of refinement: ref (nz, ny, nx) uint8, r >= 2 divides a cube
+    # into r^3 sub-cubes; rho_sub their densities, cube by cube in linear cube
+    # order, x fastest inside a cube
+    ref: Optional[np.ndarray] = None
+    rho_sub: Optional[np.ndarray] = None
 
     @property
     def ncells(self) -> int:
         return self.nx * self.ny * self.nz
+
+    @property
+    def nleaf(self) -> int:
+        return self.ncells + (0 if self.rho_sub is None else int(self.rho_sub.size))
 
     @property
     def nl(self) -> int:
@@ -329,6 +338,32 @@ def batch_specs(n_models: int = 64, seed: int = 4) -> List[dict]:
         out.append({"n": n, "n_clumps": ncl, "nl": nl, "n_packets": npk,
                     "seed": m, "geo_seed": 1000 + m})
     return out
+
+
+def sub_offsets(ref: np.ndarray) -> np.ndarray:
+    """First sub-cube of each cube: exclusive prefix sum of r^3 over the
+    divided cubes (r >= 2), in linear cube order (the layout of rho_sub)."""
+    r = np.asarray(ref, dtype=np.int64).ravel()
+    n = np.where(r >= 2, r**3, 0)
+    return np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+
+
+def refine_random(m: ModelInputs, frac: float = 0.3, rmax: int = 3, seed: int = 0,
+                  spread: float = 1.0) -> ModelInputs:
+    """Divide a random share of the cubes of a model with explicit densities
+    into r^3 sub-cubes (r uniform in 2..rmax) whose densities scatter
+    log-normally (sigma `spread`) about the cube's (seeded; inputs only)."""
+    rng = np.random.Generator(np.random.Philox(key=1000 + seed))
+    nc = m.ncells
+    ref = np.where(rng.random(nc) < frac, rng.integers(2, rmax + 1, nc), 0).astype(np.uint8)
+    rho = np.asarray(m.rho, dtype=np.float64).ravel()
+    subs = []
+    for c in np.flatnonzero(ref):
+        r = int(ref[c])
+        subs.append(rho[c] * np.exp(spread * rng.normal(size=r**3)))
+    rho_sub = np.concatenate(subs) if subs else np.zeros(0)
+    return dataclasses.replace(m, ref=ref.reshape(m.nz, m.ny, m.nx), rho_sub=rho_sub,
+                               name=m.name + "_refined")
 
 
 def image_views(n_views: int = 8, n_img: int = 16, nl: int = 100):

@@ -157,7 +157,7 @@ static int tab_init(tab_t *t, const orc_model *m) {
   int nl = m->nl, ns = m->ns;
   t->nl = nl;
   t->ns = ns;
-  t->ncell = (int64_t)m->nx * m->ny * m->nz;
+  t->ncell = orc_nleaf(m); /* leaves: every per-cell array runs over them */
   t->V = m->dcell * m->dcell * m->dcell;
   t->nu = malloc(sizeof(double) * nl);
   t->w = malloc(sizeof(double) * nl);
@@ -329,7 +329,7 @@ void orc_ylm(int lmax, const double d[3], double *y) {
 void orc_sh_view_sums(const orc_model *m, int sh_order, const double *sh, const double k[3],
                       double *out) {
   int lmax = sh_order - 1, nlm = sh_order * sh_order;
-  int64_t nc = (int64_t)m->nx * m->ny * m->nz;
+  int64_t nc = orc_nleaf(m);
   double *y = malloc(sizeof(double) * nlm);
   orc_ylm(lmax, k, y);
   for (int q = 0; q < m->nimg; q++)
@@ -417,32 +417,163 @@ static void upd_margin(double *mm, double v) {
   if (v < *mm) *mm = v;
 }
 
+/* ----------------------------------------------- leaves (one refinement level) */
+
+static int64_t n_cubes(const orc_model *m) { return (int64_t)m->nx * m->ny * m->nz; }
+
+int64_t orc_nleaf(const orc_model *m) { return n_cubes(m) + (m->ref ? m->nsub : 0); }
+
+/* sub-cubes per edge of cube cc (1: whole) */
+static int cube_r(const orc_model *m, int64_t cc) {
+  if (!m->ref) return 1;
+  int r = m->ref[cc];
+  return r > 1 ? r : 1;
+}
+
+/* leaf of sub-cube f of cube c (f = 0 for a whole cube) */
+static int64_t leaf_id(const orc_model *m, const int c[3], const int f[3]) {
+  int64_t cc = cidx(m, c);
+  int r = cube_r(m, cc);
+  if (r == 1) return cc;
+  return n_cubes(m) + m->sub_off[cc] + ((int64_t)f[2] * r + f[1]) * r + f[0];
+}
+
+static double leaf_rho(const orc_model *m, int64_t leaf) {
+  int64_t nc = n_cubes(m);
+  return leaf < nc ? m->rho[leaf] : m->rho_sub[leaf - nc];
+}
+
+/* position of face e (0..r) of the sub-cubes of cube coordinate ck on axis
+ * k: the cube's own faces are written as for a whole cube, so a walk leaves
+ * a divided cube exactly where the coarse grid puts that face */
+static double face_pos(const orc_model *m, int k, int ck, int r, int e) {
+  if (e == 0) return m->origin[k] + (double)ck * m->dcell;
+  if (e == r) return m->origin[k] + (double)(ck + 1) * m->dcell;
+  return m->origin[k] + (double)ck * m->dcell + (double)e * (m->dcell / (double)r);
+}
+
+/* sub-cube index on axis k of point x inside cube coordinate ck (a point on
+ * a face belongs to the sub-cube d points into), clamped to the cube */
+static int sub_index(const orc_model *m, int k, int ck, int r, double x, double dk) {
+  if (r == 1) return 0;
+  double q = (x - m->origin[k] - (double)ck * m->dcell) / (m->dcell / (double)r);
+  double fl = floor(q);
+  int fi = (int)fl;
+  if (q == fl && dk < 0.0) fi -= 1;
+  if (fi < 0) fi = 0;
+  if (fi > r - 1) fi = r - 1;
+  return fi;
+}
+
+/* cube c, sub-cube f and sub-cubes per edge r of a leaf */
+static void leaf_loc(const orc_model *m, int64_t leaf, int c[3], int f[3], int *r_out) {
+  int64_t nc = n_cubes(m);
+  int64_t cc = leaf;
+  int r = 1;
+  f[0] = f[1] = f[2] = 0;
+  if (leaf >= nc) {
+    /* sub_off is the exclusive prefix sum of r^3 over the divided cubes, so
+     * the cube holding sub-cube s is the last cube with sub_off <= s */
+    int64_t s = leaf - nc, lo = 0, hi = nc - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) / 2;
+      if (m->sub_off[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    cc = lo;
+    r = cube_r(m, cc);
+    int64_t loc = s - m->sub_off[cc];
+    f[0] = (int)(loc % r);
+    f[1] = (int)((loc / r) % r);
+    f[2] = (int)(loc / ((int64_t)r * r));
+  }
+  c[0] = (int)(cc % m->nx);
+  c[1] = (int)((cc / m->nx) % m->ny);
+  c[2] = (int)(cc / ((int64_t)m->nx * m->ny));
+  *r_out = r;
+}
+
+void orc_leaf_box(const orc_model *m, int64_t leaf, double lo[3], double *h, double *rho) {
+  int c[3], f[3], r;
+  leaf_loc(m, leaf, c, f, &r);
+  for (int k = 0; k < 3; k++) lo[k] = face_pos(m, k, c[k], r, f[k]);
+  *h = (r == 1) ? m->dcell : m->dcell / (double)r;
+  *rho = leaf_rho(m, leaf);
+}
+
+/* A voxel walk through the leaves along p0 + t d (Amanatides & Woo on each
+ * cube's own lattice): tm[k] is the distance to the current leaf's next face
+ * on axis k; leaving a divided cube continues on the next cube's lattice.
+ * Whole cubes take the same arithmetic as an undivided grid. */
+typedef struct {
+  const orc_model *m;
+  const double *p0, *d;
+  int c[3], f[3], r;
+  double tm[3];
+} walker_t;
+
+static void walker_faces(walker_t *W) {
+  for (int k = 0; k < 3; k++) {
+    double dk = W->d[k];
+    if (dk > 0.0) W->tm[k] = (face_pos(W->m, k, W->c[k], W->r, W->f[k] + 1) - W->p0[k]) / dk;
+    else if (dk < 0.0) W->tm[k] = (face_pos(W->m, k, W->c[k], W->r, W->f[k]) - W->p0[k]) / dk;
+    else W->tm[k] = INFINITY;
+  }
+}
+
+/* enter cube W->c at distance t (entry axis a, or -1 inside a flight start)
+ * with sub-cube indices from the position (f given: used as is) */
+static void walker_enter(walker_t *W, double t, int a, const int *f) {
+  W->r = cube_r(W->m, cidx(W->m, W->c));
+  for (int k = 0; k < 3; k++) {
+    if (f) W->f[k] = f[k];
+    else if (k == a) W->f[k] = (W->d[k] > 0.0) ? 0 : W->r - 1;
+    else W->f[k] = sub_index(W->m, k, W->c[k], W->r, W->p0[k] + t * W->d[k], W->d[k]);
+  }
+  walker_faces(W);
+}
+
+static int64_t walker_leaf(const walker_t *W) { return leaf_id(W->m, W->c, W->f); }
+
+/* step across the face on axis a reached at distance t: 1 when the walk
+ * leaves the grid */
+static int walker_cross(walker_t *W, int a, double t) {
+  const orc_model *m = W->m;
+  int s = (W->d[a] > 0.0) ? 1 : -1;
+  W->f[a] += s;
+  if (W->f[a] >= 0 && W->f[a] < W->r) {
+    double dk = W->d[a];
+    W->tm[a] = (face_pos(m, a, W->c[a], W->r, dk > 0.0 ? W->f[a] + 1 : W->f[a]) - W->p0[a]) / dk;
+    return 0;
+  }
+  W->c[a] += s;
+  int n[3] = {m->nx, m->ny, m->nz};
+  if (W->c[a] < 0 || W->c[a] >= n[a]) return 1;
+  walker_enter(W, t, a, NULL);
+  return 0;
+}
+
 /* Amanatides & Woo stepping: the smallest exit time wins, ties step the
  * lowest axis first (x < y < z); segment lengths are never negative. */
 int orc_dda(const orc_model *m, const double p0[3], const double d[3], int maxseg,
             int64_t *cells, double *lens) {
-  int c[3];
-  start_cell(m, p0, d, c);
+  walker_t W = {m, p0, d, {0, 0, 0}, {0, 0, 0}, 1, {0, 0, 0}};
+  start_cell(m, p0, d, W.c);
   int nseg = 0;
-  if (!inside(m, c)) return 0;
-  double tm[3];
-  for (int k = 0; k < 3; k++) tm[k] = plane_t(m, p0, d, c, k);
+  if (!inside(m, W.c)) return 0;
+  walker_enter(&W, 0.0, -1, NULL);
   double t = 0.0;
-  int n[3] = {m->nx, m->ny, m->nz};
   for (;;) {
     int a = 0;
-    if (tm[1] < tm[a]) a = 1;
-    if (tm[2] < tm[a]) a = 2;
-    double ell = tm[a] - t;
+    if (W.tm[1] < W.tm[a]) a = 1;
+    if (W.tm[2] < W.tm[a]) a = 2;
+    double ell = W.tm[a] - t;
     if (ell < 0.0) ell = 0.0;
     if (nseg >= maxseg) return -1;
-    cells[nseg] = cidx(m, c);
+    cells[nseg] = walker_leaf(&W);
     lens[nseg] = ell;
     nseg++;
-    t = tm[a] > t ? tm[a] : t;
-    c[a] += (d[a] > 0.0) ? 1 : -1;
-    if (c[a] < 0 || c[a] >= n[a]) return nseg;
-    tm[a] = plane_t(m, p0, d, c, a);
+    t = W.tm[a] > t ? W.tm[a] : t;
+    if (walker_cross(&W, a, t)) return nseg;
   }
 }
 
@@ -540,15 +671,29 @@ typedef struct {
 
 typedef struct {
   double p[3], d[3];
-  int c[3];
+  int c[3];   /* cube */
+  int f[3];   /* sub-cube of a divided cube (0 in a whole cube) */
   int j, status;
   uint64_t n_cross, n_scat, n_abs, n_mrw, n_lucy, n_int;
   double mm;
 } pkt_t;
 
-static int is_thin(const run_t *R, double rho) {
-  return R->o->lucy_tau > 0.0 && rho > 0.0 &&
-         rho * R->t.kext_max * R->m->dcell < R->o->lucy_tau;
+/* Lucy's thin-cell test on the cell's face-to-face depth (edge h) */
+static int is_thin(const run_t *R, double rho, double h) {
+  return R->o->lucy_tau > 0.0 && rho > 0.0 && rho * R->t.kext_max * h < R->o->lucy_tau;
+}
+
+/* edge and volume of the leaf of packet P */
+static double pkt_h(const run_t *R, const pkt_t *P) {
+  int r = cube_r(R->m, cidx(R->m, P->c));
+  return r == 1 ? R->m->dcell : R->m->dcell / (double)r;
+}
+
+static double leaf_V(const run_t *R, int64_t leaf) {
+  if (leaf < n_cubes(R->m)) return R->t.V;
+  double lo[3], h, rho;
+  orc_leaf_box(R->m, leaf, lo, &h, &rho);
+  return h * h * h;
 }
 
 static void touch(run_t *R, int64_t q) {
@@ -574,8 +719,8 @@ static double mode_T(run_t *R, int s, int64_t c) {
     return (T > 0.0) ? T : T_FLOOR;
   }
   if (!R->st->tvalid[q]) {
-    double rho = R->m->rho[c];
-    double rhs = (R->st->esnap[q] + R->xi) / (4.0 * PI_D * R->m->mass_frac[s] * rho * R->t.V);
+    double rho = leaf_rho(R->m, c);
+    double rhs = (R->st->esnap[q] + R->xi) / (4.0 * PI_D * R->m->mass_frac[s] * rho * leaf_V(R, c));
     int cl = 0;
     R->st->tt[q] = invert_t(&R->t, s, rhs, &cl);
     if (cl) R->st->st.clamped_T++;
@@ -609,30 +754,29 @@ static void lucy_deposit(run_t *R, pkt_t *P, int64_t c, double rho, double ell) 
 static int fly(run_t *R, pkt_t *P, double tau_star, rng_t *rg) {
   const int per_cell = R->o->tau_mode == ORC_TAU_PER_CELL;
   const orc_model *m = R->m;
-  int n[3] = {m->nx, m->ny, m->nz};
   double p0[3] = {P->p[0], P->p[1], P->p[2]};
   const double *d = P->d;
-  double tm[3];
-  for (int k = 0; k < 3; k++) tm[k] = plane_t(m, p0, d, P->c, k);
+  walker_t W = {m, p0, d, {P->c[0], P->c[1], P->c[2]}, {0, 0, 0}, 1, {0, 0, 0}};
+  walker_enter(&W, 0.0, -1, P->f);
   double t = 0.0, tau = 0.0;
   double kx = R->t.kext[P->j];
   for (;;) {
     int a = 0;
-    if (tm[1] < tm[a]) a = 1;
-    if (tm[2] < tm[a]) a = 2;
+    if (W.tm[1] < W.tm[a]) a = 1;
+    if (W.tm[2] < W.tm[a]) a = 2;
     {
       /* distance of the axis choice from a tie */
-      double t1 = tm[a], t2 = INFINITY;
+      double t1 = W.tm[a], t2 = INFINITY;
       for (int k = 0; k < 3; k++)
-        if (k != a && tm[k] < t2) t2 = tm[k];
+        if (k != a && W.tm[k] < t2) t2 = W.tm[k];
       if (isfinite(t2) && t2 > 0.0) upd_margin(&P->mm, (t2 - t1) / t2);
     }
-    double ell = tm[a] - t;
+    double ell = W.tm[a] - t;
     if (ell < 0.0) ell = 0.0;
-    int64_t c = cidx(m, P->c);
-    double rho = m->rho[c];
+    int64_t c = walker_leaf(&W);
+    double rho = leaf_rho(m, c);
     double dtau = rho * kx * ell;
-    int thin = is_thin(R, rho);
+    int thin = is_thin(R, rho, W.r == 1 ? m->dcell : m->dcell / (double)W.r);
     if (per_cell) {
       tau = 0.0;
       tau_star = -log(rng_next(rg));
@@ -641,19 +785,24 @@ static int fly(run_t *R, pkt_t *P, double tau_star, rng_t *rg) {
     if (tau + dtau > tau_star) {
       double tint = t + (tau_star - tau) / (rho * kx);
       if (thin) lucy_deposit(R, P, c, rho, tint - t);
-      for (int k = 0; k < 3; k++) P->p[k] = p0[k] + tint * d[k];
+      for (int k = 0; k < 3; k++) {
+        P->p[k] = p0[k] + tint * d[k];
+        P->c[k] = W.c[k];
+        P->f[k] = W.f[k];
+      }
       return 0;
     }
     if (thin) lucy_deposit(R, P, c, rho, ell);
     tau += dtau;
-    if (tm[a] > t) t = tm[a];
-    P->c[a] += (d[a] > 0.0) ? 1 : -1;
+    if (W.tm[a] > t) t = W.tm[a];
     P->n_cross++;
-    if (P->c[a] < 0 || P->c[a] >= n[a]) {
-      for (int k = 0; k < 3; k++) P->p[k] = p0[k] + t * d[k];
+    if (walker_cross(&W, a, t)) {
+      for (int k = 0; k < 3; k++) {
+        P->p[k] = p0[k] + t * d[k];
+        P->c[k] = W.c[k];
+      }
       return 1;
     }
-    tm[a] = plane_t(m, p0, d, P->c, a);
   }
 }
 
@@ -720,20 +869,23 @@ static int first_thermal(const run_t *R) {
 static int mrw_step(run_t *R, pkt_t *P, rng_t *rg) {
   const orc_model *m = R->m;
   if (!(R->o->mrw_tau > 0.0)) return 0;
-  int64_t c = cidx(m, P->c);
-  double rho = m->rho[c];
+  int64_t c = leaf_id(m, P->c, P->f);
+  double rho = leaf_rho(m, c);
+  const int r = cube_r(m, cidx(m, P->c));
+  const double h = r == 1 ? m->dcell : m->dcell / (double)r;
   if (!(rho > 0.0)) return 0;
-  if (!(rho * R->t.kext_max * m->dcell > R->o->mrw_tau)) return 0;
+  if (!(rho * R->t.kext_max * h > R->o->mrw_tau)) return 0;
   int s0 = first_thermal(R);
   double T0 = mode_T(R, s0, c);
   double kr = rosseland(R, T0);
-  double taur = rho * kr * m->dcell;
+  double taur = rho * kr * h;
   upd_margin(&P->mm, fabs(taur - R->o->mrw_tau) / R->o->mrw_tau);
   if (!(taur > R->o->mrw_tau)) return 0;
+  /* sphere radius: distance to the nearest face of the packet's cell */
   double Rs = INFINITY;
   for (int k = 0; k < 3; k++) {
-    double lo = P->p[k] - (m->origin[k] + (double)P->c[k] * m->dcell);
-    double hi = (m->origin[k] + (double)(P->c[k] + 1) * m->dcell) - P->p[k];
+    double lo = P->p[k] - face_pos(m, k, P->c[k], r, P->f[k]);
+    double hi = face_pos(m, k, P->c[k], r, P->f[k] + 1) - P->p[k];
     if (lo < Rs) Rs = lo;
     if (hi < Rs) Rs = hi;
   }
@@ -768,9 +920,9 @@ static int mrw_step(run_t *R, pkt_t *P, rng_t *rg) {
 
 static int pah_row(const run_t *R, int64_t c) {
   const orc_model *m = R->m;
-  double rho = m->rho[c];
+  double rho = leaf_rho(m, c);
   double q = (double)R->st->kpah[c] * R->xi /
-             (4.0 * PI_D * m->mass_frac[m->pah_species] * rho * R->t.V);
+             (4.0 * PI_D * m->mass_frac[m->pah_species] * rho * leaf_V(R, c));
   int r = 0;
   while (r < m->n_pah_rows - 1 && q >= m->pah_edges[r]) r++;
   return r;
@@ -786,7 +938,7 @@ static int pah_row(const run_t *R, int64_t c) {
 static int pah_dissociates_xi(const orc_model *m, const orc_opts *o, double xi, double V,
                               uint32_t kpah, int64_t c) {
   if (!(o->pah_nc > 0.0) || !(o->pah_tcool > 0.0) || kpah == 0) return 0;
-  double rho = m->rho[c];
+  double rho = leaf_rho(m, c);
   double mp = o->pah_nc * 12.0 * AMU_G;
   double e = (double)kpah * xi * mp * o->pah_tcool / (m->mass_frac[m->pah_species] * rho * V);
   return e >= 0.5 * o->pah_nc * EV_ERG;
@@ -795,7 +947,9 @@ static int pah_dissociates_xi(const orc_model *m, const orc_opts *o, double xi, 
 int orc_pah_dissociates(const orc_model *m, const orc_opts *o, uint32_t kpah, int64_t c) {
   double ltot = 0.0;
   for (int s = 0; s < m->nsrc; s++) ltot += m->src_lum[s];
-  double V = m->dcell * m->dcell * m->dcell;
+  double lo[3], h, rho;
+  orc_leaf_box(m, c, lo, &h, &rho);
+  double V = (c < n_cubes(m)) ? m->dcell * m->dcell * m->dcell : h * h * h;
   return pah_dissociates_xi(m, o, ltot / (double)o->n_total, V, kpah, c);
 }
 
@@ -851,15 +1005,24 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
   memset(&P, 0, sizeof(P));
   P.mm = INFINITY;
   R->st->st.packets++;
-  if (R->pass == 2 && !pah_dissociates_xi(m, R->o, R->xi, t->V, R->st->kpah[pcell], pcell)) {
+  if (R->pass == 2 &&
+      !pah_dissociates_xi(m, R->o, R->xi, leaf_V(R, pcell), R->st->kpah[pcell], pcell)) {
     int64_t c = pcell;
-    int cc[3] = {(int)(c % m->nx), (int)((c / m->nx) % m->ny), (int)(c / ((int64_t)m->nx * m->ny))};
     double ux = rng_next(&rg), uy = rng_next(&rg), uz = rng_next(&rg);
     double ul = rng_next(&rg), uph = rng_next(&rg), umu = rng_next(&rg);
     double uu[3] = {ux, uy, uz};
-    for (int k = 0; k < 3; k++) {
-      P.c[k] = cc[k];
-      P.p[k] = m->origin[k] + ((double)cc[k] + uu[k]) * m->dcell;
+    if (c < n_cubes(m)) {
+      int cc[3] = {(int)(c % m->nx), (int)((c / m->nx) % m->ny), (int)(c / ((int64_t)m->nx * m->ny))};
+      for (int k = 0; k < 3; k++) {
+        P.c[k] = cc[k];
+        P.p[k] = m->origin[k] + ((double)cc[k] + uu[k]) * m->dcell;
+      }
+    } else {
+      /* a sub-cube: uniform inside it */
+      int r;
+      leaf_loc(m, c, P.c, P.f, &r);
+      double h = m->dcell / (double)r;
+      for (int k = 0; k < 3; k++) P.p[k] = face_pos(m, k, P.c[k], r, P.f[k]) + uu[k] * h;
     }
     P.j = pick_pah_lambda(R, pah_row(R, c), ul, &P.mm);
     iso_dir(uph, umu, P.d);
@@ -881,6 +1044,8 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
       finish(R, &P, pid, slot);
       return;
     }
+    int r = cube_r(m, cidx(m, P.c));
+    for (int k = 0; k < 3; k++) P.f[k] = sub_index(m, k, P.c[k], r, P.p[k], P.d[k]);
   }
   for (;;) {
     while (mrw_step(R, &P, &rg)) {
@@ -897,7 +1062,7 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
       finish(R, &P, pid, slot);
       return;
     }
-    int64_t c = cidx(m, P.c);
+    int64_t c = leaf_id(m, P.c, P.f);
     double ualb = rng_next(&rg), usp = rng_next(&rg);
     int j = P.j;
     upd_margin(&P.mm, fabs(ualb - t->alb[j]));
@@ -947,7 +1112,7 @@ static void run_packet(run_t *R, uint64_t pid, int64_t pcell, uint64_t slot) {
         P.j = pick_pah_lambda(R, pah_row(R, c), ul, &P.mm);
         iso_dir(uph, umu, P.d);
       } else {
-        if (!is_thin(R, m->rho[c])) {
+        if (!is_thin(R, leaf_rho(m, c), pkt_h(R, &P))) {
           R->st->k[(int64_t)s * t->ncell + c] += 1;
           touch(R, (int64_t)s * t->ncell + c);
         }
@@ -1043,10 +1208,10 @@ void orc_finalize_T(const orc_model *m, const orc_opts *o, orc_state *st) {
   int64_t nc = R.t.ncell;
   for (int s = 0; s < R.t.ns; s++)
     for (int64_t c = 0; c < nc; c++) {
-      double rho = m->rho[c];
+      double rho = leaf_rho(m, c);
       double T = 0.0;
       if (s != m->pah_species && rho > 0.0 && m->mass_frac[s] > 0.0) {
-        double rhs = e_cell(&R, s, c) / (4.0 * PI_D * m->mass_frac[s] * rho * R.t.V);
+        double rhs = e_cell(&R, s, c) / (4.0 * PI_D * m->mass_frac[s] * rho * leaf_V(&R, c));
         int cl = 0;
         T = invert_t(&R.t, s, rhs, &cl);
         if (cl) st->st.clamped_T++;
@@ -1113,9 +1278,15 @@ void orc_init_T(const orc_model *m, double *T) {
   double *J = malloc(sizeof(double) * nl);
   double *f = malloc(sizeof(double) * nl);
   for (int64_t c = 0; c < t.ncell; c++) {
-    int cc[3] = {(int)(c % m->nx), (int)((c / m->nx) % m->ny), (int)(c / ((int64_t)m->nx * m->ny))};
     double x[3];
-    for (int k = 0; k < 3; k++) x[k] = m->origin[k] + ((double)cc[k] + 0.5) * m->dcell;
+    if (c < n_cubes(m)) {
+      int cc[3] = {(int)(c % m->nx), (int)((c / m->nx) % m->ny), (int)(c / ((int64_t)m->nx * m->ny))};
+      for (int k = 0; k < 3; k++) x[k] = m->origin[k] + ((double)cc[k] + 0.5) * m->dcell;
+    } else {
+      double lo[3], h, rho;
+      orc_leaf_box(m, c, lo, &h, &rho);
+      for (int k = 0; k < 3; k++) x[k] = lo[k] + 0.5 * h;
+    }
     for (int j = 0; j < nl; j++) J[j] = 0.0;
     for (int s = 0; s < m->nsrc; s++) {
       double dx = x[0] - m->src_pos[3 * s], dy = x[1] - m->src_pos[3 * s + 1],
@@ -1125,7 +1296,7 @@ void orc_init_T(const orc_model *m, double *T) {
     }
     for (int s = 0; s < m->ns; s++) {
       double Tv = 0.0;
-      if (s != m->pah_species && m->rho[c] > 0.0) {
+      if (s != m->pah_species && leaf_rho(m, c) > 0.0) {
         for (int j = 0; j < nl; j++) f[j] = t.w[j] * m->kabs[s * nl + j] * J[j];
         Tv = invert_t(&t, s, sum_desc(f, nl), NULL);
       }
@@ -1194,31 +1365,37 @@ static int ray_entry(const orc_model *m, const view_t *vw, int ix, int iy, doubl
   return 1;
 }
 
-/* Walk the segments of a ray from p0 in cell c: returns the count, fills
- * cells/lens (sized for the longest walk, nx+ny+nz+3). */
+/* Walk the segments of a ray from p0 in cube c (sub-cube from the
+ * position): returns the count, fills leaves/lens (sized by max_segs). */
 static int walk(const orc_model *m, const double p0[3], const double d[3], int c0[3],
                 int64_t *cells, double *lens) {
-  int c[3] = {c0[0], c0[1], c0[2]};
-  int n[3] = {m->nx, m->ny, m->nz};
-  if (!inside(m, c)) return 0;
-  double tm[3];
-  for (int k = 0; k < 3; k++) tm[k] = plane_t(m, p0, d, c, k);
+  walker_t W = {m, p0, d, {c0[0], c0[1], c0[2]}, {0, 0, 0}, 1, {0, 0, 0}};
+  if (!inside(m, W.c)) return 0;
+  walker_enter(&W, 0.0, -1, NULL);
   double t = 0.0;
   int ns = 0;
   for (;;) {
     int a = 0;
-    if (tm[1] < tm[a]) a = 1;
-    if (tm[2] < tm[a]) a = 2;
-    double ell = tm[a] - t;
+    if (W.tm[1] < W.tm[a]) a = 1;
+    if (W.tm[2] < W.tm[a]) a = 2;
+    double ell = W.tm[a] - t;
     if (ell < 0.0) ell = 0.0;
-    cells[ns] = cidx(m, c);
+    cells[ns] = walker_leaf(&W);
     lens[ns] = ell;
     ns++;
-    if (tm[a] > t) t = tm[a];
-    c[a] += (d[a] > 0.0) ? 1 : -1;
-    if (c[a] < 0 || c[a] >= n[a]) return ns;
-    tm[a] = plane_t(m, p0, d, c, a);
+    if (W.tm[a] > t) t = W.tm[a];
+    if (walker_cross(&W, a, t)) return ns;
   }
+}
+
+/* most segments a straight walk can have: each cube it enters adds at most
+ * 3 r - 2 sub-cube segments */
+static int max_segs(const orc_model *m) {
+  int rmax = 1;
+  if (m->ref)
+    for (int64_t c = 0; c < n_cubes(m); c++)
+      if (cube_r(m, c) > rmax) rmax = cube_r(m, c);
+  return (m->nx + m->ny + m->nz + 3) * 3 * rmax;
 }
 
 /* Source function per imaged wavelength (sect. 4, Eqs. 14 and 16 read as
@@ -1234,9 +1411,11 @@ static double source_fn(const tab_t *t, const orc_model *m, const double *T,
     em += m->mass_frac[s] * m->kabs[s * nl + j] * orc_planck(t->nu[j], T[(int64_t)s * t->ncell + c]);
   }
   double S = em / t->kext[j];
-  double rho = m->rho[c];
+  double lo[3], h, rho;
+  orc_leaf_box(m, c, lo, &h, &rho);
+  double V = (c < n_cubes(m)) ? t->V : h * h * h;
   if (ssca && rho > 0.0)
-    S += ssca[((int64_t)v * m->nimg + q) * t->ncell + c] / (t->V * t->w[j] * rho * t->kext[j]);
+    S += ssca[((int64_t)v * m->nimg + q) * t->ncell + c] / (V * t->w[j] * rho * t->kext[j]);
   return S;
 }
 
@@ -1257,7 +1436,8 @@ static double kabs_all(const tab_t *t, const orc_model *m, int j) {
 static double cell_literal(const tab_t *t, const orc_model *m, const double *T,
                            const double *ssca, int v, int q, int64_t c) {
   int j = m->img_idx[q], nl = t->nl;
-  double rho = m->rho[c];
+  double lo[3], h, rho;
+  orc_leaf_box(m, c, lo, &h, &rho);
   if (!(rho > 0.0)) return 0.0;
   double ka = kabs_all(t, m, j);
   double em = 0.0;
@@ -1265,18 +1445,25 @@ static double cell_literal(const tab_t *t, const orc_model *m, const double *T,
     if (s == m->pah_species) continue;
     em += m->mass_frac[s] * m->kabs[s * nl + j] * orc_planck(t->nu[j], T[(int64_t)s * t->ncell + c]);
   }
-  double I = (ka > 0.0) ? -expm1(-(rho * ka * m->dcell)) * (em / ka) : 0.0;
-  if (ssca) I += ssca[((int64_t)v * m->nimg + q) * t->ncell + c] / (t->w[j] * m->dcell * m->dcell);
+  double I = (ka > 0.0) ? -expm1(-(rho * ka * h)) * (em / ka) : 0.0;
+  if (ssca) I += ssca[((int64_t)v * m->nimg + q) * t->ncell + c] / (t->w[j] * h * h);
   return I;
 }
 
 int orc_raytrace(const orc_model *m, int rt_mode, const double *T, const double *ssca,
                  const double *rho_rt, int npx, int npy, double *img, double *sed) {
   const int lit = rt_mode == ORC_RT_ABS_LITERAL;
-  if (!rho_rt) rho_rt = m->rho;
+  double *rho_leaf = NULL;
+  if (!rho_rt) {
+    /* the model's density of every leaf */
+    int64_t nlf = orc_nleaf(m);
+    rho_leaf = malloc(sizeof(double) * nlf);
+    for (int64_t c = 0; c < nlf; c++) rho_leaf[c] = leaf_rho(m, c);
+    rho_rt = rho_leaf;
+  }
   tab_t t;
   tab_init(&t, m);
-  int maxs = m->nx + m->ny + m->nz + 3;
+  int maxs = max_segs(m);
   int64_t *cells = malloc(sizeof(int64_t) * maxs);
   double *lens = malloc(sizeof(double) * maxs);
   double D2 = m->distance * m->distance;
@@ -1337,6 +1524,7 @@ int orc_raytrace(const orc_model *m, int rt_mode, const double *T, const double 
   }
   free(cells);
   free(lens);
+  free(rho_leaf);
   tab_free(&t);
   return 0;
 }
@@ -1353,10 +1541,17 @@ int orc_raytrace_adjoint(const orc_model *m, int rt_mode, const double *T, const
    * dI/d(dtau_i) = -(I - A_i) with A_i the intensity gathered up to and
    * including cell i */
   const int lit = rt_mode == ORC_RT_ABS_LITERAL;
-  if (!rho_rt) rho_rt = m->rho;
+  double *rho_leaf = NULL;
+  if (!rho_rt) {
+    /* the model's density of every leaf */
+    int64_t nlf = orc_nleaf(m);
+    rho_leaf = malloc(sizeof(double) * nlf);
+    for (int64_t c = 0; c < nlf; c++) rho_leaf[c] = leaf_rho(m, c);
+    rho_rt = rho_leaf;
+  }
   tab_t t;
   tab_init(&t, m);
-  int maxs = m->nx + m->ny + m->nz + 3;
+  int maxs = max_segs(m);
   int64_t *cells = malloc(sizeof(int64_t) * maxs);
   double *lens = malloc(sizeof(double) * maxs);
   double D2 = m->distance * m->distance;
@@ -1441,6 +1636,7 @@ int orc_raytrace_adjoint(const orc_model *m, int rt_mode, const double *T, const
   }
   free(cells);
   free(lens);
+  free(rho_leaf);
   tab_free(&t);
   return 0;
 }

@@ -50,6 +50,18 @@ typedef struct {
   const double *view_deg;        /* [nview][2] (theta, phi) */
   const int32_t *img_idx;        /* [nimg] */
   double distance;               /* cm */
+  /* one level of refinement (sect. 2: cubes divided into sub-cubes of their
+   * own density): ref[cube] = r >= 2 divides the cube into r^3 sub-cubes of
+   * edge dcell / r whose densities start at rho_sub[sub_off[cube]], x fastest
+   * inside the cube; 0 or 1 leaves it whole; sub_off is the exclusive prefix
+   * sum over the cubes of r^3 (0 for whole cubes). ref NULL: no refinement. Leaf
+   * cells (whole cubes, sub-cubes) are numbered cube index for a whole cube,
+   * n_cubes + sub_off[cube] + local index for a sub-cube; every per-cell
+   * array (tallies, temperatures, scattering sums) runs over the leaves. */
+  const uint8_t *ref;
+  const int64_t *sub_off;
+  const double *rho_sub;
+  int64_t nsub;
 } orc_model;
 
 typedef struct {
@@ -136,9 +148,15 @@ void orc_ylm(int lmax, const double d[3], double *y);
 void orc_sh_view_sums(const orc_model *m, int sh_order, const double *sh, const double k[3],
                       double *out);
 
-/* Voxel walk from p0 along d starting in cell c (face rule applied by the
- * caller or by passing c[0] < 0). Writes up to maxseg (cell, length) pairs;
- * returns the number of segments, or -1 if maxseg was too small. */
+/* Leaf cells of the model (cubes plus sub-cubes) */
+int64_t orc_nleaf(const orc_model *m);
+/* Leaf geometry: lower corner, edge and density of leaf `leaf`. */
+void orc_leaf_box(const orc_model *m, int64_t leaf, double lo[3], double *h, double *rho);
+
+/* Voxel walk from p0 along d through the leaf cells, starting in the leaf
+ * that holds p0 (a point on a face belongs to the leaf that d points into).
+ * Writes up to maxseg (leaf, length) pairs; returns the number of segments,
+ * or -1 if maxseg was too small. */
 int orc_dda(const orc_model *m, const double p0[3], const double d[3],
             int maxseg, int64_t *cells, double *lens);
 

@@ -55,7 +55,8 @@ class Model(C.Structure):
         ("pah_edges", _dp), ("nsrc", C.c_int32), ("scat_law", C.c_int32), ("src_pos", _dp),
         ("src_lum", _dp), ("src_shape", _dp), ("src_tbb", _dp),
         ("nview", C.c_int32), ("nimg", C.c_int32), ("view_deg", _dp), ("img_idx", _ip),
-        ("distance", C.c_double),
+        ("distance", C.c_double), ("ref", C.POINTER(C.c_uint8)),
+        ("sub_off", C.POINTER(C.c_int64)), ("rho_sub", _dp), ("nsub", C.c_int64),
     ]
 
 
@@ -133,6 +134,9 @@ def lib():
         L.orc_planck_mean.restype = C.c_double
         L.orc_dda.argtypes = [C.POINTER(Model), _dp, _dp, C.c_int, C.POINTER(C.c_int64), _dp]
         L.orc_init_T.argtypes = [C.POINTER(Model), _dp]
+        L.orc_nleaf.argtypes = [C.POINTER(Model)]
+        L.orc_nleaf.restype = C.c_int64
+        L.orc_leaf_box.argtypes = [C.POINTER(Model), C.c_int64, _dp, _dp, _dp]
         L.orc_ylm.argtypes = [C.c_int, _dp, _dp]
         L.orc_sh_view_sums.argtypes = [C.POINTER(Model), C.c_int, _dp, _dp, _dp]
         L.orc_pah_dissociates.argtypes = [C.POINTER(Model), C.POINTER(Opts), C.c_uint32,
@@ -295,12 +299,27 @@ class Oracle:
         m.img_idx = _p(self.img_idx, C.c_int32)
         m.distance = float(distance)
         m.scat_law = scat_law
+        self.ref = self.sub_off = self.rho_sub = None
+        if getattr(mi, "ref", None) is not None:
+            self.ref = np.ascontiguousarray(mi.ref, dtype=np.uint8).ravel()
+            r = self.ref.astype(np.int64)
+            n = np.where(r >= 2, r**3, 0)
+            self.sub_off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(n)[:-1]]),
+                                                dtype=np.int64)
+            self.rho_sub = _f64(mi.rho_sub)
+            assert self.rho_sub.size == int(n.sum())
+            m.ref = _p(self.ref, C.c_uint8)
+            m.sub_off = _p(self.sub_off, C.c_int64)
+            m.rho_sub = _p(self.rho_sub)
+            m.nsub = self.rho_sub.size
         self.m = m
         self.reset()
 
     @property
     def ncells(self):
-        return self.mi.nx * self.mi.ny * self.mi.nz
+        """Leaf cells: cubes plus sub-cubes."""
+        return self.mi.nx * self.mi.ny * self.mi.nz + (0 if self.rho_sub is None
+                                                        else self.rho_sub.size)
 
     def reset(self):
         nc, ns, nl = self.ncells, self.frac.size, self.lam.size
@@ -403,6 +422,13 @@ class Oracle:
         lib().orc_sh_view_sums(C.byref(self.m), int(round(np.sqrt(sh.shape[1]))), _p(sh),
                                _p(_f64(k)), _p(out))
         return out
+
+    def leaf_box(self, leaf):
+        """(lower corner, edge, density) of a leaf cell."""
+        lo = np.zeros(3)
+        h, r = np.zeros(1), np.zeros(1)
+        lib().orc_leaf_box(C.byref(self.m), int(leaf), _p(lo), _p(h), _p(r))
+        return lo, float(h[0]), float(r[0])
 
     def pah_dissociates(self, kpah=None, **kw):
         """Eq. 8 decision per cell for the given pass-1 PAH counts."""
