@@ -219,6 +219,20 @@ mcrt_status mcrt_packet_records(mcrt_ctx *ctx, mcrt_packet_record *out, uint64_t
  * dtau only; S keeps the grid's values (emissivity per unit mass fixed). */
 mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt,
                                 void *img_out, double *sed_out, int mem, void *stream);
+/* mcrt_raytrace_image for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with img_out
+ * [views][n_img][npy][npx] (context precision) and sed_out [views][n_img]
+ * (FP64, nullable) in device memory only. The source functions go to a
+ * static device array of 64 MiB per GPU (held until the process ends), so
+ * views * cells * n_img * (4 FP32 | 8 FP64) bytes must fit: EINVAL beyond.
+ * ESTATE unless the context's tallies and scattering sums for the current
+ * views already exist (after mcrt_reset, a run, or mcrt_set_temperatures
+ * with views set). Calls no allocating routine. Every call on one GPU
+ * shares its array: calls that overlap on one GPU (several streams or
+ * threads) race and must be serialised by the caller. */
+mcrt_status mcrt_raytrace_image_noalloc(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt,
+                                        void *img_out, double *sed_out, void *stream);
 /* Adjoint of mcrt_raytrace_image: given dL/dimg (context precision,
  * nullable) and dL/dsed (FP64, nullable), writes dL/drho_rt [cells]
  * (context precision). Transmittance is recomputed in a second front-to-

@@ -80,6 +80,7 @@ SIGNATURES = {
     "mcrt_scattering": (C.c_int, [_ctxp, _vp, C.c_int, _vp]),
     "mcrt_packet_records": (C.c_int, [_ctxp, _vp, C.c_uint64, C.c_int]),
     "mcrt_raytrace_image": (C.c_int, [_ctxp, C.c_int, C.c_int, _vp, _vp, _vp, C.c_int, _vp]),
+    "mcrt_raytrace_image_noalloc": (C.c_int, [_ctxp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "mcrt_raytrace_adjoint": (C.c_int, [_ctxp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, C.c_int,
                                         _vp]),
     "mcrt_run_batch": (C.c_int, [C.POINTER(_ctxp), C.c_int, C.POINTER(C.c_uint64),

@@ -291,6 +291,14 @@ class Context:
                                                _stream(None)))
         return img, sed
 
+    def raytrace_noalloc(self, npx, npy, img, sed=None, rho_rt=None):
+        """mcrt_raytrace_image_noalloc into caller-owned device tensors."""
+        rr = None if rho_rt is None else C.c_void_p(rho_rt.data_ptr())
+        self._chk(self.lib.mcrt_raytrace_image_noalloc(
+            self.h, npx, npy, rr, C.c_void_p(img.data_ptr()),
+            None if sed is None else C.c_void_p(sed.data_ptr()), _stream(None)))
+        return img, sed
+
     def raytrace_adjoint_device(self, npx, npy, w_img=None, w_sed=None, rho_rt=None, out=None):
         import torch
         dt = torch.float64 if self.fp64 else torch.float32

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -213,6 +214,7 @@ static hipError_t stage_copy(mcrt_ctx *ctx, void *dst, const void *src, size_t b
 }
 
 static const size_t STAGE_BYTES = 1 << 20;
+static hipError_t scratch_init(int device);
 
 extern "C" mcrt_status mcrt_create(mcrt_ctx **out, int device, int precision) {
   mcrt_ctx *ctx = nullptr;
@@ -249,6 +251,10 @@ extern "C" mcrt_status mcrt_create(mcrt_ctx **out, int device, int precision) {
     return fail(nullptr, MCRT_ENOMEM, "context allocation failed");
   }
   (void)hipEventRecord(ctx->ev_stage, 0);
+  if (scratch_init(device) != hipSuccess) {
+    mcrt_destroy(ctx);
+    return fail(nullptr, MCRT_EDEVICE, "hipGetSymbolAddress failed for the scratch array");
+  }
   *out = ctx;
   return MCRT_OK;
 }
@@ -1722,33 +1728,20 @@ extern "C" mcrt_status mcrt_packet_records(mcrt_ctx *ctx, mcrt_packet_record *ou
 
 // ------------------------------------------------------------- ray-tracer
 
-static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt, hipStream_t st,
-                              RtArgs &A) {
+static mcrt_status rt_check(mcrt_ctx *ctx, int npx, int npy) {
   mcrt_status s = ready(ctx);
   if (s) return s;
   if (ctx->nview < 1 || ctx->nimg < 1) return fail(ctx, MCRT_ESTATE, "set_views before ray-tracing");
   if (npx < 1 || npy < 1 || (uint64_t)npx * npy > (1ull << 28)) return fail(ctx, MCRT_EINVAL, "bad image size");
-  HIPCHK(hipSetDevice(ctx->device));
-  s = ensure_state(ctx, st);
-  if (s) return s;
-  s = ensure_ssca(ctx);
-  if (s) return s;
+  return MCRT_OK;
+}
+
+// Ray-tracer arguments (frames of every view, extinction and point-source
+// terms of the imaged wavelengths) with the source functions at S, staged
+// to ctx->d_rt on stream st.
+static mcrt_status rt_args(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt, const void *S,
+                           hipStream_t st, RtArgs &A) {
   const int nq = ctx->nimg;
-  if (!ctx->S_ok) {
-    size_t need = (size_t)ctx->nview * ctx->ncell * nq * rsize(ctx);
-    if (need > ctx->S_cap) {
-      ctx->S_cap = 0;
-      HIPCHK(dev_alloc(&ctx->d_S, need));
-      ctx->S_cap = need;
-    }
-    s = upload_model_only(ctx, st);
-    if (s) return s;
-    HIPCHK(hipEventRecord(ctx->evs0, st));
-    HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, ctx->d_S, st));
-    HIPCHK(hipEventRecord(ctx->evs1, st));
-    ctx->have_s = true;
-    ctx->S_ok = true;
-  }
   memset(&A, 0, sizeof A);
   A.nx = ctx->nx; A.ny = ctx->ny; A.nz = ctx->nz; A.nimg = nq; A.npx = npx; A.npy = npy;
   A.nview = ctx->nview; A.nsrc = ctx->nsrc;
@@ -1756,7 +1749,7 @@ static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_r
   A.dcell = ctx->dcell;
   A.ncell = ctx->ncell;
   A.rho = rho_rt ? rho_rt : ctx->d_rho;
-  A.S = ctx->d_S;
+  A.S = S;
   TabOff o = tab_offsets(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows);
   for (int q = 0; q < nq; ++q) {
     int j = ctx->img_idx[q];
@@ -1786,6 +1779,33 @@ static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_r
   }
   HIPCHK(stage_copy(ctx, ctx->d_rt, &A, sizeof A, st));
   return MCRT_OK;
+}
+
+static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt, hipStream_t st,
+                              RtArgs &A) {
+  mcrt_status s = rt_check(ctx, npx, npy);
+  if (s) return s;
+  HIPCHK(hipSetDevice(ctx->device));
+  s = ensure_state(ctx, st);
+  if (s) return s;
+  s = ensure_ssca(ctx);
+  if (s) return s;
+  if (!ctx->S_ok) {
+    size_t need = (size_t)ctx->nview * ctx->ncell * ctx->nimg * rsize(ctx);
+    if (need > ctx->S_cap) {
+      ctx->S_cap = 0;
+      HIPCHK(dev_alloc(&ctx->d_S, need));
+      ctx->S_cap = need;
+    }
+    s = upload_model_only(ctx, st);
+    if (s) return s;
+    HIPCHK(hipEventRecord(ctx->evs0, st));
+    HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, ctx->d_S, st));
+    HIPCHK(hipEventRecord(ctx->evs1, st));
+    ctx->have_s = true;
+    ctx->S_ok = true;
+  }
+  return rt_args(ctx, npx, npy, rho_rt, ctx->d_S, st, A);
 }
 
 extern "C" mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt,
@@ -1822,6 +1842,65 @@ extern "C" mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, cons
     if (sed_out) HIPCHK(hipMemcpyAsync(sed_out, sed, sb, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  return MCRT_OK;
+}
+
+// ------------------------------------------- ray-tracing without allocation
+// For callers that cannot allocate device memory (code under graph capture,
+// serving loops): the source functions live in this file-scope array, one
+// copy per GPU, held until the process ends. Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device
+// (g_scratch); the array's own name is a host-side stand-in.
+static constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static constexpr int SCRATCH_MAX_DEV = 64;
+static void *g_scratch[SCRATCH_MAX_DEV];
+static std::mutex g_scratch_mu;
+
+// Called by mcrt_create with `device` current: resolves this device's copy
+// of the array once.
+static hipError_t scratch_init(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e;
+  }
+  g_scratch[device] = p;
+  return hipSuccess;
+}
+
+extern "C" mcrt_status mcrt_raytrace_image_noalloc(mcrt_ctx *ctx, int npx, int npy,
+                                                   const void *rho_rt, void *img_out,
+                                                   double *sed_out, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  mcrt_status s = rt_check(ctx, npx, npy);
+  if (s) return s;
+  if (!img_out) return fail(ctx, MCRT_EINVAL, "img_out is NULL");
+  if (!ctx->d_k || ctx->state_cells != ctx->ncell || ctx->state_ns != ctx->ns)
+    return fail(ctx, MCRT_ESTATE, "no temperatures yet (run, reset or set_temperatures first)");
+  size_t nsum = (size_t)ctx->nview * ctx->nimg * ctx->ncell * rsize(ctx);
+  if (!ctx->d_ssca || ctx->ssca_cap != nsum)
+    return fail(ctx, MCRT_ESTATE, "no scattering sums for these views (reset or run first)");
+  size_t need = (size_t)ctx->nview * ctx->ncell * ctx->nimg * rsize(ctx);
+  if (need > SCRATCH_BYTES)
+    return fail(ctx, MCRT_EINVAL,
+                "source functions need %zu bytes; the no-allocation ray-tracer holds %zu",
+                need, SCRATCH_BYTES);
+  void *S = (ctx->device < SCRATCH_MAX_DEV) ? g_scratch[ctx->device] : nullptr;
+  if (!S) return fail(ctx, MCRT_EDEVICE, "no scratch address for device %d", ctx->device);
+  HIPCHK(hipSetDevice(ctx->device));
+  s = upload_model_only(ctx, st);
+  if (s) return s;
+  // every (view, cell, wavelength) entry is written: nothing to clear
+  HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, S, st));
+  RtArgs A;
+  s = rt_args(ctx, npx, npy, rho_rt, S, st, A);
+  if (s) return s;
+  HIPCHK(launch_rt_fwd(ctx->d_rt, A, ctx->fp64, img_out, sed_out, nullptr, st));
   return MCRT_OK;
 }
 
