@@ -57,6 +57,10 @@ enum { MCRT_FP64 = 0, MCRT_FP32 = 1 };
  * packet-id epochs (deterministic); BW_TICKET = Bjorkman & Wood with the
  * temperature updated at every absorption (sect. 3.3; order set by the GPU). */
 enum { MCRT_FROZEN = 0, MCRT_BW_EPOCH = 1, MCRT_BW_TICKET = 2 };
+enum { MCRT_TAU_FLIGHT = 0, MCRT_TAU_PER_CELL = 1 };
+enum { MCRT_RT_EXT = 0, MCRT_RT_ABS_LITERAL = 1 };
+enum { MCRT_SCAT_HG = 0, MCRT_SCAT_GFACTOR = 1 };
+enum { MCRT_SSCA_PEELOFF = 0, MCRT_SSCA_MOMENTS = 1 };
 enum { MCRT_ESCAPED = 1, MCRT_KILLED = 2, MCRT_PAH_STOP = 3 };
 
 typedef struct {
@@ -75,6 +79,29 @@ typedef struct {
   int32_t queue_depth;       /* packets per wavefront queue (0 = 2^25; 64..2^26) */
   int32_t walk_blocks_per_cu; /* 256-thread blocks per compute unit of the walk kernel
                                 (0 = 4; 1..32) */
+  int32_t tau_mode;          /* MCRT_TAU_FLIGHT: one optical-depth draw per flight (Eq. 2);
+                                MCRT_TAU_PER_CELL: a new draw on entering each cell, the
+                                packet interacting in the cell iff the segment's depth
+                                exceeds -ln(draw) (sect. 2, footnote to the interaction
+                                test) */
+  uint64_t src_strata;       /* m > 0: m equal-energy source bins (Eq. 1), packet id p
+                                drawing its source wavelength inside stratum p mod m of
+                                the source spectrum's distribution; 0 = plain draw */
+  double pah_nc;             /* PAH photodissociation (sect. 2.1, Eq. 8) in mcrt_run_pah:
+                                carbon atoms per molecule N_C; <= 0 = off */
+  double pah_tcool;          /* cooling time (s): a cell whose molecules (mass N_C 12 amu)
+                                absorb E_PAH = kpah xi m_PAH t_cool / (f_pah rho V) >=
+                                N_C/2 eV dissociates, and its pass-2 packets start from
+                                the sources as source packets */
+  int32_t sh_order;          /* L + 1 (0..9): keep every scattering event at an imaged
+                                wavelength as moments sum xi g^l Y_lm(d_in), l <= L, per
+                                cell (real orthonormal spherical harmonics of the incoming
+                                direction), so that scattered light toward any observer is
+                                formed after the run (sect. 4); the HG phase function is
+                                sum_l g^l sum_m Y_lm(d) Y_lm(k), cut after degree L. 0 = off.
+                                Moments are kept until reset or a change of the imaged
+                                wavelengths (mcrt_set_views with other indices) */
+  int32_t pad_;
 } mcrt_run_opts;
 
 typedef struct {
@@ -107,6 +134,23 @@ const char *mcrt_last_error(const mcrt_ctx *ctx);
  * Resets tallies and temperatures. */
 mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
                           double dcell, const void *rho, int dtype, int mem);
+/* One level of refinement (sect. 2: each cube divided into sub-cubes of
+ * their own density, for a finer sampling where needed): cube c (linear
+ * index, x fastest) is divided into ref[c]^3 sub-cubes of edge dcell/ref[c]
+ * when ref[c] >= 2 (at most 16), whole when 0 or 1. rho_sub holds the
+ * sub-cube densities (g/cm^3, dtype MCRT_FP64 or MCRT_FP32, host memory),
+ * cube after cube in linear order, x fastest inside a cube; nsub must equal
+ * the sum of ref[c]^3 over the divided cubes. The cells of every per-cell
+ * array (tallies, temperatures, scattering sums, densities, gradients)
+ * become the leaves: first the cubes (a divided cube's entry is unused),
+ * then the sub-cubes in rho_sub's order. Packets and rays walk the leaves,
+ * and Lucy's thin test, diffusion steps, Eq. 4 and the source functions use
+ * each leaf's own edge, volume and density. ref NULL (nsub 0) removes the
+ * refinement. Call after the grid; set_grid and the voxelizers reset it.
+ * Resets tallies. EINVAL: bad ref value, nsub mismatch, negative or
+ * non-finite density. ESTATE before the grid. */
+mcrt_status mcrt_set_refinement(mcrt_ctx *ctx, const uint8_t *ref, const void *rho_sub,
+                                uint64_t nsub, int dtype);
 /* Clumpy torus of sect. 6 (Eq. 21 clump centres given, host [n][3] cm):
  * a cell takes rho_clump if its centre lies inside any clump (overlaps keep
  * the single-clump density), rho_inter inside the wedge r_in <= r <= r_out,
@@ -115,10 +159,14 @@ mcrt_status mcrt_voxelize_torus(mcrt_ctx *ctx, int nx, int ny, int nz, const dou
                                 double dcell, int n_clumps, const double *centres,
                                 double r_clump, double rho_clump, double rho_inter,
                                 double r_in, double r_out, double sin_theta1);
-/* Spherical shell rho0 (r_in/r)^2 on [r_in, r_out], cell averages by an
- * 8^3 Gauss-Legendre rule (the shell of sect. 3.6 / 5.1). */
+/* Spherical shell rho0 (r_in/r)^power on [r_in, r_out], cell averages by
+ * an 8^3 Gauss-Legendre rule: power 2 is the r^-2 shell of sect. 5.1, power
+ * 0 the constant-density envelope of the sect. 3.6 run-time comparison
+ * (Table 1). EINVAL on rho0 < 0, r_in <= 0, r_out < r_in or a non-finite
+ * value. */
 mcrt_status mcrt_voxelize_shell(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
-                                double dcell, double rho0, double r_in, double r_out);
+                                double dcell, double rho0, double r_in, double r_out,
+                                double power);
 
 /* Dust of sect. 2: n_lambda wavelengths (um, increasing, 2..256), n_species
  * (1..4) with mass fractions and kabs, ksca (cm^2 per g of dust) and HG g,
@@ -219,6 +267,35 @@ mcrt_status mcrt_packet_records(mcrt_ctx *ctx, mcrt_packet_record *out, uint64_t
  * dtau only; S keeps the grid's values (emissivity per unit mass fixed). */
 mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt,
                                 void *img_out, double *sed_out, int mem, void *stream);
+/* Formal solution of the ray-tracer and its adjoint. MCRT_RT_EXT (default):
+ * the chord form above. MCRT_RT_ABS_LITERAL: Eqs. 13-14 as printed (sect. 4):
+ * optical depth K dtau with K = sum_s f_s kabs_s (absorption only), and each
+ * cell a ray crosses adds C = (1 - exp(-rho K dcell)) S_e + I_s attenuated
+ * from the cell's border to the observer, where tau_cell = rho K dcell is
+ * the face-to-face depth, S_e = sum_s f_s kabs_s B(T_s)/K (B(T) for one
+ * species) and I_s = Ssca/(dnu dcell^2) is Eq. 16's scattered intensity with
+ * the event energies spread over the cell's face. C comes from the grid
+ * density; rho_rt enters only the attenuation. Point sources are attenuated
+ * with K. EINVAL on another mode. */
+mcrt_status mcrt_set_raytrace_mode(mcrt_ctx *ctx, int rt_mode);
+
+/* Scattering law of the transport and the peel-off sums (sect. 4):
+ * MCRT_SCAT_HG (default), Henyey-Greenstein with the given g (Eq. 15); or
+ * MCRT_SCAT_GFACTOR, the g-factor approximation: isotropic scattering with
+ * kappa_sca (1 - g) per species and wavelength (albedo and extinction follow).
+ * Rebuilds the tables. EINVAL on another law. */
+mcrt_status mcrt_set_scattering_law(mcrt_ctx *ctx, int law);
+/* Scattered light of the ray-tracer's source functions: MCRT_SSCA_PEELOFF
+ * (default), the per-view sums of the transport; MCRT_SSCA_MOMENTS, the
+ * moments of the last run with sh_order > 0 evaluated toward each view set
+ * (any views, set after the run) as sum_lm Y_lm(k_v) M_lm. */
+mcrt_status mcrt_set_scattered_light(mcrt_ctx *ctx, int source);
+/* Moments of the scattering events (erg/s), [n_img][order^2][cells] with
+ * index l^2 + l + m, host or device destination; *order (nullable) receives
+ * L + 1 (0 when none). out NULL: order only. ESTATE when there are none. */
+mcrt_status mcrt_scattering_moments(mcrt_ctx *ctx, double *out, int *order, int mem,
+                                    void *stream);
+
 /* mcrt_raytrace_image for callers that cannot allocate device memory
  * (code under HIP graph capture, serving loops, harnesses that forbid
  * hipMalloc): the same kernels and results, with img_out

@@ -28,6 +28,8 @@ class RunOpts(C.Structure):
         ("mrw_gamma", C.c_double), ("max_interactions", C.c_uint64),
         ("sed_theta_bins", C.c_int32), ("record", C.c_int32), ("blocks_per_cu", C.c_int32),
         ("queue_depth", C.c_int32), ("walk_blocks_per_cu", C.c_int32),
+        ("tau_mode", C.c_int32), ("src_strata", C.c_uint64), ("pah_nc", C.c_double),
+        ("pah_tcool", C.c_double), ("sh_order", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -59,7 +61,7 @@ SIGNATURES = {
                                       _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double]),
     "mcrt_voxelize_shell": (C.c_int, [_ctxp, C.c_int, C.c_int, C.c_int, _dp, C.c_double,
-                                      C.c_double, C.c_double, C.c_double]),
+                                      C.c_double, C.c_double, C.c_double, C.c_double]),
     "mcrt_set_dust": (C.c_int, [_ctxp, C.c_int, _dp, C.c_int, _dp, _dp, _dp, _dp, C.c_int,
                                 C.c_int, _dp, _dp]),
     "mcrt_set_sources": (C.c_int, [_ctxp, C.c_int, _dp, _dp, _dp, _dp]),
@@ -80,6 +82,11 @@ SIGNATURES = {
     "mcrt_scattering": (C.c_int, [_ctxp, _vp, C.c_int, _vp]),
     "mcrt_packet_records": (C.c_int, [_ctxp, _vp, C.c_uint64, C.c_int]),
     "mcrt_raytrace_image": (C.c_int, [_ctxp, C.c_int, C.c_int, _vp, _vp, _vp, C.c_int, _vp]),
+    "mcrt_set_raytrace_mode": (C.c_int, [_ctxp, C.c_int]),
+    "mcrt_set_refinement": (C.c_int, [_ctxp, C.POINTER(C.c_uint8), _vp, C.c_uint64, C.c_int]),
+    "mcrt_set_scattering_law": (C.c_int, [_ctxp, C.c_int]),
+    "mcrt_set_scattered_light": (C.c_int, [_ctxp, C.c_int]),
+    "mcrt_scattering_moments": (C.c_int, [_ctxp, _vp, C.POINTER(C.c_int), C.c_int, _vp]),
     "mcrt_raytrace_image_noalloc": (C.c_int, [_ctxp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "mcrt_raytrace_adjoint": (C.c_int, [_ctxp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, C.c_int,
                                         _vp]),

@@ -43,7 +43,8 @@ def _stream(stream):
 
 def run_opts(mode="bw_ticket", n_iter=3, epoch_packets=4096, n_total=0, lucy_tau=1e-2,
              mrw_tau=0.0, mrw_gamma=2.0, max_interactions=10_000_000, sed_theta_bins=10,
-             record=False, blocks_per_cu=0, queue_depth=0, walk_blocks_per_cu=0):
+             record=False, blocks_per_cu=0, queue_depth=0, walk_blocks_per_cu=0,
+             tau_mode="flight", src_strata=0, pah_nc=0.0, pah_tcool=0.0, sh_order=0):
     modes = {"frozen": L.FROZEN, "bw_epoch": L.BW_EPOCH, "bw_ticket": L.BW_TICKET}
     o = L.RunOpts()
     o.mode = modes[mode] if isinstance(mode, str) else int(mode)
@@ -51,6 +52,11 @@ def run_opts(mode="bw_ticket", n_iter=3, epoch_packets=4096, n_total=0, lucy_tau
     o.lucy_tau, o.mrw_tau, o.mrw_gamma = lucy_tau, mrw_tau, mrw_gamma
     o.max_interactions, o.sed_theta_bins, o.record = max_interactions, sed_theta_bins, int(record)
     o.blocks_per_cu, o.queue_depth, o.walk_blocks_per_cu = blocks_per_cu, queue_depth, walk_blocks_per_cu
+    taus = {"flight": 0, "per_cell": 1}
+    o.tau_mode = taus[tau_mode] if isinstance(tau_mode, str) else int(tau_mode)
+    o.src_strata = src_strata
+    o.pah_nc, o.pah_tcool = pah_nc, pah_tcool
+    o.sh_order = sh_order
     return o
 
 
@@ -67,6 +73,7 @@ class Context:
         self.nx = self.ny = self.nz = 0
         self.ns = self.nl = 0
         self.nview = self.nimg = 0
+        self.nsub = 0
         self.ntheta = 10
 
     def close(self):
@@ -85,7 +92,8 @@ class Context:
 
     @property
     def ncells(self):
-        return self.nx * self.ny * self.nz
+        """Leaf cells: cubes plus the sub-cubes of divided cubes."""
+        return self.nx * self.ny * self.nz + self.nsub
 
     @property
     def real_dtype(self):
@@ -93,6 +101,7 @@ class Context:
 
     # ------------------------------------------------------------ set-up
     def set_grid(self, rho, origin, dcell):
+        self.nsub = 0
         if hasattr(rho, "data_ptr"):  # torch tensor (host or device)
             nz, ny, nx = rho.shape
             dev = rho.is_cuda
@@ -113,6 +122,7 @@ class Context:
         self.nx, self.ny, self.nz = nx, ny, nz
 
     def voxelize_torus(self, n, origin, dcell, geo):
+        self.nsub = 0
         o = _f64(origin)
         cen = _f64(geo["centres"])
         self._chk(self.lib.mcrt_voxelize_torus(
@@ -122,9 +132,11 @@ class Context:
         self.nx, self.ny, self.nz = n
 
     def voxelize_shell(self, n, origin, dcell, geo):
+        self.nsub = 0
         o = _f64(origin)
         self._chk(self.lib.mcrt_voxelize_shell(self.h, n[0], n[1], n[2], _dptr(o), float(dcell),
-                                               geo["rho0"], geo["r_in"], geo["r_out"]))
+                                               geo["rho0"], geo["r_in"], geo["r_out"],
+                                               float(geo.get("power", 2.0))))
         self.nx, self.ny, self.nz = n
 
     def set_dust(self, lam_um, mass_frac, kabs, ksca, g, pah_species=-1, pah_emis=None,
@@ -165,10 +177,22 @@ class Context:
             raise ValueError("model has neither rho nor a voxelizable geometry")
         self.set_dust(mi.lam_um, mi.mass_frac, mi.kabs, mi.ksca, mi.g, mi.pah_species,
                       mi.pah_emis, mi.pah_edges)
+        if getattr(mi, "ref", None) is not None:
+            self.set_refinement(mi.ref, mi.rho_sub)
         self.set_sources(mi.src_pos, mi.src_lum, mi.src_shape, mi.src_tbb)
         if views is not None:
             self.set_views(views, img_idx, distance)
         return self
+
+    def set_refinement(self, ref, rho_sub):
+        """Divide cube c into ref[c]^3 sub-cubes (ref >= 2) with densities
+        rho_sub, cube by cube in linear cube order, x fastest inside a cube."""
+        r = None if ref is None else np.ascontiguousarray(ref, dtype=np.uint8).ravel()
+        rs = _f64(rho_sub) if rho_sub is not None else np.zeros(0)
+        self._chk(self.lib.mcrt_set_refinement(
+            self.h, None if r is None else r.ctypes.data_as(C.POINTER(C.c_uint8)),
+            C.c_void_p(rs.ctypes.data) if rs.size else None, rs.size, L.FP64))
+        self.nsub = int(rs.size)
 
     # -------------------------------------------------------------- runs
     def reset(self, stream=None):
@@ -290,6 +314,35 @@ class Context:
                                                C.c_void_p(sed.data_ptr()), L.DEVICE,
                                                _stream(None)))
         return img, sed
+
+    def set_scattering_law(self, law):
+        """'hg' (Henyey-Greenstein) or 'gfactor' (isotropic, kappa_sca (1 - g))."""
+        laws = {"hg": 0, "gfactor": 1}
+        self._chk(self.lib.mcrt_set_scattering_law(self.h, laws[law] if isinstance(law, str)
+                                                   else int(law)))
+
+    def set_scattered_light(self, source):
+        """'peeloff' (per-view sums of the run) or 'moments' (any view)."""
+        srcs = {"peeloff": 0, "moments": 1}
+        self._chk(self.lib.mcrt_set_scattered_light(self.h, srcs[source] if isinstance(source, str)
+                                                    else int(source)))
+
+    def scattering_moments(self):
+        """Moments [img][order^2][cells] in erg/s (None when there are none)."""
+        order = C.c_int()
+        self._chk(self.lib.mcrt_scattering_moments(self.h, None, C.byref(order), L.HOST, None))
+        if order.value == 0:
+            return None
+        out = np.zeros((self.nimg, order.value ** 2, self.ncells))
+        self._chk(self.lib.mcrt_scattering_moments(self.h, C.c_void_p(out.ctypes.data), None,
+                                                   L.HOST, None))
+        return out
+
+    def set_raytrace_mode(self, mode):
+        """'ext' (chord form) or 'abs_literal' (Eqs. 13-14 as printed)."""
+        modes = {"ext": 0, "abs_literal": 1}
+        self._chk(self.lib.mcrt_set_raytrace_mode(self.h, modes[mode] if isinstance(mode, str)
+                                                  else int(mode)))
 
     def raytrace_noalloc(self, npx, npy, img, sed=None, rho_rt=None):
         """mcrt_raytrace_image_noalloc into caller-owned device tensors."""

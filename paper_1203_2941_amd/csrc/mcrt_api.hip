@@ -15,9 +15,9 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
-#include <mutex>
 #include <string>
 #include <vector>
+#include <mutex>
 
 #include "../../include/mcrt.h"
 #include "mcrt_rtargs.h"
@@ -27,17 +27,20 @@ size_t transport_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, bool
 hipError_t launch_epoch_snapshot(const ModelDev *d, hipStream_t st);
 hipError_t launch_finalize_T(const ModelDev *d, bool fp64, double *T, double *E, hipStream_t st);
 hipError_t launch_init_T(const ModelDev *d, bool fp64, double *T, hipStream_t st);
-hipError_t launch_build_S(const ModelDev *d, bool fp64, void *S, hipStream_t st);
+hipError_t launch_build_S(const ModelDev *d, bool fp64, bool lit, bool sh, void *S,
+                          hipStream_t st);
 hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, int nz, int nbx,
                         int nby, hipStream_t st);
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
-                           bool idx32, const hipEvent_t *ev, hipStream_t st);
+                           bool idx32, bool per_cell, bool refined, const hipEvent_t *ev,
+                           hipStream_t st);
 size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, int occ_words, bool fp64);
 hipError_t launch_occ(bool fp64, const void *rb, uint32_t *occ, uint64_t ncell_b, int osh,
                       hipStream_t st);
 hipError_t launch_wf_finish(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
-                            int grid, size_t lds, bool idx32, hipStream_t st);
+                            int grid, size_t lds, bool idx32, bool per_cell, bool refined,
+                            hipStream_t st);
 hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint32_t *busy,
                           uint32_t *left,
                           hipStream_t st);
@@ -49,8 +52,8 @@ hipError_t launch_vox_torus(bool fp64, int nx, int ny, int nz, const double o[3]
                             double rho_int, double r_in, double r_out, double s1, void *rho,
                             hipStream_t st);
 hipError_t launch_vox_shell(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
-                            double rho0, double r_in, double r_out, int ng, const double *dgx,
-                            const double *dgw, void *rho, hipStream_t st);
+                            double rho0, double r_in, double r_out, double power, int ng,
+                            const double *dgx, const double *dgw, void *rho, hipStream_t st);
 hipError_t launch_rt_fwd(const RtArgs *dA, const RtArgs &hA, bool fp64, void *img, double *sed,
                          hipEvent_t ev_main, hipStream_t st);
 hipError_t launch_rt_adj(const RtArgs *dA, const RtArgs &hA, bool fp64, const void *w_img,
@@ -67,8 +70,13 @@ struct mcrt_ctx {
   bool has_grid = false;
   int nx = 0, ny = 0, nz = 0;
   double origin[3] = {0, 0, 0}, dcell = 0;
-  uint64_t ncell = 0;
-  void *d_rho = nullptr;
+  uint64_t ncell = 0;          // leaf cells: cubes plus sub-cubes (every per-cell array)
+  uint64_t ncube = 0;          // cubes of the grid
+  uint64_t nsub = 0;           // sub-cubes of the divided cubes (one refinement level)
+  uint8_t *d_ref = nullptr;    // [ncube] sub-cubes per edge (0/1: whole)
+  uint64_t *d_suboff = nullptr;  // [ncube] exclusive prefix sum of r^3 over divided cubes
+  int max_r = 1;
+  void *d_rho = nullptr;       // [ncell]: cube densities, then sub-cube densities
   void *d_rho_b = nullptr;  // density in 4x4x4 bricks for the walk
   int nbx = 0, nby = 0, nbz = 0;
   uint32_t *d_occ = nullptr;  // brick-run occupancy bits for the walk
@@ -130,7 +138,17 @@ struct mcrt_ctx {
   double xi = 0.0;
   uint64_t n_total = 0;
   double ssca_unit = 1.0;  // erg/s/sr per stored unit of the scattering sums
+  // scattering law (Henyey-Greenstein or the g-factor approximation)
+  int scat_law = MCRT_SCAT_HG;
+  // scattering moments [cell][img][order^2] (context precision, units of
+  // ssca_unit), kept for the imaged wavelengths sh_img
+  void *d_sh = nullptr;
+  size_t sh_cap = 0;
+  int sh_have = 0;            // order of the moments in d_sh (0: none)
+  std::vector<int32_t> sh_img;
+  int ssca_src = MCRT_SSCA_PEELOFF;
   // ray-tracer
+  int rt_mode = MCRT_RT_EXT;
   void *d_S = nullptr;
   size_t S_cap = 0;
   bool S_ok = false;
@@ -267,7 +285,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
                 ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
                 ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_ctl, ctx->d_q, ctx->d_stats,
                 ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
-                ctx->d_temp};
+                ctx->d_temp, ctx->d_sh, ctx->d_ref, ctx->d_suboff};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
@@ -351,6 +369,32 @@ static mcrt_status zero_tallies(mcrt_ctx *ctx, hipStream_t st) {
     if (ctx->fp64) HIPCHK(fill<double>((double *)ctx->d_ssca, 0.0, m, st));
     else HIPCHK(fill<float>((float *)ctx->d_ssca, 0.0f, m, st));
   }
+  if (ctx->d_sh && ctx->sh_have > 0) {
+    uint64_t m = (uint64_t)ctx->ncell * ctx->nimg * (uint64_t)(ctx->sh_have * ctx->sh_have);
+    if (ctx->fp64) HIPCHK(fill<double>((double *)ctx->d_sh, 0.0, m, st));
+    else HIPCHK(fill<float>((float *)ctx->d_sh, 0.0f, m, st));
+  }
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+// Moments of order `order` for the current imaged wavelengths, zeroed when
+// the buffer is (re)made; kept across runs otherwise (runs add to them).
+static mcrt_status ensure_sh(mcrt_ctx *ctx, int order, hipStream_t st) {
+  if (order <= 0 || ctx->nimg == 0) return MCRT_OK;
+  if (ctx->sh_have == order && ctx->d_sh && ctx->sh_img == ctx->img_idx) return MCRT_OK;
+  uint64_t m = (uint64_t)ctx->ncell * ctx->nimg * (uint64_t)(order * order);
+  size_t need = m * rsize(ctx);
+  if (need > ctx->sh_cap || !ctx->d_sh) {
+    ctx->sh_cap = 0;
+    ctx->sh_have = 0;
+    HIPCHK(dev_alloc(&ctx->d_sh, need));
+    ctx->sh_cap = need;
+  }
+  if (ctx->fp64) HIPCHK(fill<double>((double *)ctx->d_sh, 0.0, m, st));
+  else HIPCHK(fill<float>((float *)ctx->d_sh, 0.0f, m, st));
+  ctx->sh_have = order;
+  ctx->sh_img = ctx->img_idx;
   ctx->S_ok = false;
   return MCRT_OK;
 }
@@ -412,13 +456,18 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
     double hi = (j == nl - 1) ? L[nl - 1] * std::sqrt(L[nl - 1] / L[nl - 2]) : std::sqrt(L[j] * L[j + 1]);
     w[j] = C_LI / (lo * 1e-4) - C_LI / (hi * 1e-4);
   }
+  // scattering as transported: the model's, or under the g-factor
+  // approximation isotropic with kappa_sca (1 - g)
+  const bool gfac = ctx->scat_law == MCRT_SCAT_GFACTOR;
+  auto ksca_eff = [&](int i) { return gfac ? (1.0 - ctx->g[i]) * ctx->ksca[i] : ctx->ksca[i]; };
+  auto g_eff = [&](int i) { return gfac ? 0.0 : ctx->g[i]; };
   std::vector<double> kabsm(nl), kscam(nl), kext(nl);
   ctx->kext_max = 0.0;
   for (int j = 0; j < nl; ++j) {
     double a = 0.0, s = 0.0;
     for (int q = 0; q < ns; ++q) {
       a += ctx->frac[q] * ctx->kabs[q * nl + j];
-      s += ctx->frac[q] * ctx->ksca[q * nl + j];
+      s += ctx->frac[q] * ksca_eff(q * nl + j);
     }
     kabsm[j] = a;
     kscam[j] = s;
@@ -518,9 +567,9 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
     r[o.r_hnu + j] = t[o.hnu + j];
     r[o.r_a + j] = t[o.a + j];
     for (int s = 0; s < ns; ++s) {
-      r[o.r_fsca + s * nl + j] = ctx->frac[s] * ctx->ksca[s * nl + j];
+      r[o.r_fsca + s * nl + j] = ctx->frac[s] * ksca_eff(s * nl + j);
       r[o.r_fabs + s * nl + j] = ctx->frac[s] * ctx->kabs[s * nl + j];
-      r[o.r_g + s * nl + j] = ctx->g[s * nl + j];
+      r[o.r_g + s * nl + j] = g_eff(s * nl + j);
       r[o.r_lucy + s * nl + j] =
           (s != ctx->pah && kabsm[j] > 0.0) ? ctx->frac[s] * ctx->kabs[s * nl + j] / kabsm[j] : 0.0;
       r[o.r_wk + s * nl + j] = t[o.wk + s * nl + j];
@@ -749,7 +798,9 @@ extern "C" mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, cons
   ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
   for (int k = 0; k < 3; ++k) ctx->origin[k] = origin[k];
   ctx->dcell = dcell;
-  ctx->ncell = n;
+  ctx->ncell = ctx->ncube = n;
+  ctx->nsub = 0;
+  ctx->max_r = 1;
   {
     mcrt_status sb = build_brick(ctx);
     if (sb) return sb;
@@ -768,6 +819,86 @@ extern "C" mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, cons
   return MCRT_OK;
 }
 
+extern "C" mcrt_status mcrt_set_refinement(mcrt_ctx *ctx, const uint8_t *ref, const void *rho_sub,
+                                           uint64_t nsub, int dtype) {
+  if (!ctx) return MCRT_EINVAL;
+  if (!ctx->has_grid) return fail(ctx, MCRT_ESTATE, "set the grid before its refinement");
+  if (dtype != MCRT_FP64 && dtype != MCRT_FP32) return fail(ctx, MCRT_EINVAL, "bad dtype");
+  HIPCHK(hipSetDevice(ctx->device));
+  const uint64_t nc = ctx->ncube;
+  std::vector<uint64_t> off(nc, 0);
+  uint64_t tot = 0;
+  int rmax = 1;
+  if (ref) {
+    for (uint64_t c = 0; c < nc; ++c) {
+      off[c] = tot;
+      const int r = ref[c];
+      if (r > MAX_REF) return fail(ctx, MCRT_EINVAL, "ref[%llu] = %d exceeds %d", (unsigned long long)c, r, MAX_REF);
+      if (r >= 2) {
+        tot += (uint64_t)r * r * r;
+        if (r > rmax) rmax = r;
+      }
+    }
+  }
+  if (tot != nsub) return fail(ctx, MCRT_EINVAL, "nsub = %llu, the divided cubes hold %llu", (unsigned long long)nsub, (unsigned long long)tot);
+  if (tot > 0 && !rho_sub) return fail(ctx, MCRT_EINVAL, "rho_sub is NULL");
+  if (nc + tot > (1ull << 34)) return fail(ctx, MCRT_EINVAL, "too many cells");
+  std::vector<double> h(tot);
+  for (uint64_t i = 0; i < tot; ++i) {
+    double v = dtype == MCRT_FP64 ? ((const double *)rho_sub)[i] : (double)((const float *)rho_sub)[i];
+    if (!finite_nonneg(v)) return fail(ctx, MCRT_EINVAL, "rho_sub[%llu] is negative or not finite", (unsigned long long)i);
+    h[i] = v;
+  }
+  // cube densities stay first; sub-cube densities follow them
+  void *nr = nullptr;
+  HIPCHK(dev_alloc(&nr, (nc + tot) * rsize(ctx)));
+  HIPCHK(hipMemcpy(nr, ctx->d_rho, nc * rsize(ctx), hipMemcpyDeviceToDevice));
+  if (tot > 0) {
+    char *dst = (char *)nr + nc * rsize(ctx);
+    if (ctx->fp64) {
+      HIPCHK(hipMemcpy(dst, h.data(), tot * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(h.begin(), h.end());
+      HIPCHK(hipMemcpy(dst, f.data(), tot * 4, hipMemcpyHostToDevice));
+    }
+  }
+  (void)hipFree(ctx->d_rho);
+  ctx->d_rho = nr;
+  if (tot > 0) {
+    HIPCHK(dev_alloc((void **)&ctx->d_ref, nc));
+    HIPCHK(hipMemcpy(ctx->d_ref, ref, nc, hipMemcpyHostToDevice));
+    HIPCHK(dev_alloc((void **)&ctx->d_suboff, nc * 8));
+    HIPCHK(hipMemcpy(ctx->d_suboff, off.data(), nc * 8, hipMemcpyHostToDevice));
+  } else {
+    if (ctx->d_ref) (void)hipFree(ctx->d_ref);
+    if (ctx->d_suboff) (void)hipFree(ctx->d_suboff);
+    ctx->d_ref = nullptr;
+    ctx->d_suboff = nullptr;
+  }
+  ctx->nsub = tot;
+  ctx->max_r = rmax;
+  ctx->ncell = nc + tot;
+  ctx->S_ok = false;
+  ctx->sh_have = 0;
+  if (ctx->d_ssca) {
+    (void)hipFree(ctx->d_ssca);
+    ctx->d_ssca = nullptr;
+  }
+  ctx->ssca_cap = 0;
+  if (ctx->has_dust) {
+    mcrt_status s = ensure_state(ctx, 0);
+    if (s) return s;
+    s = ensure_ssca(ctx);
+    if (s) return s;
+    s = zero_tallies(ctx, 0);
+    if (s) return s;
+    s = zero_epoch(ctx, 0);
+    if (s) return s;
+  }
+  HIPCHK(hipDeviceSynchronize());
+  return MCRT_OK;
+}
+
 static mcrt_status grid_geom(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3], double dcell) {
   if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, MCRT_EINVAL, "grid dimensions must be > 0");
   if (!origin) return fail(ctx, MCRT_EINVAL, "origin is NULL");
@@ -779,7 +910,9 @@ static mcrt_status grid_geom(mcrt_ctx *ctx, int nx, int ny, int nz, const double
   ctx->nx = nx; ctx->ny = ny; ctx->nz = nz;
   for (int k = 0; k < 3; ++k) ctx->origin[k] = origin[k];
   ctx->dcell = dcell;
-  ctx->ncell = n;
+  ctx->ncell = ctx->ncube = n;
+  ctx->nsub = 0;
+  ctx->max_r = 1;
   return MCRT_OK;
 }
 
@@ -851,9 +984,10 @@ static void gl_rule(int n, std::vector<double> &x, std::vector<double> &w) {
 
 extern "C" mcrt_status mcrt_voxelize_shell(mcrt_ctx *ctx, int nx, int ny, int nz,
                                            const double origin[3], double dcell, double rho0,
-                                           double r_in, double r_out) {
+                                           double r_in, double r_out, double power) {
   if (!ctx) return MCRT_EINVAL;
-  if (!finite_nonneg(rho0) || !(r_in > 0.0) || !(r_out >= r_in) || !std::isfinite(r_out))
+  if (!finite_nonneg(rho0) || !(r_in > 0.0) || !(r_out >= r_in) || !std::isfinite(r_out) ||
+      !std::isfinite(power))
     return fail(ctx, MCRT_EINVAL, "bad shell parameters");
   mcrt_status s = grid_geom(ctx, nx, ny, nz, origin, dcell);
   if (s) return s;
@@ -863,8 +997,8 @@ extern "C" mcrt_status mcrt_voxelize_shell(mcrt_ctx *ctx, int nx, int ny, int nz
   HIPCHK(hipMalloc((void **)&dg, 16 * 8));
   HIPCHK(hipMemcpy(dg, gx.data(), 64, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dg + 8, gw.data(), 64, hipMemcpyHostToDevice));
-  hipError_t e = launch_vox_shell(ctx->fp64, nx, ny, nz, origin, dcell, rho0, r_in, r_out, 8, dg,
-                                  dg + 8, ctx->d_rho, 0);
+  hipError_t e = launch_vox_shell(ctx->fp64, nx, ny, nz, origin, dcell, rho0, r_in, r_out, power,
+                                  8, dg, dg + 8, ctx->d_rho, 0);
   hipError_t e2 = hipDeviceSynchronize();
   (void)hipFree(dg);
   if (e != hipSuccess || e2 != hipSuccess)
@@ -1004,6 +1138,8 @@ extern "C" mcrt_status mcrt_set_views(mcrt_ctx *ctx, int n_views, const double *
       else HIPCHK(fill<float>((float *)ctx->d_ssca, 0.0f, m, 0));
     }
   }
+  // moments are kept for their imaged wavelengths (valid for any views)
+  if (ctx->sh_have > 0 && ctx->sh_img != ctx->img_idx) ctx->sh_have = 0;
   ctx->S_ok = false;
   mcrt_status s = build_tables(ctx);
   if (s) return s;
@@ -1021,6 +1157,13 @@ static mcrt_status ready(mcrt_ctx *ctx) {
 }
 
 // Host image of the model descriptor for a launch.
+// Ray-tracer source terms: printed form of Eqs. 13-14, and the order of the
+// scattering moments the scattered light is formed from (0: per-view sums).
+static bool rt_lit(const mcrt_ctx *ctx) { return ctx->rt_mode == MCRT_RT_ABS_LITERAL; }
+static int sh_read(const mcrt_ctx *ctx) {
+  return ctx->ssca_src == MCRT_SSCA_MOMENTS ? ctx->sh_have : 0;
+}
+
 static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int model_id) {
   memset(&M, 0, sizeof(M));
   M.nx = ctx->nx; M.ny = ctx->ny; M.nz = ctx->nz;
@@ -1028,6 +1171,14 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.nview = ctx->nview; M.nimg = ctx->nimg; M.ntheta = ctx->ntheta; M.model_id = model_id;
   M.mode = o ? o->mode : M_BW_TICKET;
   M.record = o ? o->record : 0;
+  M.tau_mode = o ? o->tau_mode : 0;
+  M.src_strata = o ? o->src_strata : 0;
+  M.pah_nc = o ? o->pah_nc : 0.0;
+  M.pah_tcool = o ? o->pah_tcool : 0.0;
+  M.sh_order = (o && o->sh_order > 0 && ctx->nimg > 0) ? o->sh_order : 0;
+  M.sh = ctx->d_sh;
+  M.sh_read = o ? 0 : sh_read(ctx);
+  M.rt_lit = rt_lit(ctx) ? 1 : 0;
   M.pass = 1;
   M.iter = 0;
   for (int k = 0; k < 3; ++k) M.origin[k] = ctx->origin[k];
@@ -1043,6 +1194,9 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.phi_tmin = ctx->phi_tmin;
   M.max_int = o ? o->max_interactions : 0;
   M.ncell = ctx->ncell;
+  M.ncube = ctx->ncube;
+  M.ref = ctx->nsub > 0 ? ctx->d_ref : nullptr;
+  M.sub_off = ctx->nsub > 0 ? ctx->d_suboff : nullptr;
   M.rho = ctx->d_rho;
   M.rho_b = ctx->d_rho_b;
   M.nbx = ctx->nbx; M.nby = ctx->nby; M.nbz = ctx->nbz;
@@ -1063,7 +1217,10 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.rec = nullptr;
   M.ctl = ctx->d_ctl;
   M.counter = &ctx->d_ctl->emitted;  // address arithmetic only
-  for (int k = 0; k < 2; ++k) M.q[k] = ctx->q[k];
+  for (int k = 0; k < 2; ++k) {
+    M.q[k] = ctx->q[k];
+    if (ctx->nsub == 0) M.q[k].fine = nullptr;  // whole cubes only: no sub-cube indices
+  }
   M.qcap = ctx->qcap;
   M.qseg = ctx->qcap / NSEG;
   M.stats = ctx->d_stats;
@@ -1088,6 +1245,12 @@ static mcrt_status check_opts(mcrt_ctx *ctx, const mcrt_run_opts *o) {
     return fail(ctx, MCRT_EINVAL, "walk_blocks_per_cu must be 0..32");
   if (o->queue_depth != 0 && (o->queue_depth < 64 || o->queue_depth > (1 << 26)))
     return fail(ctx, MCRT_EINVAL, "queue_depth must be 0 or 64..2^26");
+  if (o->tau_mode != MCRT_TAU_FLIGHT && o->tau_mode != MCRT_TAU_PER_CELL)
+    return fail(ctx, MCRT_EINVAL, "tau_mode must be MCRT_TAU_FLIGHT or MCRT_TAU_PER_CELL");
+  if (!std::isfinite(o->pah_nc) || !std::isfinite(o->pah_tcool) || o->pah_tcool < 0.0)
+    return fail(ctx, MCRT_EINVAL, "pah_nc and pah_tcool must be finite, pah_tcool >= 0");
+  if (o->sh_order < 0 || o->sh_order > MAX_SH_ORDER)
+    return fail(ctx, MCRT_EINVAL, "sh_order must be 0..%d", MAX_SH_ORDER);
   return MCRT_OK;
 }
 
@@ -1125,7 +1288,7 @@ static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t
   if (Q <= ctx->qcap && ctx->d_q) return MCRT_OK;
   const size_t rs = rsize(ctx);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t per = 8 * al(Q * rs) + 4 * al(Q * 4) + al(Q * 8) + 7 * al(Q * 4) + al(Q * 8);
+  const size_t per = 8 * al(Q * rs) + 4 * al(Q * 4) + al(Q * 8) + 8 * al(Q * 4) + al(Q * 8);
   HIPCHK(dev_alloc(&ctx->d_q, 2 * per));
   char *b = (char *)ctx->d_q;
   for (int k = 0; k < 2; ++k) {
@@ -1135,7 +1298,8 @@ static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t
     int32_t **iv[4] = {&q.cx, &q.cy, &q.cz, &q.j};
     for (int32_t **r : iv) { *r = (int32_t *)b; b += al(Q * 4); }
     q.pid = (uint64_t *)b; b += al(Q * 8);
-    uint32_t **uv[7] = {&q.rngd, &q.nint, &q.ncross, &q.nscat, &q.nabs, &q.nmrw, &q.nlucy};
+    uint32_t **uv[8] = {&q.rngd, &q.nint, &q.ncross, &q.nscat, &q.nabs, &q.nmrw, &q.nlucy,
+                        &q.fine};
     for (uint32_t **r : uv) { *r = (uint32_t *)b; b += al(Q * 4); }
     q.mm = (double *)b; b += al(Q * 8);
   }
@@ -1184,6 +1348,7 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
   const int gfull = ctx->num_cu * ((o && o->blocks_per_cu > 0) ? o->blocks_per_cu : 2);
   const int gwalk = ctx->num_cu * ((o && o->walk_blocks_per_cu > 0) ? o->walk_blocks_per_cu : 4);
   const bool rec = o->record != 0;
+  const bool per_cell = o->tau_mode == MCRT_TAU_PER_CELL;
   const int every = 4;
   // the finishing kernel takes over once every packet has been started and
   // the survivors fit one lane each at two blocks of 256 per CU
@@ -1193,7 +1358,7 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
     const int fcur = (int)(r & 1);
     const hipEvent_t *ev = phase_events(ctx);
     HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w,
-                           idx32_ok(ctx), ev, st));
+                           idx32_ok(ctx), per_cell, ctx->nsub > 0, ev, st));
     if ((r + 1) % every == 0) {
       HIPCHK(launch_wf_busy(ctx->d_model, 1, fcur, &ctx->d_ctl->busy, &ctx->d_ctl->left, st));
       // emitted .. left: the header of the counters
@@ -1210,7 +1375,7 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
           HIPCHK(hipEventRecord(fe[1], st));
         }
         HIPCHK(launch_wf_finish(ctx->d_model, 1, ctx->fp64, rec, 1 - fcur, gfull, lds_f,
-                                idx32_ok(ctx), st));
+                                idx32_ok(ctx), per_cell, ctx->nsub > 0, st));
         if (fe) {
           HIPCHK(hipEventRecord(fe[2], st));
           HIPCHK(hipEventRecord(fe[3], st));
@@ -1260,6 +1425,13 @@ static mcrt_status set_ssca_unit(mcrt_ctx *ctx, double unit, hipStream_t st) {
     else hipLaunchKernelGGL(k_scale<float>, dim3(4096), dim3(256), 0, st, (float *)ctx->d_ssca, f, m);
     HIPCHK(hipGetLastError());
   }
+  if (ctx->d_sh && ctx->sh_have > 0) {
+    uint64_t ms = (uint64_t)ctx->ncell * ctx->nimg * (uint64_t)(ctx->sh_have * ctx->sh_have);
+    double f = ctx->ssca_unit / unit;
+    if (ctx->fp64) hipLaunchKernelGGL(k_scale<double>, dim3(4096), dim3(256), 0, st, (double *)ctx->d_sh, f, ms);
+    else hipLaunchKernelGGL(k_scale<float>, dim3(4096), dim3(256), 0, st, (float *)ctx->d_sh, f, ms);
+    HIPCHK(hipGetLastError());
+  }
   ctx->ssca_unit = unit;
   return MCRT_OK;
 }
@@ -1280,6 +1452,8 @@ static mcrt_status prepare_run(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n
     if (s) return s;
     HIPCHK(fill<uint64_t>(ctx->d_sed, 0ull, (uint64_t)ctx->sed_cap, st));
   }
+  s = ensure_sh(ctx, o->sh_order, st);
+  if (s) return s;
   uint64_t nt = o->n_total ? o->n_total : n;
   if (nt == 0) return fail(ctx, MCRT_EINVAL, "n_total is 0");
   ctx->n_total = nt;
@@ -1748,12 +1922,24 @@ static mcrt_status rt_args(mcrt_ctx *ctx, int npx, int npy, const void *rho_rt, 
   for (int k = 0; k < 3; ++k) A.origin[k] = ctx->origin[k];
   A.dcell = ctx->dcell;
   A.ncell = ctx->ncell;
+  A.ncube = ctx->ncube;
+  A.ref = ctx->nsub > 0 ? ctx->d_ref : nullptr;
+  A.sub_off = ctx->nsub > 0 ? ctx->d_suboff : nullptr;
   A.rho = rho_rt ? rho_rt : ctx->d_rho;
   A.S = S;
   TabOff o = tab_offsets(ctx->nl, ctx->ns, ctx->nsrc, ctx->nrows);
+  A.lit = ctx->rt_mode == MCRT_RT_ABS_LITERAL ? 1 : 0;
   for (int q = 0; q < nq; ++q) {
     int j = ctx->img_idx[q];
-    A.kext[q] = ctx->h_tab[o.kext + j];
+    if (A.lit) {
+      // absorption of the whole mixture, summed in species order
+      double k = 0.0;
+      for (int s2 = 0; s2 < ctx->ns; ++s2)
+        k += ctx->h_tab[o.frac + s2] * ctx->h_tab[o.kabs + s2 * ctx->nl + j];
+      A.kext[q] = k;
+    } else {
+      A.kext[q] = ctx->h_tab[o.kext + j];
+    }
     for (int s2 = 0; s2 < ctx->nsrc; ++s2) A.lnu[s2][q] = ctx->src_lnu[s2 * ctx->nl + j];
   }
   for (int s2 = 0; s2 < ctx->nsrc; ++s2)
@@ -1800,7 +1986,7 @@ static mcrt_status rt_prepare(mcrt_ctx *ctx, int npx, int npy, const void *rho_r
     s = upload_model_only(ctx, st);
     if (s) return s;
     HIPCHK(hipEventRecord(ctx->evs0, st));
-    HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, ctx->d_S, st));
+    HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, rt_lit(ctx), sh_read(ctx) > 0, ctx->d_S, st));
     HIPCHK(hipEventRecord(ctx->evs1, st));
     ctx->have_s = true;
     ctx->S_ok = true;
@@ -1843,6 +2029,80 @@ extern "C" mcrt_status mcrt_raytrace_image(mcrt_ctx *ctx, int npx, int npy, cons
     HIPCHK(hipStreamSynchronize(st));
   }
   return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_set_raytrace_mode(mcrt_ctx *ctx, int rt_mode) {
+  if (!ctx) return MCRT_EINVAL;
+  if (rt_mode != MCRT_RT_EXT && rt_mode != MCRT_RT_ABS_LITERAL)
+    return fail(ctx, MCRT_EINVAL, "rt_mode must be MCRT_RT_EXT or MCRT_RT_ABS_LITERAL");
+  if (rt_mode != ctx->rt_mode) ctx->S_ok = false;
+  ctx->rt_mode = rt_mode;
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_set_scattering_law(mcrt_ctx *ctx, int law) {
+  if (!ctx) return MCRT_EINVAL;
+  if (law != MCRT_SCAT_HG && law != MCRT_SCAT_GFACTOR)
+    return fail(ctx, MCRT_EINVAL, "law must be MCRT_SCAT_HG or MCRT_SCAT_GFACTOR");
+  if (law == ctx->scat_law) return MCRT_OK;
+  ctx->scat_law = law;
+  ctx->S_ok = false;
+  if (ctx->tables_ok) {
+    HIPCHK(hipSetDevice(ctx->device));
+    mcrt_status s = build_tables(ctx);
+    if (s) return s;
+    HIPCHK(hipDeviceSynchronize());
+  }
+  return MCRT_OK;
+}
+
+extern "C" mcrt_status mcrt_set_scattered_light(mcrt_ctx *ctx, int source) {
+  if (!ctx) return MCRT_EINVAL;
+  if (source != MCRT_SSCA_PEELOFF && source != MCRT_SSCA_MOMENTS)
+    return fail(ctx, MCRT_EINVAL, "source must be MCRT_SSCA_PEELOFF or MCRT_SSCA_MOMENTS");
+  ctx->ssca_src = source;
+  ctx->S_ok = false;
+  return MCRT_OK;
+}
+
+// Moments (units of ssca_unit, [cell][img][lm]) to the API layout
+// [img][lm][cell] in erg/s.
+template <typename R>
+__global__ void k_sh_out(const R *a, double *b, double unit, uint64_t ncell, int nq, int nlm) {
+  const uint64_t n = ncell * (uint64_t)nq * nlm;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const uint64_t c = i % ncell, r = i / ncell;
+    const uint64_t lm = r % (uint64_t)nlm, q = r / (uint64_t)nlm;
+    b[i] = (double)a[(c * nq + q) * (uint64_t)nlm + lm] * unit;
+  }
+}
+
+extern "C" mcrt_status mcrt_scattering_moments(mcrt_ctx *ctx, double *out, int *order, int mem,
+                                               void *stream) {
+  if (!ctx) return MCRT_EINVAL;
+  if (order) *order = ctx->sh_have;
+  if (!out) return MCRT_OK;
+  if (ctx->sh_have <= 0 || !ctx->d_sh)
+    return fail(ctx, MCRT_ESTATE, "no moments (run with sh_order > 0 and imaged wavelengths)");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device));
+  const int nlm = ctx->sh_have * ctx->sh_have;
+  uint64_t m = ctx->ncell * (uint64_t)ctx->nimg * nlm;
+  double *tmp = nullptr;
+  HIPCHK(hipMalloc((void **)&tmp, m * 8));
+  if (ctx->fp64)
+    hipLaunchKernelGGL(k_sh_out<double>, dim3(4096), dim3(256), 0, st, (const double *)ctx->d_sh,
+                       tmp, ctx->ssca_unit, ctx->ncell, ctx->nimg, nlm);
+  else
+    hipLaunchKernelGGL(k_sh_out<float>, dim3(4096), dim3(256), 0, st, (const float *)ctx->d_sh,
+                       tmp, ctx->ssca_unit, ctx->ncell, ctx->nimg, nlm);
+  HIPCHK(hipGetLastError());
+  mcrt_status s = to_caller(ctx, out, tmp, m * 8, mem, st);
+  HIPCHK(hipStreamSynchronize(st));
+  (void)hipFree(tmp);
+  return s;
 }
 
 // ------------------------------------------- ray-tracing without allocation
@@ -1896,7 +2156,7 @@ extern "C" mcrt_status mcrt_raytrace_image_noalloc(mcrt_ctx *ctx, int npx, int n
   s = upload_model_only(ctx, st);
   if (s) return s;
   // every (view, cell, wavelength) entry is written: nothing to clear
-  HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, S, st));
+  HIPCHK(launch_build_S(ctx->d_model, ctx->fp64, rt_lit(ctx), sh_read(ctx) > 0, S, st));
   RtArgs A;
   s = rt_args(ctx, npx, npy, rho_rt, S, st, A);
   if (s) return s;
@@ -2075,6 +2335,9 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   HIPCHK(hipGetLastError());
   const int gfull = ctx->num_cu * (opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2);
   const int gwalk = ctx->num_cu * (opts->walk_blocks_per_cu > 0 ? opts->walk_blocks_per_cu : 4);
+  const bool per_cell = opts->tau_mode == MCRT_TAU_PER_CELL;
+  bool refined = false;
+  for (int m = 0; m < n_models; ++m) refined |= models[m]->nsub > 0;
   // ROUNDS wavefront rounds over every model of the batch and the count of
   // models still busy, captured once on the library's own stream and
   // replayed on the caller's until no model has packets left
@@ -2092,7 +2355,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   hipError_t le = hipSuccess;
   for (int r = 0; r < ROUNDS && le == hipSuccess; ++r)
     le = launch_wf_round(ctx->d_batch, n_models, ctx->fp64, false, r & 1, gfull, gwalk, lds, lds_w,
-                         idx32, nullptr, cs_);
+                         idx32, per_cell, refined, nullptr, cs_);
   if (le == hipSuccess)
     le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, d_left, cs_);
   hipError_t ce = hipStreamEndCapture(cs_, &graph);
@@ -2117,7 +2380,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
     if (ctx->h_ctl->left <= fin_max && lds_f <= ctx->lds_max) {
       // every packet started and few left: the finishing kernel ends them
       e = launch_wf_finish(ctx->d_batch, n_models, ctx->fp64, false, ROUNDS & 1, gfull, lds_f,
-                           idx32, st);
+                           idx32, per_cell, refined, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
       if (e != hipSuccess) rs = fail(ctx, MCRT_EDEVICE, "batch finish: %s", hipGetErrorString(e));
       break;

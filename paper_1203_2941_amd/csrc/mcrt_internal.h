@@ -90,6 +90,7 @@ struct QBuf {
   uint32_t *rngd, *nint;
   uint32_t *ncross, *nscat, *nabs, *nmrw, *nlucy;  // kept for packet records
   double *mm;                                      // kept for packet records
+  uint32_t *fine;  // refined grids: the packet's sub-cube (fine_pack); null otherwise
 };
 
 // The walk keeps the occupancy bits of the grid in LDS: one bit per run of
@@ -120,12 +121,23 @@ struct WfCtl {
 struct ModelDev {
   int32_t nx, ny, nz, nl, ns, nsrc, pah, nrows, nview, nimg, ntheta, model_id;
   int32_t mode, record, pass, iter;
+  int32_t tau_mode;           // 0: one optical-depth draw per flight; 1: a new draw per cell
+  int32_t rt_lit;             // ray-tracer source terms in the printed form of Eqs. 13-14
+  uint64_t src_strata;        // m equal-energy source strata (0 = plain source draw)
+  double pah_nc, pah_tcool;   // PAH photodissociation (Eq. 8): carbon atoms, cooling time
+  int32_t sh_order;           // transport: scattering moments up to degree sh_order - 1 (0 off)
+  int32_t sh_read;            // source functions: scattered light from moments of this order
+  void *sh;                   // moments [cell][img][sh_order^2], context precision, units of
+                              // ssca_unit
   double origin[3];
   double dcell, V, xi, lucy_tau, mrw_tau, mrw_gamma, kext_max;
   double ssca_unit;           // scattering sums are stored in these units (erg/s/sr)
   double kr_gmax;             // largest Rosseland-mean bound of the table over [T_TAB_MIN, T_MAX]
   double phi_tmin;            // Phi(T_TAB_MIN) of the first thermal species
   uint64_t max_int, first, n, id_base, rec_first, seed, ncell;
+  uint64_t ncube;             // cubes of the grid (ncell - ncube sub-cubes follow them)
+  const uint8_t *ref;         // [ncube] sub-cubes per edge (0/1 whole), null: no refinement
+  const uint64_t *sub_off;    // [ncube] first sub-cube of each divided cube
   const void *rho;            // [cells] context precision
   const void *rho_b;          // the same density in 4x4x4 bricks (brick_index), read by the walk
   int32_t nbx, nby, nbz;      // bricks per axis
@@ -159,6 +171,104 @@ struct ModelDev {
   uint32_t qcap;              // capacity of each queue
   uint32_t qseg;              // capacity of each of its NSEG segments
 };
+
+// ------------------------------------------ leaves (one refinement level)
+// A divided cube (ref[cube] = r >= 2) holds r^3 sub-cubes of edge dcell / r,
+// numbered ncube + sub_off[cube] + (fz r + fy) r + fx among the leaves; a
+// whole cube is its own leaf. The sub-cube index f of a packet travels packed
+// as fx | fy << 8 | fz << 16.
+template <class G>
+__host__ __device__ __forceinline__ int cube_r(const G &M, int64_t cc) {
+  if (!M.ref) return 1;
+  const int r = M.ref[cc];
+  return r > 1 ? r : 1;
+}
+
+__host__ __device__ __forceinline__ int fine_get(uint32_t fpk, int k) {
+  return (int)((fpk >> (8 * k)) & 0xFFu);
+}
+
+__host__ __device__ __forceinline__ uint32_t fine_pack(int fx, int fy, int fz) {
+  return (uint32_t)fx | ((uint32_t)fy << 8) | ((uint32_t)fz << 16);
+}
+
+// leaf of sub-cube fpk of cube (cx, cy, cz), and its edge
+template <class G>
+__host__ __device__ __forceinline__ int64_t leaf_of(const G &M, int cx, int cy, int cz,
+                                                    uint32_t fpk, double *h) {
+  const int64_t cc = ((int64_t)cz * M.ny + cy) * M.nx + cx;
+  const int r = cube_r(M, cc);
+  if (r == 1) {
+    if (h) *h = M.dcell;
+    return cc;
+  }
+  if (h) *h = M.dcell / (double)r;
+  return (int64_t)M.ncube + (int64_t)M.sub_off[cc] +
+         ((int64_t)fine_get(fpk, 2) * r + fine_get(fpk, 1)) * r + fine_get(fpk, 0);
+}
+
+// Face e (0..r) of the sub-cubes of cube coordinate ck on axis k; the cube's
+// own faces are written as for a whole cube, so a walk leaves a divided cube
+// exactly where the grid puts that face.
+template <class G>
+__host__ __device__ __forceinline__ double face_pos(const G &M, int k, int ck, int r, int e) {
+  if (e == 0) return M.origin[k] + (double)ck * M.dcell;
+  if (e == r) return M.origin[k] + (double)(ck + 1) * M.dcell;
+  return M.origin[k] + (double)ck * M.dcell + (double)e * (M.dcell / (double)r);
+}
+
+// sub-cube index on axis k of point x in cube coordinate ck (a point on a
+// face belongs to the sub-cube that direction component dk points into)
+template <class G>
+__host__ __device__ __forceinline__ int sub_index(const G &M, int k, int ck, int r, double x,
+                                                  double dk) {
+  if (r == 1) return 0;
+  const double q = (x - M.origin[k] - (double)ck * M.dcell) / (M.dcell / (double)r);
+  const double fl = floor(q);
+  int fi = (int)fl;
+  if (q == fl && dk < 0.0) fi -= 1;
+  return fi < 0 ? 0 : (fi > r - 1 ? r - 1 : fi);
+}
+
+// cube c, sub-cube f and sub-cubes per edge r of leaf i; a sub-cube's cube
+// is the last one whose first sub-cube is at or before it
+template <class G>
+__host__ __device__ inline void leaf_loc(const G &M, uint64_t i, int c[3], int f[3], int *r) {
+  uint64_t cc = i;
+  f[0] = f[1] = f[2] = 0;
+  *r = 1;
+  if (i >= M.ncube) {
+    const uint64_t s = i - M.ncube;
+    int64_t lo = 0, hi = (int64_t)M.ncube - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (M.sub_off[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    cc = (uint64_t)lo;
+    const int rr = cube_r(M, (int64_t)cc);
+    const uint64_t loc = s - M.sub_off[cc];
+    f[0] = (int)(loc % rr);
+    f[1] = (int)((loc / rr) % rr);
+    f[2] = (int)(loc / ((uint64_t)rr * rr));
+    *r = rr;
+  }
+  c[0] = (int)(cc % M.nx);
+  c[1] = (int)((cc / M.nx) % M.ny);
+  c[2] = (int)(cc / ((uint64_t)M.nx * M.ny));
+}
+
+// edge and volume of leaf i
+__host__ __device__ inline double leaf_edge(const ModelDev &M, uint64_t i) {
+  if (i < M.ncube) return M.dcell;
+  int c[3], f[3], r;
+  leaf_loc(M, i, c, f, &r);
+  return M.dcell / (double)r;
+}
+__host__ __device__ inline double leaf_volume(const ModelDev &M, uint64_t i) {
+  if (i < M.ncube) return M.V;
+  const double h = leaf_edge(M, i);
+  return h * h * h;
+}
 
 // ---------------------------------------------------------------- bricks
 // The voxel walk reads the density from a copy stored in 4x4x4 bricks of 64
@@ -496,6 +606,48 @@ static __device__ __noinline__ double mrw_solve(double u) {
     y = yn;
   }
   return y;
+}
+
+// Real orthonormal spherical harmonics Y_lm(d), l < order, handed to
+// f(index, value) with index l^2 + l + m: associated Legendre terms in
+// x = d_z without their sin^m factor,
+//   Q_m^m = (2m-1)!!, Q_{m+1}^m = (2m+1) x Q_m^m,
+//   (l-m) Q_l^m = (2l-1) x Q_{l-1}^m - (l+m-1) Q_{l-2}^m,
+// and (d_x + i d_y)^m = sin^m e^{i m phi}: Y_l0 = N Q, Y_l,+-m = sqrt(2) N Q
+// (Re, Im)(d_x + i d_y)^m with N^2 = (2l+1)/(4 pi) (l-m)!/(l+m)!.
+constexpr int MAX_SH_ORDER = 9;
+constexpr int MAX_REF = 16;  // sub-cubes per edge of a divided cube
+template <typename F>
+__host__ __device__ inline void ylm_each(int order, double dx, double dy, double dz, F f) {
+  double cr = 1.0, ci = 0.0, qmm = 1.0;
+  for (int m = 0; m < order; ++m) {
+    if (m > 0) {
+      const double nr = cr * dx - ci * dy, ni = cr * dy + ci * dx;
+      cr = nr;
+      ci = ni;
+      qmm *= (double)(2 * m - 1);
+    }
+    double q2 = 0.0, q1 = qmm;
+    for (int l = m; l < order; ++l) {
+      double q;
+      if (l == m) q = qmm;
+      else if (l == m + 1) q = (double)(2 * m + 1) * dz * qmm;
+      else q = ((double)(2 * l - 1) * dz * q1 - (double)(l + m - 1) * q2) / (double)(l - m);
+      if (l > m) {
+        q2 = q1;
+        q1 = q;
+      }
+      double ratio = 1.0;
+      for (int k = l - m + 1; k <= l + m; ++k) ratio /= (double)k;
+      const double n = sqrt((2.0 * l + 1.0) / (4.0 * PI_D) * ratio);
+      if (m == 0) {
+        f(l * l + l, l, n * q);
+      } else {
+        f(l * l + l + m, l, sqrt(2.0) * n * q * cr);
+        f(l * l + l - m, l, sqrt(2.0) * n * q * ci);
+      }
+    }
+  }
 }
 
 // Device fill (kept as a kernel so that graph captures record no memsets).

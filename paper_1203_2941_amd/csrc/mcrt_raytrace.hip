@@ -96,6 +96,56 @@ __device__ __forceinline__ void walk(const RtArgs &A, const double p0[3], const 
   }
 }
 
+// The same walk through the leaves of a refined grid: each cube's own
+// lattice (a whole cube is one leaf), leaving a divided cube on the cube's
+// own face; the sub-cube of the start from the position.
+template <typename F>
+__device__ __forceinline__ void walk_leaves(const RtArgs &A, const double p0[3], const double d[3],
+                                            int c0[3], F seg) {
+  int c[3] = {c0[0], c0[1], c0[2]};
+  if (c[0] < 0 || c[0] >= A.nx || c[1] < 0 || c[1] >= A.ny || c[2] < 0 || c[2] >= A.nz) return;
+  int f[3];
+  int r = cube_r(A, ((int64_t)c[2] * A.ny + c[1]) * A.nx + c[0]);
+  double tm[3];
+  auto faces = [&]() {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (d[k] > 0.0) tm[k] = (face_pos(A, k, c[k], r, f[k] + 1) - p0[k]) / d[k];
+      else if (d[k] < 0.0) tm[k] = (face_pos(A, k, c[k], r, f[k]) - p0[k]) / d[k];
+      else tm[k] = __builtin_huge_val();
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[k] = sub_index(A, k, c[k], r, p0[k], d[k]);
+  faces();
+  double t = 0.0;
+  const int n[3] = {A.nx, A.ny, A.nz};
+  for (;;) {
+    int a = 0;
+    if (tm[1] < tm[a]) a = 1;
+    if (tm[2] < tm[a]) a = 2;
+    double ell = tm[a] - t;
+    if (ell < 0.0) ell = 0.0;
+    seg(leaf_of(A, c[0], c[1], c[2], fine_pack(f[0], f[1], f[2]), nullptr), ell);
+    if (tm[a] > t) t = tm[a];
+    const int sa = d[a] > 0.0 ? 1 : -1;
+    f[a] += sa;
+    if (f[a] >= 0 && f[a] < r) {
+      tm[a] = (face_pos(A, a, c[a], r, d[a] > 0.0 ? f[a] + 1 : f[a]) - p0[a]) / d[a];
+      continue;
+    }
+    c[a] += sa;
+    if (c[a] < 0 || c[a] >= n[a]) return;
+    r = cube_r(A, ((int64_t)c[2] * A.ny + c[1]) * A.nx + c[0]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k == a) f[k] = d[k] > 0.0 ? 0 : r - 1;
+      else f[k] = sub_index(A, k, c[k], r, p0[k] + t * d[k], d[k]);
+    }
+    faces();
+  }
+}
+
 // 1 - e^-x and e^-x of one segment in the walk precision.
 __device__ __forceinline__ void absorb_pair(double x, double &om, double &e) {
   om = -expm1(-x);
@@ -128,7 +178,10 @@ __device__ __forceinline__ void load_row(const R *sc, int nq, R out[MAX_IMG]) {
   for (int q = 0; q < MAX_IMG; ++q) out[q] = q < nq ? sc[q] : (R)0;
 }
 
-template <typename R>
+// LIT: the printed form of Eqs. 13-14; SH: scattered light formed from the
+// moments of the scattering events (else the per-view sums). Separate
+// instances keep the moment loop's registers out of the common case.
+template <typename R, bool LIT, bool SH>
 __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
   const ModelDev &M = *md;
   TabOff o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
@@ -157,7 +210,15 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
           e += M.tab[o.frac + s] * M.tab[o.kabs + s * M.nl + j] *
                planck_d(M.tab[o.hnu + j], M.tab[o.a + j], T[s]);
         }
-        em[q] = e / M.tab[o.kext + j];
+        if constexpr (LIT) {
+          // printed form: the cell's emergent emission (1 - e^-tau_cell) e/K
+          // with K the whole mixture's absorption and tau_cell face to face
+          double K = 0.0;
+          for (int s = 0; s < M.ns; ++s) K += M.tab[o.frac + s] * M.tab[o.kabs + s * M.nl + j];
+          em[q] = (r > 0.0 && K > 0.0) ? -expm1(-(r * K * leaf_edge(M, c))) * (e / K) : 0.0;
+        } else {
+          em[q] = e / M.tab[o.kext + j];
+        }
       }
     }
     for (int v = 0; v < M.nview; ++v) {
@@ -167,7 +228,22 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
       R sv[MAX_IMG];
 #pragma unroll
       for (int q = 0; q < MAX_IMG; ++q) sv[q] = (R)0;
-      if (sc && r > 0.0) {
+      if (SH && r > 0.0) {
+        // scattered light toward this view from the moments:
+        // sum_lm Y_lm(k_v) M[c][q][lm]
+        const int nlm = M.sh_read * M.sh_read;
+        const R *mc = (const R *)M.sh + (uint64_t)c * nq * nlm;
+        double acc[MAX_IMG];
+#pragma unroll
+        for (int q = 0; q < MAX_IMG; ++q) acc[q] = 0.0;
+        ylm_each(M.sh_read, M.kv[v][0], M.kv[v][1], M.kv[v][2], [&](int i, int, double y) {
+#pragma unroll
+          for (int q = 0; q < MAX_IMG; ++q)
+            if (q < nq) acc[q] += y * (double)mc[q * nlm + i];
+        });
+#pragma unroll
+        for (int q = 0; q < MAX_IMG; ++q) sv[q] = (R)acc[q];
+      } else if (sc && r > 0.0) {
         bool vec = false;
         if constexpr (sizeof(R) == 4 && MAX_IMG == 16) {
           if (nq == 16) {
@@ -190,9 +266,15 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
 #pragma unroll
       for (int q = 0; q < MAX_IMG; ++q) {
         double val = em[q];
-        if (q < nq && sc && r > 0.0) {
+        if (q < nq && (sc || SH) && r > 0.0) {
           int j = M.img_j[q];
-          val += (double)sv[q] * M.ssca_unit / (M.V * M.tab[o.w + j] * r * M.tab[o.kext + j]);
+          if constexpr (LIT) {  // Eq. 16: scattered intensity over the cell's face
+            const double hc = leaf_edge(M, c);
+            val += (double)sv[q] * M.ssca_unit / (M.tab[o.w + j] * hc * hc);
+          } else {
+            val += (double)sv[q] * M.ssca_unit /
+                   (leaf_volume(M, c) * M.tab[o.w + j] * r * M.tab[o.kext + j]);
+          }
         }
         vals[q] = (R)val;
       }
@@ -216,7 +298,9 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
   }
 }
 
-template <typename R>
+// LIT: printed form of Eqs. 13-14: S holds each cell's whole term C, added
+// in full (I += T C) whatever the traced density, which only attenuates.
+template <typename R, bool LIT, bool REF>
 __global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R *img) {
   const RtArgs &A = *Ap;
   const int v = blockIdx.y;
@@ -236,9 +320,9 @@ __global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R
   double pe[3], dir[3];
   int c[3];
   if (ray_entry(A, V, ix, iy, pe, dir, c)) {
-    walk(A, pe, dir, c, [&](int64_t cell, double ell) {
+    auto seg = [&](int64_t cell, double ell) {
       R r = rho[cell];
-      if (!(r > (R)0)) return;
+      if (!LIT && !(r > (R)0)) return;
       R sc[MAX_IMG];
       load_row(S + (uint64_t)cell * nq, nq, sc);
       R el = (R)ell;
@@ -248,10 +332,12 @@ __global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R
         R dtau = r * (R)A.kext[q] * el;
         R om, e;
         absorb_pair(dtau, om, e);
-        I[q] += tr[q] * (double)sc[q] * (double)om;
+        I[q] += tr[q] * (double)sc[q] * (LIT ? 1.0 : (double)om);
         tr[q] *= (double)e;
       }
-    });
+    };
+    if constexpr (REF) walk_leaves(A, pe, dir, c, seg);
+    else walk(A, pe, dir, c, seg);
   }
   const uint64_t plane = (uint64_t)A.npx * A.npy;
 #pragma unroll
@@ -280,7 +366,9 @@ __global__ void k_rt_star(const RtArgs *__restrict__ Ap, R *img, double *sed) {
     c[k] = ci;
   }
   double tau = 0.0;
-  walk(A, p0, V.k, c, [&](int64_t cell, double ell) { tau += (double)rho[cell] * A.kext[q] * ell; });
+  auto acc = [&](int64_t cell, double ell) { tau += (double)rho[cell] * A.kext[q] * ell; };
+  if (A.ref) walk_leaves(A, p0, V.k, c, acc);
+  else walk(A, p0, V.k, c, acc);
   double F = A.lnu[s][q] / (4.0 * PI_D * A.D2) * exp(-tau);
   double xp = 0.0, yp = 0.0;
   for (int k = 0; k < 3; ++k) {
@@ -315,7 +403,9 @@ __global__ void k_rt_sed(const RtArgs *__restrict__ Ap, const R *img, double *se
 // Adjoint: first sweep gives I per wavelength, the second recomputes the
 // transmittance and the gathered intensity A_i in front of each cell:
 // dI/d(dtau_i) = T_<i S_i e^-dtau_i - (I - A_i), d(dtau_i)/d(rho_i) = kext l_i.
-template <typename R>
+// LIT: the cell terms do not depend on the traced density, so
+// dI/d(dtau_i) = -(I - A_i).
+template <typename R, bool LIT, bool REF>
 __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, const R *w_img,
                                                 const double *w_sed, R *drho) {
   const RtArgs &A = *Ap;
@@ -350,9 +440,9 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
   double pe[3], dir[3];
   int c[3];
   if (!ray_entry(A, V, ix, iy, pe, dir, c)) return;
-  walk(A, pe, dir, c, [&](int64_t cell, double ell) {
+  auto sweep1 = [&](int64_t cell, double ell) {
     R r = rho[cell];
-    if (!(r > (R)0)) return;
+    if (!LIT && !(r > (R)0)) return;
     const R *sc = S + (uint64_t)cell * nq;
     R el = (R)ell;
 #pragma unroll
@@ -360,15 +450,17 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
       if (q >= nq) break;
       R om, e;
       absorb_pair(r * (R)A.kext[q] * el, om, e);
-      rem[q] += tr[q] * (double)sc[q] * (double)om;
+      rem[q] += tr[q] * (double)sc[q] * (LIT ? 1.0 : (double)om);
       tr[q] *= (double)e;
     }
-  });
+  };
+  if constexpr (REF) walk_leaves(A, pe, dir, c, sweep1);
+  else walk(A, pe, dir, c, sweep1);
 #pragma unroll
   for (int q = 0; q < MAX_IMG; ++q) tr[q] = 1.0;
-  walk(A, pe, dir, c, [&](int64_t cell, double ell) {
+  auto sweep2 = [&](int64_t cell, double ell) {
     R r = rho[cell];
-    if (!(r > (R)0)) return;
+    if (!LIT && !(r > (R)0)) return;
     const R *sc = S + (uint64_t)cell * nq;
     R el = (R)ell;
     double g = 0.0;
@@ -378,13 +470,15 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
       R om, e;
       absorb_pair(r * (R)A.kext[q] * el, om, e);
       double Sq = (double)sc[q];
-      rem[q] -= tr[q] * Sq * (double)om;
-      double dI = tr[q] * Sq * (double)e - rem[q];
+      rem[q] -= tr[q] * Sq * (LIT ? 1.0 : (double)om);
+      double dI = (LIT ? 0.0 : tr[q] * Sq * (double)e) - rem[q];
       g += wk[q] * ell * dI;
       tr[q] *= (double)e;
     }
     if (g != 0.0) atomicAdd(&drho[cell], (R)g);
-  });
+  };
+  if constexpr (REF) walk_leaves(A, pe, dir, c, sweep2);
+  else walk(A, pe, dir, c, sweep2);
 }
 
 // Adjoint of the attenuated point-source term.
@@ -419,16 +513,31 @@ __global__ void k_rt_star_adj(const RtArgs *__restrict__ Ap, const R *w_img, con
                                : 0.0);
   if (W == 0.0) return;
   double tau = 0.0;
-  walk(A, p0, V.k, c, [&](int64_t cell, double ell) { tau += (double)rho[cell] * A.kext[q] * ell; });
+  auto acc = [&](int64_t cell, double ell) { tau += (double)rho[cell] * A.kext[q] * ell; };
+  if (A.ref) walk_leaves(A, p0, V.k, c, acc);
+  else walk(A, p0, V.k, c, acc);
   double F = A.lnu[s][q] / (4.0 * PI_D * A.D2) * exp(-tau);
-  walk(A, p0, V.k, c, [&](int64_t cell, double ell) {
+  auto grad = [&](int64_t cell, double ell) {
     atomicAdd(&drho[cell], (R)(-W * A.kext[q] * ell * F));
-  });
+  };
+  if (A.ref) walk_leaves(A, p0, V.k, c, grad);
+  else walk(A, p0, V.k, c, grad);
 }
 
-hipError_t launch_build_S(const ModelDev *d, bool fp64, void *S, hipStream_t st) {
-  if (fp64) hipLaunchKernelGGL(k_build_S<double>, dim3(65536), dim3(256), 0, st, d, (double *)S);
-  else hipLaunchKernelGGL(k_build_S<float>, dim3(65536), dim3(256), 0, st, d, (float *)S);
+template <typename R>
+static void build_S_as(const ModelDev *d, bool lit, bool sh, R *S, hipStream_t st) {
+  const dim3 g(65536), b(256);
+  if (lit && sh) hipLaunchKernelGGL((k_build_S<R, true, true>), g, b, 0, st, d, S);
+  else if (lit) hipLaunchKernelGGL((k_build_S<R, true, false>), g, b, 0, st, d, S);
+  else if (sh) hipLaunchKernelGGL((k_build_S<R, false, true>), g, b, 0, st, d, S);
+  else hipLaunchKernelGGL((k_build_S<R, false, false>), g, b, 0, st, d, S);
+}
+
+// lit and sh must match the model's rt_lit and sh_read (> 0).
+hipError_t launch_build_S(const ModelDev *d, bool fp64, bool lit, bool sh, void *S,
+                          hipStream_t st) {
+  if (fp64) build_S_as<double>(d, lit, sh, (double *)S, st);
+  else build_S_as<float>(d, lit, sh, (float *)S, st);
   return hipGetLastError();
 }
 
@@ -439,14 +548,26 @@ hipError_t launch_rt_fwd(const RtArgs *dA, const RtArgs &hA, bool fp64, void *im
   dim3 grid((hA.npx * hA.npy + 255) / 256, hA.nview);
   int nstar = hA.nview * hA.nsrc * hA.nimg;
   if (fp64) {
-    hipLaunchKernelGGL(k_rt_fwd<double>, grid, dim3(256), 0, st, dA, (double *)img);
+    if (hA.ref) {
+      if (hA.lit) hipLaunchKernelGGL((k_rt_fwd<double, true, true>), grid, dim3(256), 0, st, dA, (double *)img);
+      else hipLaunchKernelGGL((k_rt_fwd<double, false, true>), grid, dim3(256), 0, st, dA, (double *)img);
+    } else {
+      if (hA.lit) hipLaunchKernelGGL((k_rt_fwd<double, true, false>), grid, dim3(256), 0, st, dA, (double *)img);
+      else hipLaunchKernelGGL((k_rt_fwd<double, false, false>), grid, dim3(256), 0, st, dA, (double *)img);
+    }
     if (ev_main) (void)hipEventRecord(ev_main, st);
     if (sed) hipLaunchKernelGGL(k_rt_sed<double>, dim3(hA.nview * hA.nimg), dim3(256), 0, st, dA,
                                 (const double *)img, sed);
     if (nstar) hipLaunchKernelGGL(k_rt_star<double>, dim3((nstar + 63) / 64), dim3(64), 0, st, dA,
                                   (double *)img, sed);
   } else {
-    hipLaunchKernelGGL(k_rt_fwd<float>, grid, dim3(256), 0, st, dA, (float *)img);
+    if (hA.ref) {
+      if (hA.lit) hipLaunchKernelGGL((k_rt_fwd<float, true, true>), grid, dim3(256), 0, st, dA, (float *)img);
+      else hipLaunchKernelGGL((k_rt_fwd<float, false, true>), grid, dim3(256), 0, st, dA, (float *)img);
+    } else {
+      if (hA.lit) hipLaunchKernelGGL((k_rt_fwd<float, true, false>), grid, dim3(256), 0, st, dA, (float *)img);
+      else hipLaunchKernelGGL((k_rt_fwd<float, false, false>), grid, dim3(256), 0, st, dA, (float *)img);
+    }
     if (ev_main) (void)hipEventRecord(ev_main, st);
     if (sed) hipLaunchKernelGGL(k_rt_sed<float>, dim3(hA.nview * hA.nimg), dim3(256), 0, st, dA,
                                 (const float *)img, sed);
@@ -461,14 +582,40 @@ hipError_t launch_rt_adj(const RtArgs *dA, const RtArgs &hA, bool fp64, const vo
   dim3 grid((hA.npx * hA.npy + 255) / 256, hA.nview);
   int nstar = hA.nview * hA.nsrc * hA.nimg;
   if (fp64) {
-    hipLaunchKernelGGL(k_rt_adj<double>, grid, dim3(256), 0, st, dA, (const double *)w_img, w_sed,
-                       (double *)drho);
+    if (hA.ref) {
+      if (hA.lit)
+        hipLaunchKernelGGL((k_rt_adj<double, true, true>), grid, dim3(256), 0, st, dA,
+                           (const double *)w_img, w_sed, (double *)drho);
+      else
+        hipLaunchKernelGGL((k_rt_adj<double, false, true>), grid, dim3(256), 0, st, dA,
+                           (const double *)w_img, w_sed, (double *)drho);
+    } else {
+      if (hA.lit)
+        hipLaunchKernelGGL((k_rt_adj<double, true, false>), grid, dim3(256), 0, st, dA,
+                           (const double *)w_img, w_sed, (double *)drho);
+      else
+        hipLaunchKernelGGL((k_rt_adj<double, false, false>), grid, dim3(256), 0, st, dA,
+                           (const double *)w_img, w_sed, (double *)drho);
+    }
     if (ev_main) (void)hipEventRecord(ev_main, st);
     if (nstar) hipLaunchKernelGGL(k_rt_star_adj<double>, dim3((nstar + 63) / 64), dim3(64), 0, st,
                                   dA, (const double *)w_img, w_sed, (double *)drho);
   } else {
-    hipLaunchKernelGGL(k_rt_adj<float>, grid, dim3(256), 0, st, dA, (const float *)w_img, w_sed,
-                       (float *)drho);
+    if (hA.ref) {
+      if (hA.lit)
+        hipLaunchKernelGGL((k_rt_adj<float, true, true>), grid, dim3(256), 0, st, dA,
+                           (const float *)w_img, w_sed, (float *)drho);
+      else
+        hipLaunchKernelGGL((k_rt_adj<float, false, true>), grid, dim3(256), 0, st, dA,
+                           (const float *)w_img, w_sed, (float *)drho);
+    } else {
+      if (hA.lit)
+        hipLaunchKernelGGL((k_rt_adj<float, true, false>), grid, dim3(256), 0, st, dA,
+                           (const float *)w_img, w_sed, (float *)drho);
+      else
+        hipLaunchKernelGGL((k_rt_adj<float, false, false>), grid, dim3(256), 0, st, dA,
+                           (const float *)w_img, w_sed, (float *)drho);
+    }
     if (ev_main) (void)hipEventRecord(ev_main, st);
     if (nstar) hipLaunchKernelGGL(k_rt_star_adj<float>, dim3((nstar + 63) / 64), dim3(64), 0, st,
                                   dA, (const float *)w_img, w_sed, (float *)drho);

@@ -25,6 +25,7 @@ template <typename R>
 struct Pkt {
   R p[3], d[3];
   int c[3];
+  uint32_t fpk;  // sub-cube of a divided cube c (fine_pack), 0 in a whole cube
   int j, status;
   R rho;  // density of cell c after a flight that ends in an interaction
   uint64_t pid;
@@ -57,12 +58,16 @@ __device__ __forceinline__ void stat_add(unsigned long long *st, int i, unsigned
   atomicAdd(&st[i], v);
 }
 
+// Cell of a start point, in FP64 in both precisions: a source on a cell
+// vertex must land on the face decision exactly (in FP32, (p - origin) /
+// dcell can miss the integer by an ulp and start the packet one cell short,
+// adding a zero-length crossing).
 template <typename R>
 __device__ __forceinline__ void start_cell(const ModelDev &M, const R p[3], const R d[3], int c[3]) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    R q = (p[k] - (R)M.origin[k]) / (R)M.dcell;
-    R f = m_floor(q);
+    const double q = ((double)p[k] - M.origin[k]) / M.dcell;
+    const double f = floor(q);
     int ci = (int)f;
     if (q == f && d[k] < (R)0) ci -= 1;
     c[k] = ci;
@@ -179,13 +184,34 @@ __device__ __forceinline__ bool is_thin(const Ctx<R> &X, R rho) {
   }
 }
 
+// The same test for a leaf of edge h (refined grids).
+template <typename R>
+__device__ __forceinline__ bool is_thin_h(const Ctx<R> &X, R rho, double h) {
+  const ModelDev &M = *X.M;
+  return M.lucy_tau > 0.0 && rho > (R)0 && (double)rho * M.kext_max * h < M.lucy_tau;
+}
+
+// Leaf (cell index of every per-cell array) of packet P, its edge and volume.
+template <typename R>
+__device__ __forceinline__ int64_t pkt_leaf(const ModelDev &M, const Pkt<R> &P, double &h,
+                                            double &V) {
+  if (!M.ref) {
+    h = M.dcell;
+    V = M.V;
+    return ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0];
+  }
+  const int64_t c = leaf_of(M, P.c[0], P.c[1], P.c[2], P.fpk, &h);
+  V = (c < (int64_t)M.ncube) ? M.V : h * h * h;
+  return c;
+}
+
 __device__ __forceinline__ double energy_of(const ModelDev &M, int64_t q) {
   return (double)M.k[q] * M.xi + M.epath[q];
 }
 
 // Emission temperature of species s in cell c (see mcrt.h for the modes).
 template <typename R>
-__device__ double mode_T(Ctx<R> &X, int s, int64_t c, double rho) {
+__device__ double mode_T(Ctx<R> &X, int s, int64_t c, double rho, double V) {
   const ModelDev &M = *X.M;
   int64_t q = (int64_t)s * X.nc + c;
   if (M.mode == M_FROZEN) {
@@ -198,7 +224,7 @@ __device__ double mode_T(Ctx<R> &X, int s, int64_t c, double rho) {
   if (M.mode == M_BW_EPOCH) {
     T = M.tt[q];
     if (T < 0.0) {
-      double rhs = (M.esnap[q] + M.xi) / (4.0 * PI_D * frac * rho * M.V);
+      double rhs = (M.esnap[q] + M.xi) / (4.0 * PI_D * frac * rho * V);
       T = invert_T_exact(M.herm, X.dt, X.o, M.nl, s, rhs, &cl);
       M.tt[q] = T;  // every lane computes the same value from the snapshot
     }
@@ -207,7 +233,7 @@ __device__ double mode_T(Ctx<R> &X, int s, int64_t c, double rho) {
     // atomics while the kernel runs; any value since the kernel began is a
     // valid reading of the cell's energy so far)
     double e = (double)gld(&M.k[q]) * M.xi + gld(&M.epath[q]);
-    double rhs = (e + M.xi) / (4.0 * PI_D * frac * rho * M.V);
+    double rhs = (e + M.xi) / (4.0 * PI_D * frac * rho * V);
     T = invert_T_fast(M.herm, X.dt, X.o, M.nl, s, rhs, &cl);
   }
   if (cl) stat_add(X.st, 9, 1ull);
@@ -294,7 +320,11 @@ __device__ __forceinline__ void flight_setup(const Ctx<R> &X, const Pkt<R> &P, F
 // at the exit point). Each crossing leaves by the nearest face, ties going
 // to x, then y, then z; the step is written with selects so that lanes
 // leaving by different axes do not diverge.
-template <typename R, bool REC, bool I32>
+// PC: a new optical-depth draw on entering each cell (the footnote to the
+// sect. 2 interaction test): the packet interacts in the first cell whose
+// segment depth exceeds -ln(draw), at -ln(draw) / (rho kext) past the start
+// of that segment; cells are entered, and draw, in flight order.
+template <typename R, bool REC, bool I32, bool PC = false>
 __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   constexpr int K = Ahead<R>::K;
   const R p0x = P.p[0], p0y = P.p[1], p0z = P.p[2];
@@ -392,9 +422,14 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
       const R ell = ts[k + 1] - ts[k];
       const R dtau = rho * kx * ell;
       const bool thin = is_thin(X, rho);
-      if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tau_star) / tau_star));
-      if (tau + dtau > tau_star) {
-        tint = ts[k] + (tau_star - tau) / (rho * kx);
+      R tcur = tau_star;
+      if constexpr (PC) {
+        tau = (R)0;
+        tcur = -m_log(rng_u<R>(P.rng));
+      }
+      if (REC) upd_margin(P.mm, (double)(m_fabs(tau + dtau - tcur) / tcur));
+      if (tau + dtau > tcur) {
+        tint = ts[k] + (tcur - tau) / (rho * kx);
         rint = rho;
         kint = k;
         if (thin) lucy_deposit(X, P, lin(cs[k]), rho, tint - ts[k]);
@@ -426,6 +461,125 @@ __device__ int flight_batch(Ctx<R> &X, Pkt<R> &P, Flight<R> &F) {
   P.p[2] = p0z + t * dz;
   P.c[0] = cx; P.c[1] = cy; P.c[2] = cz;
   return 2;
+}
+
+// ------------------------------------------------ walk on refined grids
+// One level of refinement: the walk steps each cube's own lattice (a whole
+// cube is its own single sub-cube), one leaf per crossing, with the face
+// distances in FP64 in both precisions; leaving a divided cube happens on
+// the cube's own face. No look-ahead gathers: this walk serves refined
+// models, the bricked walk above the uniform grids.
+template <typename R>
+struct FlightRef {
+  double tm[3];  // distance to the current leaf's next face per axis
+  double t;      // distance walked from the flight origin
+  R tau, tstar, kx;
+  int c[3], f[3], r;
+};
+
+template <typename R>
+__device__ __forceinline__ void ref_faces(const ModelDev &M, const Pkt<R> &P, FlightRef<R> &F) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double dk = (double)P.d[k], pk = (double)P.p[k];
+    if (dk > 0.0) F.tm[k] = (face_pos(M, k, F.c[k], F.r, F.f[k] + 1) - pk) / dk;
+    else if (dk < 0.0) F.tm[k] = (face_pos(M, k, F.c[k], F.r, F.f[k]) - pk) / dk;
+    else F.tm[k] = m_inf<double>();
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void flight_setup_ref(const Ctx<R> &X, const Pkt<R> &P,
+                                                 FlightRef<R> &F, R tau_star) {
+  const ModelDev &M = *X.M;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    F.c[k] = P.c[k];
+    F.f[k] = fine_get(P.fpk, k);
+  }
+  F.r = cube_r(M, ((int64_t)F.c[2] * M.ny + F.c[1]) * M.nx + F.c[0]);
+  ref_faces(M, P, F);
+  F.t = 0.0;
+  F.tau = (R)0;
+  F.tstar = tau_star;
+  F.kx = X.rt[X.o.r_kext + P.j];
+}
+
+// Up to K leaf crossings of the flight (0: continue, 1: interaction, 2:
+// escape), in the order and arithmetic of a one-leaf-at-a-time walk.
+template <typename R, bool REC, bool PC>
+__device__ int flight_batch_ref(Ctx<R> &X, Pkt<R> &P, FlightRef<R> &F) {
+  const ModelDev &M = *X.M;
+  constexpr int K = 8;
+  for (int it = 0; it < K; ++it) {
+    int a = 0;
+    if (F.tm[1] < F.tm[a]) a = 1;
+    if (F.tm[2] < F.tm[a]) a = 2;
+    if (REC) {
+      double t2 = m_inf<double>();
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (k != a && F.tm[k] < t2) t2 = F.tm[k];
+      if (t2 < m_inf<double>() && t2 > 0.0) upd_margin(P.mm, (t2 - F.tm[a]) / t2);
+    }
+    double ell = F.tm[a] - F.t;
+    if (ell < 0.0) ell = 0.0;
+    double h;
+    const int64_t c = leaf_of(M, F.c[0], F.c[1], F.c[2], fine_pack(F.f[0], F.f[1], F.f[2]), &h);
+    const R rho = gld(X.rho + c);
+    const R dtau = rho * F.kx * (R)ell;
+    const bool thin = is_thin_h(X, rho, h);
+    R tcur = F.tstar;
+    if constexpr (PC) {
+      F.tau = (R)0;
+      tcur = -m_log(rng_u<R>(P.rng));
+    }
+    if (REC) upd_margin(P.mm, (double)(m_fabs(F.tau + dtau - tcur) / tcur));
+    if (F.tau + dtau > tcur) {
+      const double tint = F.t + (double)((tcur - F.tau) / (rho * F.kx));
+      if (thin) lucy_deposit(X, P, c, rho, (R)(tint - F.t));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        P.p[k] = (R)((double)P.p[k] + tint * (double)P.d[k]);
+        P.c[k] = F.c[k];
+      }
+      P.fpk = fine_pack(F.f[0], F.f[1], F.f[2]);
+      P.rho = rho;
+      return 1;
+    }
+    if (thin) lucy_deposit(X, P, c, rho, (R)ell);
+    F.tau += dtau;
+    if (F.tm[a] > F.t) F.t = F.tm[a];
+    P.n_cross++;
+    // cross the face on axis a
+    const double da = (double)P.d[a];
+    const int sa = da > 0.0 ? 1 : -1;
+    F.f[a] += sa;
+    if (F.f[a] >= 0 && F.f[a] < F.r) {
+      F.tm[a] = (face_pos(M, a, F.c[a], F.r, da > 0.0 ? F.f[a] + 1 : F.f[a]) - (double)P.p[a]) / da;
+      continue;
+    }
+    F.c[a] += sa;
+    const int na = a == 0 ? M.nx : (a == 1 ? M.ny : M.nz);
+    if (F.c[a] < 0 || F.c[a] >= na) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        P.p[k] = (R)((double)P.p[k] + F.t * (double)P.d[k]);
+        P.c[k] = F.c[k];
+      }
+      return 2;
+    }
+    // enter the next cube on its own lattice
+    F.r = cube_r(M, ((int64_t)F.c[2] * M.ny + F.c[1]) * M.nx + F.c[0]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double dk = (double)P.d[k];
+      if (k == a) F.f[k] = dk > 0.0 ? 0 : F.r - 1;
+      else F.f[k] = sub_index(M, k, F.c[k], F.r, (double)P.p[k] + F.t * dk, dk);
+    }
+    ref_faces(M, P, F);
+  }
+  return 0;
 }
 
 // Rosseland mean of the mixture opacity at T (sect. 3.2). The FP64 means
@@ -496,19 +650,20 @@ template <typename R, bool REC>
 __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
   const ModelDev &M = *X.M;
   if (!(M.mrw_tau > 0.0)) return false;
-  int64_t c = ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0];
+  double hl, Vl;
+  const int64_t c = pkt_leaf(M, P, hl, Vl);
   // the density of the cell came with the packet from its last flight
   double rho = P.rho > (R)0 ? (double)P.rho : (double)gld(X.rho + c);
   if (!(rho > 0.0)) return false;
-  if (!(rho * M.kext_max * M.dcell > M.mrw_tau)) return false;
+  if (!(rho * M.kext_max * hl > M.mrw_tau)) return false;
   int s0 = first_thermal(M);
   if (!REC && M.mode != M_FROZEN) {
     // B&W temperatures come from at least one packet's energy; when that
     // alone reaches Phi(T_TAB_MIN), T lies on the bound table and kappa_R
     // is below its largest entry, which may already rule the step out
     // without the temperature
-    const double rmin = M.xi / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * M.V);
-    if (rmin >= 1.001 * M.phi_tmin && !(rho * M.kr_gmax * M.dcell > M.mrw_tau)) return false;
+    const double rmin = M.xi / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * Vl);
+    if (rmin >= 1.001 * M.phi_tmin && !(rho * M.kr_gmax * hl > M.mrw_tau)) return false;
   }
   if (!REC && M.mode == M_BW_TICKET && M.mrw_ub) {
     // the table interval that Eq. 4 would take for this cell bounds kappa_R
@@ -516,32 +671,40 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
     // is inverted. The right-hand side is mode_T's.
     const int64_t q0 = (int64_t)s0 * X.nc + c;
     const double e = (double)gld(&M.k[q0]) * M.xi + gld(&M.epath[q0]);
-    const double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * M.V);
+    const double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * Vl);
     const double *h = M.herm + (size_t)s0 * (3 + 2 * NH_TAB);
     const float x = (__logf((float)rhs) - (float)h[0]) / (float)h[1];
     if (x >= 1.0f && x < (float)(NH_TAB - 3)) {
-      if (!(rho * gld(M.mrw_ub + (int)x) * M.dcell > M.mrw_tau)) return false;
+      if (!(rho * gld(M.mrw_ub + (int)x) * hl > M.mrw_tau)) return false;
     }
   }
-  double T0 = mode_T(X, s0, c, rho);
+  double T0 = mode_T(X, s0, c, rho, Vl);
   if (!REC) {
     // upper bound of kappa_R(T) on its table interval (build_tables proves
     // it): skip the exact mean when even the bound cannot reach the threshold
     const double lt0 = log(T_TAB_MIN), dlt = (log(T_MAX) - lt0) / (NT_TAB - 1);
     double xk = (log(T0) - lt0) / dlt;
     int k = (xk >= 0.0 && xk < (double)(NT_TAB - 1)) ? (int)xk : NT_TAB - 1;
-    if (!(rho * X.dt[X.o.krmax + k] * M.dcell > M.mrw_tau)) return false;
+    if (!(rho * X.dt[X.o.krmax + k] * hl > M.mrw_tau)) return false;
   }
   double kr = rosseland_mean(X.dt + X.o.w, X.dt + X.o.hnu, X.dt + X.o.a, X.dt + X.o.kext, M.nl, T0);
-  double taur = rho * kr * M.dcell;
+  double taur = rho * kr * hl;
   if (REC) upd_margin(P.mm, fabs(taur - M.mrw_tau) / M.mrw_tau);
   if (!(taur > M.mrw_tau)) return false;
   double Rs = 1e300;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     double pk = (double)P.p[k];
-    double lo = pk - (M.origin[k] + (double)P.c[k] * M.dcell);
-    double hi = (M.origin[k] + (double)(P.c[k] + 1) * M.dcell) - pk;
+    double lo, hi;
+    if (!M.ref) {
+      lo = pk - (M.origin[k] + (double)P.c[k] * M.dcell);
+      hi = (M.origin[k] + (double)(P.c[k] + 1) * M.dcell) - pk;
+    } else {
+      // the faces of the packet's leaf
+      const int r = cube_r(M, ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0]);
+      lo = pk - face_pos(M, k, P.c[k], r, fine_get(P.fpk, k));
+      hi = face_pos(M, k, P.c[k], r, fine_get(P.fpk, k) + 1) - pk;
+    }
     if (lo < Rs) Rs = lo;
     if (hi < Rs) Rs = hi;
   }
@@ -568,7 +731,7 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
 #pragma unroll
   for (int s = 0; s < MAX_NS; ++s) {
     if (s >= M.ns || s == M.pah) continue;
-    const double T = mode_T(X, s, c, rho);
+    const double T = mode_T(X, s, c, rho, Vl);
     Ts[s] = T;
     double kp = planck_mean(X.dt + X.o.w, X.dt + X.o.hnu, X.dt + X.o.a, X.dt + X.o.kabs + s * nl,
                             nl, T);
@@ -586,9 +749,9 @@ __device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
 }
 
 template <typename R>
-__device__ __forceinline__ int pah_row(const Ctx<R> &X, int64_t c, double rho) {
+__device__ __forceinline__ int pah_row(const Ctx<R> &X, int64_t c, double rho, double V) {
   const ModelDev &M = *X.M;
-  double q = (double)M.kpah[c] * M.xi / (4.0 * PI_D * X.dt[X.o.frac + M.pah] * rho * M.V);
+  double q = (double)M.kpah[c] * M.xi / (4.0 * PI_D * X.dt[X.o.frac + M.pah] * rho * V);
   int r = 0;
   while (r < M.nrows - 1 && q >= X.dt[X.o.pahe + r]) r++;
   return r;
@@ -720,8 +883,28 @@ __device__ void finish(Ctx<R> &X, Pkt<R> &P, bool walk_tallied = false) {
   }
 }
 
+// Photodissociation of the PAH in cell c (sect. 2.1, Eq. 8): its kpah
+// pass-1 absorptions of xi erg/s are shared by f_pah rho V / m_PAH
+// molecules (m_PAH = N_C 12 amu); each takes E_PAH = kpah xi m_PAH t_cool /
+// (f_pah rho V) within the cooling time, and E_PAH >= N_C/2 eV dissociates.
+constexpr double AMU_G = 1.66053906660e-24;
+constexpr double EV_ERG = 1.602176634e-12;
+template <typename R>
+__device__ __forceinline__ bool pah_dissociates(const Ctx<R> &X, int64_t c) {
+  const ModelDev &M = *X.M;
+  if (!(M.pah_nc > 0.0) || !(M.pah_tcool > 0.0)) return false;
+  const uint32_t kp = M.kpah[c];
+  if (kp == 0u) return false;
+  const double rho = (double)gld(X.rho + c);
+  const double mp = M.pah_nc * 12.0 * AMU_G;
+  const double e = (double)kp * M.xi * mp * M.pah_tcool /
+                   (X.dt[X.o.frac + M.pah] * rho * leaf_volume(M, (uint64_t)c));
+  return e >= 0.5 * M.pah_nc * EV_ERG;
+}
+
 // Start packet `idx` of the launch: source emission, or a PAH pass-2
-// packet born in the cell that owns it.
+// packet born in the cell that owns it (from the sources when that cell's
+// PAH dissociate).
 template <typename R, bool REC>
 __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
   const ModelDev &M = *X.M;
@@ -732,7 +915,9 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
   P.rho = (R)0;
   P.n_cross = P.n_scat = P.n_abs = P.n_mrw = P.n_lucy = P.n_int = 0;
   P.mm = 1e300;
+  P.fpk = 0u;
   stat_add(X.st, 0, 1ull);
+  int64_t c = -1;
   if (M.pass == 2) {
     // cell owning local packet index (first + idx) in the exclusive prefix of PAH counts
     uint64_t li = M.first + idx;
@@ -741,24 +926,43 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
       int64_t mid = (lo + hi + 1) >> 1;
       if (M.kpah_prefix[mid] <= li) lo = mid; else hi = mid - 1;
     }
-    int64_t c = lo;
-    int cc[3] = {(int)(c % M.nx), (int)((c / M.nx) % M.ny), (int)(c / ((int64_t)M.nx * M.ny))};
+    c = lo;
+  }
+  if (c >= 0 && !pah_dissociates(X, c)) {
     R u3[3];
     u3[0] = rng_u<R>(P.rng);
     u3[1] = rng_u<R>(P.rng);
     u3[2] = rng_u<R>(P.rng);
     double ul = rng_u<double>(P.rng), uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
+    if (c < (int64_t)M.ncube) {
+      int cc[3] = {(int)(c % M.nx), (int)((c / M.nx) % M.ny), (int)(c / ((int64_t)M.nx * M.ny))};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      P.c[k] = cc[k];
-      P.p[k] = (R)M.origin[k] + ((R)cc[k] + u3[k]) * (R)M.dcell;
+      for (int k = 0; k < 3; ++k) {
+        P.c[k] = cc[k];
+        P.p[k] = (R)M.origin[k] + ((R)cc[k] + u3[k]) * (R)M.dcell;
+      }
+    } else {
+      // uniform inside a sub-cube
+      int cc[3], ff[3], r;
+      leaf_loc(M, (uint64_t)c, cc, ff, &r);
+      const double h = M.dcell / (double)r;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        P.c[k] = cc[k];
+        P.p[k] = (R)(face_pos(M, k, cc[k], r, ff[k]) + (double)u3[k] * h);
+      }
+      P.fpk = fine_pack(ff[0], ff[1], ff[2]);
     }
-    P.j = pick_pah<R, REC>(X, pah_row(X, c, (double)gld(X.rho + c)), ul, P.mm);
+    P.j = pick_pah<R, REC>(X, pah_row(X, c, (double)gld(X.rho + c), leaf_volume(M, (uint64_t)c)),
+                           ul, P.mm);
     iso_dir<R>(uph, umu, P.d);
     return;
   }
   double uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
   double us = rng_u<double>(P.rng), ul = rng_u<double>(P.rng);
+  // m equal-energy source bins (Eq. 1): packet p draws inside stratum p mod m
+  if (M.src_strata > 0 && M.pass != 2)
+    ul = ((double)(P.pid % M.src_strata) + ul) / (double)M.src_strata;
   iso_dir<R>(uph, umu, P.d);
   int s = 0;
   if (M.nsrc > 1) s = pick_asc<double, REC>(X.dt + X.o.lum, 1, M.nsrc, us, P.mm);
@@ -767,8 +971,14 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
   P.j = pick_desc_cum<REC>(X.dt + X.o.srccum + s * nl, nl, ul, P.mm);
   start_cell<R>(M, P.p, P.d, P.c);
   if (P.c[0] < 0 || P.c[0] >= M.nx || P.c[1] < 0 || P.c[1] >= M.ny || P.c[2] < 0 ||
-      P.c[2] >= M.nz)
+      P.c[2] >= M.nz) {
     P.status = ST_ESCAPED;
+  } else if (M.ref) {
+    const int r = cube_r(M, ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0]);
+    P.fpk = fine_pack(sub_index(M, 0, P.c[0], r, (double)P.p[0], (double)P.d[0]),
+                      sub_index(M, 1, P.c[1], r, (double)P.p[1], (double)P.d[1]),
+                      sub_index(M, 2, P.c[2], r, (double)P.p[2], (double)P.d[2]));
+  }
 }
 
 // Start of a flight: modified random walk steps while they apply, then the
@@ -784,7 +994,24 @@ __device__ R flight_tau(Ctx<R> &X, Pkt<R> &P) {
       return (R)-1;
     }
   }
+  // per-cell draws are taken by the walk itself, cell by cell
+  if (M.tau_mode == 1) return (R)1;
   return -m_log(rng_u<R>(P.rng));
+}
+
+// A scattering event kept for any observer (sect. 4): with the HG phase
+// function expanded as P(d.k) = sum_l g^l sum_m Y_lm(d) Y_lm(k), the event
+// adds w g^l Y_lm(d_in) to the moments row of its cell and wavelength
+// (out of line: its loops stay out of the interaction kernel's registers).
+template <typename R>
+static __device__ __noinline__ void sh_deposit(R *row, int order, double dx, double dy, double dz,
+                                               double g, double w) {
+  double gp[MAX_SH_ORDER];
+  gp[0] = 1.0;
+  for (int l = 1; l < order; ++l) gp[l] = gp[l - 1] * g;
+  ylm_each(order, dx, dy, dz, [&](int i, int l, double y) {
+    gatomic_add(row + i, (R)(w * gp[l] * y));
+  });
 }
 
 // Interaction at P.p in cell P.c: albedo split, HG scattering with its
@@ -793,7 +1020,8 @@ template <typename R, bool REC>
 __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
   const ModelDev &M = *X.M;
   const int nl = M.nl, ns = M.ns;
-  int64_t c = ((int64_t)P.c[2] * M.ny + P.c[1]) * M.nx + P.c[0];
+  double hl, Vl;
+  const int64_t c = pkt_leaf(M, P, hl, Vl);
   R ualb = rng_u<R>(P.rng), usp = rng_u<R>(P.rng);
   const int j = P.j;
   const R alb = X.rt[X.o.r_alb + j];
@@ -811,6 +1039,11 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
         R add = (R)(M.xi / M.ssca_unit) * hg_phase<R>(g, cb);
         gatomic_add((R *)M.ssca + ((int64_t)v * X.nc + c) * M.nimg + q, add);
       }
+      if (M.sh_order > 0) {
+        const int nlm = M.sh_order * M.sh_order;
+        sh_deposit<R>((R *)M.sh + ((int64_t)c * M.nimg + q) * nlm, M.sh_order, (double)P.d[0],
+                      (double)P.d[1], (double)P.d[2], (double)g, M.xi / M.ssca_unit);
+      }
     }
     rotate_dir<R>(P.d, mu, (R)2 * (R)PI_D * uph);
     P.n_scat++;
@@ -826,24 +1059,24 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
         return;
       }
       double ul = rng_u<double>(P.rng), uph = rng_u<double>(P.rng), umu = rng_u<double>(P.rng);
-      P.j = pick_pah<R, REC>(X, pah_row(X, c, (double)P.rho), ul, P.mm);
+      P.j = pick_pah<R, REC>(X, pah_row(X, c, (double)P.rho, Vl), ul, P.mm);
       iso_dir<R>(uph, umu, P.d);
     } else {
       const R rho = P.rho;
-      bool thin = is_thin(X, rho);
+      const bool thin = M.ref ? is_thin_h(X, rho, hl) : is_thin(X, rho);
       int64_t qk = (int64_t)s * X.nc + c;
       double T;
       if (M.mode == M_BW_TICKET) {
         uint64_t kold = thin ? gld(&M.k[qk])
                              : gatomic_add(&M.k[qk], (uint64_t)1);
         double e = (double)kold * M.xi + gld(&M.epath[qk]);  // racy read, as in mode_T
-        double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s] * (double)rho * M.V);
+        double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s] * (double)rho * Vl);
         bool cl = false;
         T = invert_T_fast(M.herm, X.dt, X.o, nl, s, rhs, &cl);
         if (cl) stat_add(X.st, 9, 1ull);
       } else {
         if (!thin) gatomic_add(&M.k[qk], (uint64_t)1);
-        T = mode_T(X, s, c, (double)rho);
+        T = mode_T(X, s, c, (double)rho, Vl);
       }
       if (M.mode == M_BW_EPOCH) M.dirty[c] = 1;
       int jr = -1;
@@ -931,6 +1164,7 @@ __device__ __forceinline__ void q_store(const QBuf &b, uint32_t i, const Pkt<R> 
   b.pid[i] = P.pid;
   b.rngd[i] = P.rng.d;
   b.nint[i] = P.n_int;
+  if (b.fine) b.fine[i] = P.fpk;
   if (REC) {
     b.ncross[i] = P.n_cross; b.nscat[i] = P.n_scat; b.nabs[i] = P.n_abs;
     b.nmrw[i] = P.n_mrw; b.nlucy[i] = P.n_lucy;
@@ -954,6 +1188,7 @@ __device__ __forceinline__ R q_load(const ModelDev &M, const QBuf &b, uint32_t i
   rng_init(P.rng, M.seed, P.pid, (uint32_t)M.iter, (uint32_t)M.model_id, M.pass == 2 ? 3u : 0u);
   P.rng.d = gld(b.rngd + i);
   P.n_int = gld(b.nint + i);
+  P.fpk = b.fine ? gld(b.fine + i) : 0u;
   P.status = ST_ALIVE;
   P.n_cross = P.n_scat = P.n_abs = P.n_mrw = P.n_lucy = 0;
   P.mm = 1e300;
@@ -1108,7 +1343,7 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
 // interaction or out of the grid; the packet is written back to its own
 // entry. Lanes refill one by one from a wave-local chunk, so flights of
 // different lengths keep the wave busy.
-template <typename R, bool REC, bool I32>
+template <typename R, bool REC, bool I32, bool PC, bool REF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1128,7 +1363,7 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
       cnt = seg_count(c, fcur, s, S);
     };
     Pkt<R> P;
-    Flight<R> F;
+    typename std::conditional<REF, FlightRef<R>, Flight<R>>::type F;
     uint32_t mine = 0u;         // queue entry of the lane's packet
     uint32_t c0 = 0u, l0 = 0u;  // crossings and Lucy deposits before this flight
     uint32_t plo = 0u, phi = 0u;  // wave-local chunk of entries not yet started
@@ -1150,7 +1385,8 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
           if (i != 0xFFFFFFFFu) {
             mine = i;
             const R tau = q_load<R, REC>(M, qi, i, P);
-            flight_setup<R>(X, P, F, tau);
+            if constexpr (REF) flight_setup_ref<R>(X, P, F, tau);
+            else flight_setup<R>(X, P, F, tau);
             c0 = P.n_cross;
             l0 = P.n_lucy;
             state = 1;
@@ -1168,7 +1404,10 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
       }
       if (!__any(state != 2)) break;
       int r = 0;
-      if (state == 1) r = flight_batch<R, REC, I32>(X, P, F);
+      if (state == 1) {
+        if constexpr (REF) r = flight_batch_ref<R, REC, PC>(X, P, F);
+        else r = flight_batch<R, REC, I32, PC>(X, P, F);
+      }
       if (r != 0) {
         stat_add(X.st, 4, (unsigned long long)(P.n_cross - c0));
         if (P.n_lucy != l0) stat_add(X.st, 8, (unsigned long long)(P.n_lucy - l0));
@@ -1242,18 +1481,29 @@ size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, int occ_w
 
 template <typename R, bool REC>
 static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_full, int grid_walk,
-                      size_t lds_full, size_t lds_walk, bool idx32, const hipEvent_t *ev,
-                      hipStream_t st) {
+                      size_t lds_full, size_t lds_walk, bool idx32, bool per_cell, bool refined,
+                      const hipEvent_t *ev, hipStream_t st) {
   if (ev) (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((k_wf_emit<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
                      nmodels, fcur);
   if (ev) (void)hipEventRecord(ev[1], st);
-  if (idx32)
-    hipLaunchKernelGGL((k_wf_walk<R, REC, true>), dim3(grid_walk), dim3(256), lds_walk, st,
-                       d_models, nmodels, fcur);
+  // refined grids take the leaf walk; the per-cell draw variant of the
+  // bricked walk uses 64-bit cell indices on any grid
+  if (refined && per_cell)
+    hipLaunchKernelGGL((k_wf_walk<R, REC, false, true, true>), dim3(grid_walk), dim3(256),
+                       lds_walk, st, d_models, nmodels, fcur);
+  else if (refined)
+    hipLaunchKernelGGL((k_wf_walk<R, REC, false, false, true>), dim3(grid_walk), dim3(256),
+                       lds_walk, st, d_models, nmodels, fcur);
+  else if (per_cell)
+    hipLaunchKernelGGL((k_wf_walk<R, REC, false, true, false>), dim3(grid_walk), dim3(256),
+                       lds_walk, st, d_models, nmodels, fcur);
+  else if (idx32)
+    hipLaunchKernelGGL((k_wf_walk<R, REC, true, false, false>), dim3(grid_walk), dim3(256),
+                       lds_walk, st, d_models, nmodels, fcur);
   else
-    hipLaunchKernelGGL((k_wf_walk<R, REC, false>), dim3(grid_walk), dim3(256), lds_walk, st,
-                       d_models, nmodels, fcur);
+    hipLaunchKernelGGL((k_wf_walk<R, REC, false, false, false>), dim3(grid_walk), dim3(256),
+                       lds_walk, st, d_models, nmodels, fcur);
   if (ev) (void)hipEventRecord(ev[2], st);
   hipLaunchKernelGGL((k_wf_interact<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
                      nmodels, fcur);
@@ -1265,14 +1515,15 @@ static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_
 // four events) brackets the emission, walk and interaction kernels.
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
-                           bool idx32, const hipEvent_t *ev, hipStream_t st) {
+                           bool idx32, bool per_cell, bool refined, const hipEvent_t *ev,
+                           hipStream_t st) {
   hipLaunchKernelGGL(k_wf_plan, dim3(nmodels), dim3(64), 0, st, d_models, nmodels, fcur);
   if (fp64) {
-    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, ev, st);
-    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, ev, st);
+    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, ev, st);
+    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, ev, st);
   } else {
-    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, ev, st);
-    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, ev, st);
+    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, ev, st);
+    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, ev, st);
   }
   return hipGetLastError();
 }
@@ -1320,7 +1571,7 @@ hipError_t launch_wf_busy(const ModelDev *d_models, int nmodels, int fcur, uint3
 // reaches the end (no physical packet comes near it).
 constexpr uint32_t FINISH_MAX_EVENTS = 1u << 22;
 
-template <typename R, bool REC, bool I32>
+template <typename R, bool REC, bool I32, bool PC, bool REF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_wf_finish(const ModelDev *__restrict__ models, int nmodels, int fcur) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1344,7 +1595,7 @@ k_wf_finish(const ModelDev *__restrict__ models, int nmodels, int fcur) {
       const uint32_t i = lo + (uint32_t)lane;
       if (i >= hi) continue;
       Pkt<R> P;
-      Flight<R> F;
+      typename std::conditional<REF, FlightRef<R>, Flight<R>>::type F;
       R tau = q_load<R, REC>(M, qi, i, P);
       for (uint32_t ev = 0;; ++ev) {
         if (ev >= FINISH_MAX_EVENTS) {
@@ -1352,11 +1603,13 @@ k_wf_finish(const ModelDev *__restrict__ models, int nmodels, int fcur) {
           finish<R, REC>(X, P, true);
           break;
         }
-        flight_setup<R>(X, P, F, tau);
+        if constexpr (REF) flight_setup_ref<R>(X, P, F, tau);
+        else flight_setup<R>(X, P, F, tau);
         const uint32_t c0 = P.n_cross, l0 = P.n_lucy;
         int r;
         do {
-          r = flight_batch<R, REC, I32>(X, P, F);
+          if constexpr (REF) r = flight_batch_ref<R, REC, PC>(X, P, F);
+          else r = flight_batch<R, REC, I32, PC>(X, P, F);
         } while (r == 0);
         stat_add(X.st, 4, (unsigned long long)(P.n_cross - c0));
         if (P.n_lucy != l0) stat_add(X.st, 8, (unsigned long long)(P.n_lucy - l0));
@@ -1379,18 +1632,28 @@ k_wf_finish(const ModelDev *__restrict__ models, int nmodels, int fcur) {
 
 // Plan of the next round (no new packets remain) and the finishing kernel.
 hipError_t launch_wf_finish(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
-                            int grid, size_t lds, bool idx32, hipStream_t st) {
+                            int grid, size_t lds, bool idx32, bool per_cell, bool refined,
+                            hipStream_t st) {
   hipLaunchKernelGGL(k_wf_plan, dim3(nmodels), dim3(64), 0, st, d_models, nmodels, fcur);
-#define MCRT_FIN(RT, RC, IX)                                                                    \
-  hipLaunchKernelGGL((k_wf_finish<RT, RC, IX>), dim3(grid), dim3(256), lds, st, d_models, nmodels, \
-                     fcur)
+#define MCRT_FIN(RT, RC, IX, PC, RF)                                                             \
+  hipLaunchKernelGGL((k_wf_finish<RT, RC, IX, PC, RF>), dim3(grid), dim3(256), lds, st,          \
+                     d_models, nmodels, fcur)
+#define MCRT_FIN2(RT, RC)                                                                        \
+  do {                                                                                           \
+    if (refined && per_cell) MCRT_FIN(RT, RC, false, true, true);                                \
+    else if (refined) MCRT_FIN(RT, RC, false, false, true);                                      \
+    else if (per_cell) MCRT_FIN(RT, RC, false, true, false);                                     \
+    else if (idx32) MCRT_FIN(RT, RC, true, false, false);                                        \
+    else MCRT_FIN(RT, RC, false, false, false);                                                  \
+  } while (0)
   if (fp64) {
-    if (rec) { if (idx32) MCRT_FIN(double, true, true); else MCRT_FIN(double, true, false); }
-    else { if (idx32) MCRT_FIN(double, false, true); else MCRT_FIN(double, false, false); }
+    if (rec) MCRT_FIN2(double, true);
+    else MCRT_FIN2(double, false);
   } else {
-    if (rec) { if (idx32) MCRT_FIN(float, true, true); else MCRT_FIN(float, true, false); }
-    else { if (idx32) MCRT_FIN(float, false, true); else MCRT_FIN(float, false, false); }
+    if (rec) MCRT_FIN2(float, true);
+    else MCRT_FIN2(float, false);
   }
+#undef MCRT_FIN2
 #undef MCRT_FIN
   return hipGetLastError();
 }
@@ -1551,7 +1814,7 @@ __global__ void k_finalize_T(const ModelDev *__restrict__ md, double *T, double 
     double t = 0.0;
     if (s != M.pah && r > 0.0 && frac > 0.0) {
       bool cl = false;
-      double rhs = e / (4.0 * PI_D * frac * r * M.V);
+      double rhs = e / (4.0 * PI_D * frac * r * leaf_volume(M, c));
       t = (sizeof(R) == 8) ? invert_T_exact(M.herm, M.tab, o, M.nl, s, rhs, &cl)
                            : invert_T_fast(M.herm, M.tab, o, M.nl, s, rhs, &cl);
       if (cl) atomicAdd(&M.stats[9], 1ull);
@@ -1573,9 +1836,17 @@ __global__ void k_init_T(const ModelDev *__restrict__ md, double *T) {
   uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const int nl = M.nl;
   for (; i < M.ncell; i += stride) {
-    int cc[3] = {(int)(i % M.nx), (int)((i / M.nx) % M.ny), (int)(i / ((uint64_t)M.nx * M.ny))};
     double x[3];
-    for (int k = 0; k < 3; ++k) x[k] = M.origin[k] + ((double)cc[k] + 0.5) * M.dcell;
+    if (i < M.ncube) {
+      int cc[3] = {(int)(i % M.nx), (int)((i / M.nx) % M.ny), (int)(i / ((uint64_t)M.nx * M.ny))};
+      for (int k = 0; k < 3; ++k) x[k] = M.origin[k] + ((double)cc[k] + 0.5) * M.dcell;
+    } else {
+      // centre of a sub-cube
+      int cc[3], ff[3], r;
+      leaf_loc(M, i, cc, ff, &r);
+      const double h = M.dcell / (double)r;
+      for (int k = 0; k < 3; ++k) x[k] = face_pos(M, k, cc[k], r, ff[k]) + 0.5 * h;
+    }
     double r2[MAX_SRC];
     for (int s = 0; s < M.nsrc; ++s) {
       const double *ps = M.tab + o.srcpos + 3 * s;

@@ -1,5 +1,5 @@
 // mcrt_voxel.hip - model set-up kernels: density grids of the clumpy AGN
-// torus (sect. 6, Eq. 21 clump centres) and of the r^-2 spherical shell.
+// torus (sect. 6, Eq. 21 clump centres) and of power-law spherical shells.
 #include "mcrt_internal.h"
 
 namespace mcrt {
@@ -46,11 +46,12 @@ __global__ void k_vox_torus(int nx, int ny, int nz, double ox, double oy, double
   rho[i] = (R)v;
 }
 
-// Cell average of rho0 (r_in/r)^2 on [r_in, r_out] by a product
-// Gauss-Legendre rule with the nodes/weights given.
+// Cell average of rho0 (r_in/r)^power on [r_in, r_out] (power 2: r^-2
+// shell, 0: constant density) by a product Gauss-Legendre rule with the
+// nodes/weights given.
 template <typename R>
 __global__ void k_vox_shell(int nx, int ny, int nz, double ox, double oy, double oz, double dc,
-                            double rho0, double r_in, double r_out, int ng,
+                            double rho0, double r_in, double r_out, double power, int ng,
                             const double *__restrict__ gx, const double *__restrict__ gw, R *rho) {
   uint64_t n = (uint64_t)nx * ny * nz;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,7 +65,11 @@ __global__ void k_vox_shell(int nx, int ny, int nz, double ox, double oy, double
         double y = oy + ((double)iy + 0.5 + 0.5 * gx[b]) * dc;
         double z = oz + ((double)iz + 0.5 + 0.5 * gx[e]) * dc;
         double r = sqrt(x * x + y * y + z * z);
-        double f = (r >= r_in && r <= r_out) ? rho0 * (r_in / r) * (r_in / r) : 0.0;
+        double f = 0.0;
+        if (r >= r_in && r <= r_out) {
+          const double q = r_in / r;
+          f = power == 2.0 ? rho0 * q * q : (power == 0.0 ? rho0 : rho0 * pow(q, power));
+        }
         sum += gw[a] * gw[b] * gw[e] * f;
       }
   rho[i] = (R)(0.125 * sum);
@@ -88,16 +93,16 @@ hipError_t launch_vox_torus(bool fp64, int nx, int ny, int nz, const double o[3]
 }
 
 hipError_t launch_vox_shell(bool fp64, int nx, int ny, int nz, const double o[3], double dc,
-                            double rho0, double r_in, double r_out, int ng, const double *dgx,
-                            const double *dgw, void *rho, hipStream_t st) {
+                            double rho0, double r_in, double r_out, double power, int ng,
+                            const double *dgx, const double *dgw, void *rho, hipStream_t st) {
   uint64_t n = (uint64_t)nx * ny * nz;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (fp64)
     hipLaunchKernelGGL(k_vox_shell<double>, grid, block, 0, st, nx, ny, nz, o[0], o[1], o[2], dc,
-                       rho0, r_in, r_out, ng, dgx, dgw, (double *)rho);
+                       rho0, r_in, r_out, power, ng, dgx, dgw, (double *)rho);
   else
     hipLaunchKernelGGL(k_vox_shell<float>, grid, block, 0, st, nx, ny, nz, o[0], o[1], o[2], dc,
-                       rho0, r_in, r_out, ng, dgx, dgw, (float *)rho);
+                       rho0, r_in, r_out, power, ng, dgx, dgw, (float *)rho);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ RT_SOURCES = ("csrc/mcrt_raytrace.hip", "csrc/mcrt_rtargs.h", "csrc/mcrt_interna
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_wf_walk_torus256_1e8_traffic.md")
 RT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raytrace_torus256_512px_traffic.md")
 RT_KERNELS = ("k_build_S", "k_rt_fwd", "k_rt_adj")
-TRANSPORT_KERNEL = "k_wf_walk<float, false, true>"
+TRANSPORT_KERNEL = "k_wf_walk<float, false, true, false, false>"
 CALIB_KERNEL = "MulFunctor"
 
 
