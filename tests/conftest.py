@@ -16,5 +16,10 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def orc():
     from oracle import oracle
-    oracle.build(force=False)
+    lib = os.environ.get("MCRT_ORACLE_LIB")
+    if lib:
+        # a separately built oracle (the sanitizer run sets this)
+        oracle.use_library(lib)
+    else:
+        oracle.build(force=False)
     return oracle

@@ -11,11 +11,12 @@ def gpu_context(mi, precision="fp64", views=None, img_idx=None, distance=1.0):
     return ctx
 
 
-def compare_records(rg, ro, tol=1e-6, scale=1.0, allow_frac=1e-6):
+def compare_records(rg, ro, tol=1e-6, scale=1.0, allow_frac=1e-6, pos_tol=None):
     """Per-packet parity: same status, wavelength and event counts; escape
-    point and direction within tol. Packets whose closest decision lies
-    within 1e-9 of a tie on either side may legitimately differ; they must
-    be rarer than allow_frac (at least one allowed when N is small)."""
+    point (within pos_tol, default tol, of `scale`) and direction within tol.
+    Packets whose closest decision lies within 1e-9 of a tie on either side
+    may legitimately differ; they must be rarer than allow_frac (at least one
+    allowed when N is small)."""
     assert len(rg) == len(ro)
     assert np.array_equal(rg["pid"], ro["pid"])
     same = ((rg["status"] == ro["status"]) & (rg["j"] == ro["j"])
@@ -25,7 +26,7 @@ def compare_records(rg, ro, tol=1e-6, scale=1.0, allow_frac=1e-6):
     dp = np.linalg.norm(rg["pos"] - ro["pos"], axis=1) / scale
     dd = np.linalg.norm(rg["dir"] - ro["dir"], axis=1)
     dw = np.abs(rg["weight"] - ro["weight"]) / np.abs(ro["weight"])
-    same &= (dp <= tol) & (dd <= tol) & (dw <= tol)
+    same &= (dp <= (tol if pos_tol is None else pos_tol)) & (dd <= tol) & (dw <= tol)
     near = np.minimum(rg["min_margin"], ro["min_margin"]) < 1e-9
     bad = ~same & ~near
     diverged = ~same & near

@@ -32,11 +32,29 @@ def test_library_exports_every_declared_symbol():
         assert n in _lib.SIGNATURES, f"binding lacks {n}"
 
 
-def test_binding_structs_match_header_sizes():
+def test_binding_structs_match_header_layout(tmp_path):
+    """Size and every field offset of the ctypes structures against the C
+    compiler's layout of include/mcrt.h."""
+    import subprocess
     from paper_1203_2941_amd import _lib
-    assert C.sizeof(_lib.PacketRecord) == 120
-    assert C.sizeof(_lib.RunOpts) == 80
-    assert C.sizeof(_lib.RunStats) == 88
+    structs = {"mcrt_packet_record": _lib.PacketRecord, "mcrt_run_opts": _lib.RunOpts,
+               "mcrt_run_stats": _lib.RunStats}
+    inc = os.path.join(ROOT, "include")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mcrt.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, "-o", str(exe), str(src)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
 
 
 def test_create_without_device_reports_error():

@@ -77,3 +77,30 @@ def test_autotuner_picks_a_candidate(tmp_path, monkeypatch):
     assert res["packets_per_s"] > 0
     again = autotune.tune(ctxs, [m.n_packets for m in ms], [m.seed for m in ms], mode="bw_ticket")
     assert again == res  # served from the cache
+
+
+def test_batch_against_oracle(orc):
+    """A batch of two tori and a refined cube (the leaf walk then serves
+    every model), single FROZEN pass from the thin-limit temperatures,
+    against the oracle per model: absorption, PAH and SED counts agree up to
+    packets that sit within 1e-9 of a decision tie (a handful at most)."""
+    import paper_1203_2941_amd as mc
+    from tests.test_oracle_refinement import refined_cube
+    rc = refined_cube(n=(6, 5, 7), seed=31, frac=0.4, rmax=3, tau=2.0)
+    rc.n_packets = 15000
+    ms = models()[:2] + [rc]
+    ctxs = [gpu_context(m) for m in ms]
+    for c in ctxs:
+        c.init_temperatures()
+    st = mc.run_batch(ctxs, [m.n_packets for m in ms], [m.seed for m in ms], mode="frozen",
+                      n_iter=1)
+    for c, m, s in zip(ctxs, ms, st):
+        o = orc.Oracle(m)
+        o.init_T()
+        o.run(mode=orc.FROZEN, n_iter=1, n_total=m.n_packets)
+        k, ep, kp = c.tallies()
+        assert s["packets"] == m.n_packets
+        assert np.abs(k.astype(np.int64) - o.k.astype(np.int64)).sum() <= 4
+        assert np.abs(kp.astype(np.int64) - o.kpah.astype(np.int64)).sum() <= 4
+        assert np.abs(c.sed()[1].astype(np.int64) - o.sed.astype(np.int64)).sum() <= 4
+        assert abs(s["crossings"] - o.stats["crossings"]) <= 1e-5 * o.stats["crossings"]

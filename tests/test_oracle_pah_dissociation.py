@@ -23,7 +23,7 @@ def t_star(o, m, c):
     the power one molecule absorbs (kpah xi over f rho V / (N_C 12 amu)
     molecules) times t."""
     V = m.dcell**3
-    per_gram = o.kpah[c] * o.xi() / (m.mass_frac[m.pah_species] * m.rho.ravel()[c] * V)
+    per_gram = o.kpah[c] * o.xi() / (m.mass_frac[m.pah_species] * o.rho.ravel()[c] * V)
     return 0.5 * EV / (12.0 * AMU * per_gram)
 
 
