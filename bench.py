@@ -176,6 +176,11 @@ def main():
                     help="walk precision of the context (the benchmark line is fp32)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one elementwise copy of this many MiB first (counter calibration)")
+    ap.add_argument("--workload", choices=("torus", "replica", "batch", "shell"), default="torus",
+                    help="torus: the benchmark step (default); replica: the sect. 3.6 run-time "
+                         "comparison (Table 1) on its constant-density envelope; batch: 64 "
+                         "uneven torus models in one batched launch against per-model launches; "
+                         "shell: the 128^3 r^-2 shell at tau_V 1, 10, 100, FP32 against FP64")
     ap.add_argument("--cpu-worker", nargs=5, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
@@ -185,6 +190,15 @@ def main():
         print("bench.py runs on one GPU only (the method is not sharded here); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "replica":
+        replica(args)
+        return
+    if args.workload == "batch":
+        batch(args)
+        return
+    if args.workload == "shell":
+        shell(args)
+        return
 
     import torch
 
@@ -353,7 +367,7 @@ def main():
                      "rounds": n_walk},
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_wf_walk<{tn}, false, true>",
+            "kernel": f"k_wf_walk<{tn}, false, true, false, false>",
             "achieved": b_alg / t_walk / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
@@ -373,9 +387,9 @@ def main():
                                     "interaction (wavefront queues; not the method's bytes)",
         },
         "roofline_raytrace": {
-            "build_S": roof(f"k_build_S<{tn}>", b_S, t_S, "k_build_S"),
-            "forward": roof(f"k_rt_fwd<{tn}>", b_fwd, t_fk, "k_rt_fwd"),
-            "adjoint": roof(f"k_rt_adj<{tn}>", b_adj, t_ak, "k_rt_adj"),
+            "build_S": roof(f"k_build_S<{tn}, false, false>", b_S, t_S, "k_build_S"),
+            "forward": roof(f"k_rt_fwd<{tn}, false, false>", b_fwd, t_fk, "k_rt_fwd"),
+            "adjoint": roof(f"k_rt_adj<{tn}, false, false>", b_adj, t_ak, "k_rt_adj"),
             "bytes_rule": "compulsory: each array once per launch (density and source "
                           "functions per view, images, weights, gradient; for S: temperatures, "
                           "density, scattering sums in and S out)",
@@ -462,6 +476,254 @@ def accuracy(args, m, views, idx, D, ctx32, opts):
            "note": "per output: FP32 path against the FP64 path on the benchmark torus; the "
                    "second block is the Monte Carlo noise at this packet count"}
     return fp64_path, err
+
+
+# Table 1 of the paper (minutes for 1e7 packets on the sect. 3.6 envelope,
+# 1e6 cells; 2012 hardware: one 3 GHz core, 8 threads, a 256-core GPU).
+TABLE1_MIN = {"Lucy, 1 thread": 180, "B&W, 1 thread": 60, "Lucy, 8 threads": 45,
+              "B&W, 8 threads": 20, "GPU (iterative)": 3, "GPU+Lucy": 4, "GPU+B&W": 2,
+              "GPU+B&W+Lucy": 2}
+
+
+def replica(args):
+    """The run-time comparison of sect. 3.6 on its own model: a 2500 K, 1 L_sun
+    star in a constant-density envelope (0.7-700 AU, tau_V = 10, 100^3 cells),
+    1e7 packets per pass. The GPU runs the variants of Table 1 (iterative
+    scheme with three passes from the thin-limit temperatures, with and
+    without Lucy's estimator; immediate B&W with and without Lucy); the FP64
+    oracle (serial B&W, Lucy off and on) is timed on one core on a sample and
+    scaled to 1e7 packets. Prints one JSON line."""
+    import torch
+
+    import mcrt_inputs as mi
+    import paper_1203_2941_amd as mc
+    from oracle import oracle
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    N = args.packets if args.packets != 100_000_000 else 10_000_000
+    m = mi.replica(n=100, n_packets=N)
+    ctx = mc.Context(0, args.precision).from_inputs(m)
+    variants = {
+        "GPU (iterative)": dict(mode="frozen", n_iter=3, lucy_tau=0.0),
+        "GPU+Lucy": dict(mode="frozen", n_iter=3, lucy_tau=1e-2),
+        "GPU+B&W": dict(mode="bw_ticket", lucy_tau=0.0),
+        "GPU+B&W+Lucy": dict(mode="bw_ticket", lucy_tau=1e-2),
+    }
+    out_v = {}
+    for name, kw in variants.items():
+        times, stats = [], None
+        for k in range(args.warmup + args.steps):
+            ctx.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if kw["mode"] == "frozen":
+                ctx.init_temperatures()
+            st = ctx.run_packets(0, N, 100 + k, n_total=N, mrw_tau=0.0, **kw)
+            ctx.finalize_temperatures()
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(time.perf_counter() - t0)
+                stats = st
+        sec = float(np.median(times))
+        passes = kw.get("n_iter", 1) if kw["mode"] == "frozen" else 1
+        out_v[name] = {"seconds": sec, "passes": passes, "packets_per_pass": N,
+                       "packets_per_s": passes * N / sec,
+                       "crossings": int(stats["crossings"]),
+                       "paper_minutes": TABLE1_MIN[name],
+                       "speedup_vs_paper": TABLE1_MIN[name] * 60.0 / sec}
+        log(f"replica {name}: {sec:.3f} s ({passes} x {N} packets)")
+    # CPU oracle, one core, serial B&W (one packet per epoch), scaled
+    cpu = {}
+    n_cpu = max(1000, min(args.cpu_sample, 20000))
+    if not args.no_cpu_baseline:
+        o = oracle.Oracle(m)
+        for name, lt in (("B&W, 1 thread", 0.0), ("Lucy+B&W, 1 thread", 1e-2)):
+            o.reset()
+            t0 = time.perf_counter()
+            o.run(n=n_cpu, mode=oracle.BW_EPOCH, epoch=1, lucy_tau=lt, n_total=N)
+            dt = time.perf_counter() - t0
+            cpu[name] = {"sample_packets": n_cpu, "seconds": dt,
+                         "scaled_minutes_1e7": dt * (N / n_cpu) / 60.0,
+                         "paper_minutes": TABLE1_MIN.get(name)}
+            log(f"replica cpu {name}: {dt:.2f} s for {n_cpu} packets")
+    best = min(out_v.values(), key=lambda v: v["seconds"])
+    print(json.dumps({
+        "metric": "run time of the sect. 3.6 comparison (Table 1 replica)",
+        "value": best["seconds"], "unit": "s", "higher_is_better": False,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": (f"constant-density envelope 0.7-700 AU, tau_V = 10, "
+                                f"{m.nx}^3 cells, 2500 K 1 L_sun star, Ivezic 1D dust law, "
+                                f"{m.nl} wavelengths, {N} packets per pass")},
+        "variants": out_v, "cpu_oracle": cpu,
+        "paper_table1_minutes": TABLE1_MIN,
+        "note": "paper times are for 2012 hardware (context, not a target)",
+    }), flush=True)
+
+
+def batch(args):
+    """64 uneven clumpy-torus models (grids 64^3-192^3, 200-1e4 clumps, 40-100
+    wavelengths, 1e6-1e7 packets each, about 2.5e8 in all): one batched
+    launch (every model in each wavefront round, rounds replayed from a HIP
+    graph) against the same models launched one after the other. FP32 walk,
+    immediate B&W, MRW armed. Prints one JSON line."""
+    import torch
+
+    import mcrt_inputs as mi
+    import paper_1203_2941_amd as mc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    specs = mi.batch_specs(64, seed=4)
+    ctxs, npk, seeds = [], [], []
+    t0 = time.perf_counter()
+    for s in specs:
+        m = mi.torus(n=s["n"], n_clumps=s["n_clumps"], nl=s["nl"], n_packets=s["n_packets"],
+                     seed=s["seed"], geo_seed=s["geo_seed"])
+        ctxs.append(mc.Context(0, args.precision).from_inputs(m))
+        npk.append(s["n_packets"])
+        seeds.append(s["seed"])
+    torch.cuda.synchronize()
+    log(f"batch: 64 models set up in {time.perf_counter() - t0:.1f} s, {sum(npk)} packets")
+    opts = dict(mode="bw_ticket", mrw_tau=50.0, mrw_gamma=2.0, lucy_tau=1e-2,
+                queue_depth=args.queue_depth or (1 << 20))
+    times = []
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = mc.run_batch(ctxs, npk, [s + 1000 * k for s in seeds], **opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert all(x["escaped"] + x["killed"] + x["pah_stopped"] == n for x, n in zip(st, npk))
+        if k >= args.warmup:
+            times.append(dt)
+        log(f"batched run {k}: {dt:.3f} s")
+    seq = []
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c, n, s in zip(ctxs, npk, seeds):
+            c.reset()
+            c.run_packets(0, n, s + 1000 * k, n_total=n, **opts)
+            c.finalize_temperatures()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if k >= args.warmup:
+            seq.append(dt)
+        log(f"per-model runs {k}: {dt:.3f} s")
+    tb, ts = float(np.median(times)), float(np.median(seq))
+    total = sum(npk)
+    print(json.dumps({
+        "metric": "photon packets/s, 64-model batch", "value": total / tb, "unit": "packets/s",
+        "higher_is_better": True, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": tb * 1e3, "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": ("64 clumpy-torus models: grids 64^3-192^3, 200-1e4 clumps, "
+                                "40-100 wavelengths, 1e6-1e7 packets each; immediate B&W, "
+                                "MRW tau_R > 50, PAH"),
+                   "packets": total, "queue_depth": opts["queue_depth"]},
+        "batched_s": tb, "per_model_s": ts, "per_model_packets_per_s": total / ts,
+        "batch_speedup": ts / tb,
+        "note": "per-model runs include a tally reset and Eq. 4 per model, as the batch does",
+    }), flush=True)
+
+
+def tally_diffs(a, b, nth):
+    """Temperature, absorbed-energy and SED differences of run a against run b
+    (thermal species 0..nth-1; SED counts by polar bin and wavelength)."""
+    k = (a["E"][:nth] > 0) & (b["E"][:nth] > 0)
+    w = a["E"][:nth][k]
+    dT = np.abs(a["T"][:nth][k] / b["T"][:nth][k] - 1.0)
+    sa, sb = a["sed"], b["sed"]
+    ok = (sa + sb) > 50
+    return {
+        "T_rel_energy_weighted": float(np.sum(w * dT) / np.sum(w)),
+        "T_rel_median": float(np.median(dT)),
+        "E_total_rel": [float(a["E"][s].sum() / b["E"][s].sum() - 1.0) for s in range(nth)],
+        "sed_counts_chi2_per_bin": float(np.sum((sa[ok] - sb[ok]) ** 2 / (sa[ok] + sb[ok]))
+                                         / max(ok.sum(), 1)),
+        "crossings_per_packet_rel": float(a["st"]["crossings"] / b["st"]["crossings"] - 1.0),
+    }
+
+
+def shell(args):
+    """The r^-2 shell of the sect. 3.6 and 5.1 comparisons on 128^3 cells
+    (R_in = 1 AU to 1000 R_in, 2500 K 1 L_sun star, two species) at radial
+    tau_V = 1, 10 and 100 with 1e7 packets each: FP32 and FP64 transport rates
+    (immediate B&W, Lucy and diffusion steps armed, Eq. 4 included), the FP32
+    outputs against FP64 beside the FP64 seed-to-seed noise, and the oracle's
+    rate (serial B&W) on a sample of about 10 s per optical depth. Prints one
+    JSON line; `value` is the FP32 rate at tau_V = 10."""
+    import torch
+
+    import mcrt_inputs as mi
+    import paper_1203_2941_amd as mc
+    from oracle import oracle
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    N = args.packets if args.packets != 100_000_000 else 10_000_000
+    n = args.grid if args.grid != 256 else 128
+    opts = dict(mode="bw_ticket", n_total=N, mrw_tau=50.0, mrw_gamma=2.0, lucy_tau=1e-2,
+                max_interactions=10_000_000, sed_theta_bins=10)
+    res = {}
+    for tau in (1.0, 10.0, 100.0):
+        m = mi.shell(n=n, tau_v=tau, n_packets=N)
+        ctx = {p: mc.Context(0, p).from_inputs(m) for p in ("fp32", "fp64")}
+
+        def run(c, seed):
+            c.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = c.run_packets(0, N, seed, **opts)
+            c.finalize_temperatures()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            T, E = c.temperatures(with_energy=True)
+            _, cnt = c.sed()
+            return {"st": st, "s": dt, "T": T, "E": E, "sed": cnt.astype(np.float64)}
+
+        for p in ctx:
+            run(ctx[p], 1)  # warm-up
+        r32, r64, r64b = run(ctx["fp32"], 11), run(ctx["fp64"], 11), run(ctx["fp64"], 12)
+        del ctx
+        torch.cuda.empty_cache()
+        log(f"shell tau_V {tau:g}: FP32 {r32['s']:.3f} s, FP64 {r64['s']:.3f} s for {N} packets")
+        cpu = None
+        if not args.no_cpu_baseline:
+            o = oracle.Oracle(m)
+            done, t0 = 0, time.perf_counter()
+            while time.perf_counter() - t0 < 10.0 and done < N:
+                k = min(500, N - done)
+                o.run(first=done, n=k, seed=11, mode=oracle.BW_EPOCH, epoch=1, n_total=N,
+                      lucy_tau=1e-2, mrw_tau=50.0, mrw_gamma=2.0, max_int=10_000_000)
+                done += k
+            dt = time.perf_counter() - t0
+            cpu = {"kind": "oracle", "cores": 1, "sample_packets": done, "seconds": dt,
+                   "packets_per_s": done / dt,
+                   "crossings_per_s": o.stats["crossings"] / dt}
+            log(f"shell tau_V {tau:g}: oracle {done} packets in {dt:.1f} s")
+        res[f"{tau:g}"] = {
+            "fp32": {"seconds": r32["s"], "packets_per_s": N / r32["s"],
+                     "crossings_per_s": r32["st"]["crossings"] / r32["s"],
+                     "events": {k: int(v) for k, v in r32["st"].items() if k != "kernel_ms"}},
+            "fp64": {"seconds": r64["s"], "packets_per_s": N / r64["s"],
+                     "crossings_per_s": r64["st"]["crossings"] / r64["s"]},
+            "fp32_vs_fp64_same_seed": tally_diffs(r32, r64, m.ns),
+            "fp64_vs_fp64_other_seed": tally_diffs(r64b, r64, m.ns),
+            "cpu_oracle": cpu,
+        }
+    v = res["10"]["fp32"]["packets_per_s"]
+    print(json.dumps({
+        "metric": "photon packets/s, r^-2 shell", "value": v, "unit": "packets/s",
+        "higher_is_better": True, "n_gpus": 1, "steps": 1, "warmup": 1,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"r^-2 shell {n}^3, R_in 1 AU to 1000 R_in, 2500 K 1 L_sun star, "
+                                f"two species, 100 wavelengths, {N} packets per optical depth; "
+                                f"immediate B&W, Lucy 1e-2, diffusion steps above 50"),
+                   "value_at_tau_v": 10},
+        "tau_v": res,
+        "note": "timed: reset, transport and Eq. 4 per run (FP32 walk or FP64 walk); the FP64 "
+                "second seed gives the Monte Carlo noise the FP32 differences stand beside",
+    }), flush=True)
 
 
 if __name__ == "__main__":

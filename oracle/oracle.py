@@ -25,13 +25,19 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 
 
-def build(force: bool = True, out: str = None, native: bool = False) -> str:
+def build(force: bool = True, out: str = None, native: bool = False,
+          sanitize: bool = False) -> str:
     """Compile the oracle with gcc (FP64, no contraction, no value-changing
     optimisation). native=True adds -O3 -march=native for timing on the
-    machine that runs it (same IEEE arithmetic, written to `out`)."""
+    machine that runs it (same IEEE arithmetic, written to `out`).
+    sanitize=True builds with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal); the process that loads it must preload libasan."""
     path = out or LIB_PATH
     if force or not os.path.exists(path):
         opt = ["-O3", "-march=native"] if native else ["-O2"]
+        if sanitize:
+            opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                   "-fno-sanitize-recover=all"]
         cmd = ["gcc", *opt, "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
                "-fno-fast-math", "-o", path, SRC, "-lm"]
         subprocess.check_call(cmd, cwd=HERE)
