@@ -33,8 +33,9 @@ hipError_t launch_brick(bool fp64, const void *rho, void *rb, int nx, int ny, in
                         int nby, hipStream_t st);
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
-                           bool idx32, bool per_cell, bool refined, const hipEvent_t *ev,
-                           hipStream_t st);
+                           bool idx32, bool per_cell, bool refined, int fast,
+                           const hipEvent_t *ev, hipStream_t st);
+hipError_t launch_mrw_cand(const ModelDev *d_models, int nmodels, int ncu, hipStream_t st);
 size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, int occ_words, bool fp64);
 hipError_t launch_occ(bool fp64, const void *rb, uint32_t *occ, uint64_t ncell_b, int osh,
                       hipStream_t st);
@@ -98,11 +99,14 @@ struct mcrt_ctx {
   std::vector<double> h_tab;
   double kext_max = 0.0, ltot = 0.0;
   double kr_gmax = 0.0, phi_tmin = 0.0;  // MRW pre-test bounds (see build_tables)
+  double herm_pmin[MAX_NS] = {0.0, 0.0, 0.0, 0.0};  // lower ends of the Hermite tables
   double *d_tab = nullptr;
   void *d_rtab = nullptr;
   int32_t *d_imgmap = nullptr;
   double *d_herm = nullptr;
   double *d_mrw_ub = nullptr;  // MRW pre-test bound per herm node interval (FP32 walk)
+  uint32_t *d_mrw_flags = nullptr;  // candidate and current diffusion bits, [2][words]
+  size_t mrw_flags_cap = 0;         // words per half
   float *d_rej_pe = nullptr;   // FP32 re-emission proposal tables (alias prob, envelope)
   uint8_t *d_rej_al = nullptr;
   size_t tab_cap = 0, rtab_cap = 0;
@@ -281,7 +285,7 @@ extern "C" void mcrt_destroy(mcrt_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_occ, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_mrw_ub, ctx->d_rej_pe, ctx->d_rej_al, ctx->d_k, ctx->d_epath,
+  void *ps[] = {ctx->d_rho, ctx->d_rho_b, ctx->d_occ, ctx->d_tab, ctx->d_rtab, ctx->d_imgmap, ctx->d_herm, ctx->d_mrw_ub, ctx->d_mrw_flags, ctx->d_rej_pe, ctx->d_rej_al, ctx->d_k, ctx->d_epath,
                 ctx->d_T, ctx->d_esnap, ctx->d_tt, ctx->d_tmp, ctx->d_dirty, ctx->d_kpah,
                 ctx->d_prefix, ctx->d_sed, ctx->d_ssca, ctx->d_rec, ctx->d_ctl, ctx->d_q, ctx->d_stats,
                 ctx->d_model, ctx->d_S, ctx->d_rt, ctx->d_img_tmp, ctx->d_sed_tmp, ctx->d_batch,
@@ -598,10 +602,14 @@ static mcrt_status build_tables(mcrt_ctx *ctx) {
     double *hh = &herm[(size_t)s * HS];
     if (!(p0 > 0.0) || !(p1 > p0)) {
       hh[0] = 0.0; hh[1] = 1.0; hh[2] = 0.0;  // empty table: always the Newton path
+      ctx->herm_pmin[s] = HUGE_VAL;
       continue;
     }
     double u0 = std::log(p0), u1 = std::log(p1), du = (u1 - u0) / (NH_TAB - 1);
     hh[0] = u0; hh[1] = du; hh[2] = NH_TAB;
+    // a right-hand side at or above this inverts by the table alone: the
+    // table index (ln rhs - u0)/du of any such value is at least 0
+    ctx->herm_pmin[s] = std::exp(u0) * (1.0 + 1e-12);
     double T = T_HERM_MIN;
     for (int k = 0; k < NH_TAB; ++k) {
       double target = u0 + k * du;
@@ -1157,6 +1165,29 @@ static mcrt_status ready(mcrt_ctx *ctx) {
 }
 
 // Host image of the model descriptor for a launch.
+// The fast interaction kernel (with its slow list) serves the FP32 walk in
+// immediate B&W without packet records or scattering moments.
+static bool fast_interactions(const mcrt_ctx *ctx, const mcrt_run_opts *o) {
+  return !ctx->fp64 && o && o->record == 0 && o->mode == MCRT_BW_TICKET &&
+         !(o->sh_order > 0 && ctx->nimg > 0);
+}
+
+// Round variant: 0 general interaction kernel, 1 fast kernel, 2 fast kernel
+// with the per-cell diffusion flags (diffusion steps armed).
+static int fast_mode(const mcrt_ctx *ctx, const mcrt_run_opts *o) {
+  if (!fast_interactions(ctx, o)) return 0;
+  return o->mrw_tau > 0.0 ? 2 : 1;
+}
+
+static mcrt_status ensure_mrw_flags(mcrt_ctx *ctx) {
+  const size_t nw = (ctx->ncell + 31) / 32;
+  if (ctx->d_mrw_flags && ctx->mrw_flags_cap >= nw) return MCRT_OK;
+  ctx->mrw_flags_cap = 0;
+  HIPCHK(dev_alloc((void **)&ctx->d_mrw_flags, 2 * nw * 4));
+  ctx->mrw_flags_cap = nw;
+  return MCRT_OK;
+}
+
 // Ray-tracer source terms: printed form of Eqs. 13-14, and the order of the
 // scattering moments the scattered light is formed from (0: per-view sums).
 static bool rt_lit(const mcrt_ctx *ctx) { return ctx->rt_mode == MCRT_RT_ABS_LITERAL; }
@@ -1192,6 +1223,7 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.ssca_unit = ctx->ssca_unit;
   M.kr_gmax = ctx->kr_gmax;
   M.phi_tmin = ctx->phi_tmin;
+  for (int k = 0; k < MAX_NS; ++k) M.herm_pmin[k] = ctx->herm_pmin[k];
   M.max_int = o ? o->max_interactions : 0;
   M.ncell = ctx->ncell;
   M.ncube = ctx->ncube;
@@ -1207,6 +1239,9 @@ static void fill_model(mcrt_ctx *ctx, ModelDev &M, const mcrt_run_opts *o, int m
   M.imgmap = ctx->d_imgmap;
   M.herm = ctx->d_herm;
   M.mrw_ub = ctx->d_mrw_ub;
+  const bool flags = fast_mode(ctx, o) == 2 && ctx->d_mrw_flags;
+  M.mrw_cand = flags ? ctx->d_mrw_flags : nullptr;
+  M.mrw_bits = flags ? ctx->d_mrw_flags + ctx->mrw_flags_cap : nullptr;
   M.rej_pe = ctx->d_rej_pe;
   M.rej_al = ctx->d_rej_al;
   for (int q = 0; q < ctx->nimg; ++q) M.img_j[q] = ctx->img_idx[q];
@@ -1275,6 +1310,7 @@ static mcrt_status set_range(mcrt_ctx *ctx, uint64_t first, uint64_t n, hipStrea
   return MCRT_OK;
 }
 
+
 // Wavefront queues: two queues of Q packets as structures of arrays,
 // carved from one allocation (256-byte aligned arrays).
 static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n) {
@@ -1288,7 +1324,7 @@ static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t
   if (Q <= ctx->qcap && ctx->d_q) return MCRT_OK;
   const size_t rs = rsize(ctx);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t per = 8 * al(Q * rs) + 4 * al(Q * 4) + al(Q * 8) + 8 * al(Q * 4) + al(Q * 8);
+  const size_t per = 8 * al(Q * rs) + 4 * al(Q * 4) + al(Q * 8) + 9 * al(Q * 4) + al(Q * 8);
   HIPCHK(dev_alloc(&ctx->d_q, 2 * per));
   char *b = (char *)ctx->d_q;
   for (int k = 0; k < 2; ++k) {
@@ -1298,8 +1334,8 @@ static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t
     int32_t **iv[4] = {&q.cx, &q.cy, &q.cz, &q.j};
     for (int32_t **r : iv) { *r = (int32_t *)b; b += al(Q * 4); }
     q.pid = (uint64_t *)b; b += al(Q * 8);
-    uint32_t **uv[8] = {&q.rngd, &q.nint, &q.ncross, &q.nscat, &q.nabs, &q.nmrw, &q.nlucy,
-                        &q.fine};
+    uint32_t **uv[9] = {&q.rngd, &q.nint, &q.ncross, &q.nscat, &q.nabs, &q.nmrw, &q.nlucy,
+                        &q.fine, &q.slow};
     for (uint32_t **r : uv) { *r = (uint32_t *)b; b += al(Q * 4); }
     q.mm = (double *)b; b += al(Q * 8);
   }
@@ -1349,6 +1385,8 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
   const int gwalk = ctx->num_cu * ((o && o->walk_blocks_per_cu > 0) ? o->walk_blocks_per_cu : 4);
   const bool rec = o->record != 0;
   const bool per_cell = o->tau_mode == MCRT_TAU_PER_CELL;
+  const int fast = fast_mode(ctx, o);
+  if (fast == 2) HIPCHK(launch_mrw_cand(ctx->d_model, 1, ctx->num_cu, st));
   const int every = 4;
   // the finishing kernel takes over once every packet has been started and
   // the survivors fit one lane each at two blocks of 256 per CU
@@ -1358,7 +1396,7 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
     const int fcur = (int)(r & 1);
     const hipEvent_t *ev = phase_events(ctx);
     HIPCHK(launch_wf_round(ctx->d_model, 1, ctx->fp64, rec, fcur, gfull, gwalk, lds, lds_w,
-                           idx32_ok(ctx), per_cell, ctx->nsub > 0, ev, st));
+                           idx32_ok(ctx), per_cell, ctx->nsub > 0, fast, ev, st));
     if ((r + 1) % every == 0) {
       HIPCHK(launch_wf_busy(ctx->d_model, 1, fcur, &ctx->d_ctl->busy, &ctx->d_ctl->left, st));
       // emitted .. left: the header of the counters
@@ -1454,6 +1492,10 @@ static mcrt_status prepare_run(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t n
   }
   s = ensure_sh(ctx, o->sh_order, st);
   if (s) return s;
+  if (fast_mode(ctx, o) == 2) {
+    s = ensure_mrw_flags(ctx);
+    if (s) return s;
+  }
   uint64_t nt = o->n_total ? o->n_total : n;
   if (nt == 0) return fail(ctx, MCRT_EINVAL, "n_total is 0");
   ctx->n_total = nt;
@@ -2333,6 +2375,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   }
   hipLaunchKernelGGL(k_wf_reset, dim3(n_models), dim3(256), 0, st, ctx->d_batch, n_models);
   HIPCHK(hipGetLastError());
+  if (fast_mode(ctx, opts) == 2) HIPCHK(launch_mrw_cand(ctx->d_batch, n_models, ctx->num_cu, st));
   const int gfull = ctx->num_cu * (opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2);
   const int gwalk = ctx->num_cu * (opts->walk_blocks_per_cu > 0 ? opts->walk_blocks_per_cu : 4);
   const bool per_cell = opts->tau_mode == MCRT_TAU_PER_CELL;
@@ -2355,7 +2398,7 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   hipError_t le = hipSuccess;
   for (int r = 0; r < ROUNDS && le == hipSuccess; ++r)
     le = launch_wf_round(ctx->d_batch, n_models, ctx->fp64, false, r & 1, gfull, gwalk, lds, lds_w,
-                         idx32, per_cell, refined, nullptr, cs_);
+                         idx32, per_cell, refined, fast_mode(ctx, opts), nullptr, cs_);
   if (le == hipSuccess)
     le = launch_wf_busy(ctx->d_batch, n_models, (ROUNDS - 1) & 1, d_busy, d_left, cs_);
   hipError_t ce = hipStreamEndCapture(cs_, &graph);

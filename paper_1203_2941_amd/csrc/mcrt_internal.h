@@ -91,6 +91,7 @@ struct QBuf {
   uint32_t *ncross, *nscat, *nabs, *nmrw, *nlucy;  // kept for packet records
   double *mm;                                      // kept for packet records
   uint32_t *fine;  // refined grids: the packet's sub-cube (fine_pack); null otherwise
+  uint32_t *slow;  // entries of this queue whose interaction left the fast kernel (see WfCtl)
 };
 
 // The walk keeps the occupancy bits of the grid in LDS: one bit per run of
@@ -105,6 +106,7 @@ constexpr int OCC_MAX_WORDS = 2048;
 // 11 ns each on this GPU), on distinct lines they do not.
 constexpr int NSEG = 64;
 constexpr int CLINE = 32;  // uint32 per counter line
+constexpr uint32_t SLOW_FLIGHT = 0x80000000u;  // slow-list flag (queue indices stay below 2^31)
 
 struct WfCtl {
   uint64_t emitted;  // packets of the launch started so far (launch-relative)
@@ -113,7 +115,10 @@ struct WfCtl {
   uint32_t busy;     // models with packets left (written by k_wf_busy)
   uint32_t inq;      // upper bound of this round's flight-ready packets (plan)
   uint32_t left;     // packets queued for the next round, all models (k_wf_busy)
-  uint32_t pad[24];
+  uint32_t nslow;    // entries of the walked queue handed to the slow interaction kernel
+                     // this round: index, with SLOW_FLIGHT set when only the next
+                     // flight's start (diffusion steps, optical depth) remains
+  uint32_t pad[23];
   uint32_t nseg[2][NSEG][CLINE];  // entries appended to segment g of queue f (clamp to capacity)
   uint32_t work[3][NSEG][CLINE];  // next entry of segment g handed out by emit, walk, interact
 };
@@ -134,6 +139,9 @@ struct ModelDev {
   double ssca_unit;           // scattering sums are stored in these units (erg/s/sr)
   double kr_gmax;             // largest Rosseland-mean bound of the table over [T_TAB_MIN, T_MAX]
   double phi_tmin;            // Phi(T_TAB_MIN) of the first thermal species
+  double herm_pmin[MAX_NS];   // Phi at the lower end of each species' Hermite table (infinity
+                              // when the table is empty): Eq. 4 right-hand sides at or above it
+                              // are inverted by the table alone
   uint64_t max_int, first, n, id_base, rec_first, seed, ncell;
   uint64_t ncube;             // cubes of the grid (ncell - ncube sub-cubes follow them)
   const uint8_t *ref;         // [ncube] sub-cubes per edge (0/1 whole), null: no refinement
@@ -149,6 +157,10 @@ struct ModelDev {
   const double *herm;         // [ns][3 + 2*NH_TAB]: u0, du, n, then (ln T, dlnT/dlnPhi) per node
   const double *mrw_ub;       // [NH_TAB - 1] or null: Rosseland bound per node interval of the
                               // first thermal species' herm table (see build_tables)
+  uint32_t *mrw_cand;         // fast interactions with diffusion steps armed: per leaf cell, one
+  uint32_t *mrw_bits;         // bit each (words of 32): cells past the temperature-free bounds,
+                              // and those of them the tally bound leaves open this round; null
+                              // otherwise
   const float *rej_pe;        // FP32 walk: [2 modes][ns][NK_REJ][nl] (alias prob, envelope) pairs
   const uint8_t *rej_al;      // FP32 walk: [2 modes][ns][NK_REJ][nl] alias bins
   int32_t img_j[MAX_IMG];     // wavelength index of each imaged wavelength

@@ -644,40 +644,143 @@ __device__ __forceinline__ int first_thermal(const ModelDev &M) {
   return 0;
 }
 
-// Modified random walk step (sect. 3.2): see the public header for the
-// trigger. Returns true when a step was taken.
+// The packet's cell as the modified random walk sees it.
+struct MrwCell {
+  int64_t c;
+  double rho, hl, Vl;
+  int s0;
+};
+
+// Temperature-free bounds of a modified random walk step (sect. 3.2) in
+// cell c of density rho, edge hl and volume Vl: false when the step can
+// never apply there. frac_s0 is the mass fraction of the first thermal
+// species. The second bound is used without records only.
+template <bool REC>
+__device__ __forceinline__ bool mrw_possible_cell(const ModelDev &M, double rho, double hl,
+                                                  double Vl, double frac_s0) {
+  if (!(M.mrw_tau > 0.0) || !(rho > 0.0)) return false;
+  if (!(rho * M.kext_max * hl > M.mrw_tau)) return false;
+  if (!REC && M.mode != M_FROZEN) {
+    // B&W temperatures come from at least one packet's energy; when that
+    // alone reaches Phi(T_TAB_MIN), T lies on the bound table and kappa_R
+    // is below its largest entry, which may already rule the step out
+    // without the temperature
+    const double rmin = M.xi / (4.0 * PI_D * frac_s0 * rho * Vl);
+    if (rmin >= 1.001 * M.phi_tmin && !(rho * M.kr_gmax * hl > M.mrw_tau)) return false;
+  }
+  return true;
+}
+
+// Immediate B&W without records: the table interval that Eq. 4 takes for
+// the cell's current tallies bounds kappa_R at its temperature (mrw_ub), so
+// one lookup may rule the step out before T is inverted (false). The
+// right-hand side is mode_T's.
+__device__ __forceinline__ bool mrw_possible_now(const ModelDev &M, int64_t c, int s0,
+                                                 double rho, double hl, double Vl,
+                                                 double frac_s0) {
+  if (M.mode != M_BW_TICKET || !M.mrw_ub) return true;
+  const int64_t q0 = (int64_t)s0 * (int64_t)M.ncell + c;
+  const double e = (double)gld(&M.k[q0]) * M.xi + gld(&M.epath[q0]);
+  const double rhs = (e + M.xi) / (4.0 * PI_D * frac_s0 * rho * Vl);
+  const double *h = M.herm + (size_t)s0 * (3 + 2 * NH_TAB);
+  const float x = (__logf((float)rhs) - (float)h[0]) / (float)h[1];
+  if (x >= 1.0f && x < (float)(NH_TAB - 3)) {
+    if (!(rho * gld(M.mrw_ub + (int)x) * hl > M.mrw_tau)) return false;
+  }
+  return true;
+}
+
+// Bounds that rule a modified random walk step out before the cell
+// temperature is formed: false when the step cannot apply, true when the
+// exact test (Rosseland depth at the cell temperature, sphere size) has to
+// decide.
 template <typename R, bool REC>
-__device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
+__device__ bool mrw_candidate(Ctx<R> &X, const Pkt<R> &P, MrwCell &C) {
   const ModelDev &M = *X.M;
   if (!(M.mrw_tau > 0.0)) return false;
   double hl, Vl;
   const int64_t c = pkt_leaf(M, P, hl, Vl);
   // the density of the cell came with the packet from its last flight
   double rho = P.rho > (R)0 ? (double)P.rho : (double)gld(X.rho + c);
-  if (!(rho > 0.0)) return false;
-  if (!(rho * M.kext_max * hl > M.mrw_tau)) return false;
-  int s0 = first_thermal(M);
-  if (!REC && M.mode != M_FROZEN) {
-    // B&W temperatures come from at least one packet's energy; when that
-    // alone reaches Phi(T_TAB_MIN), T lies on the bound table and kappa_R
-    // is below its largest entry, which may already rule the step out
-    // without the temperature
-    const double rmin = M.xi / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * Vl);
-    if (rmin >= 1.001 * M.phi_tmin && !(rho * M.kr_gmax * hl > M.mrw_tau)) return false;
-  }
-  if (!REC && M.mode == M_BW_TICKET && M.mrw_ub) {
-    // the table interval that Eq. 4 would take for this cell bounds kappa_R
-    // at its temperature (mrw_ub): one lookup may rule the step out before T
-    // is inverted. The right-hand side is mode_T's.
-    const int64_t q0 = (int64_t)s0 * X.nc + c;
-    const double e = (double)gld(&M.k[q0]) * M.xi + gld(&M.epath[q0]);
-    const double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s0] * rho * Vl);
-    const double *h = M.herm + (size_t)s0 * (3 + 2 * NH_TAB);
-    const float x = (__logf((float)rhs) - (float)h[0]) / (float)h[1];
-    if (x >= 1.0f && x < (float)(NH_TAB - 3)) {
-      if (!(rho * gld(M.mrw_ub + (int)x) * hl > M.mrw_tau)) return false;
+  const int s0 = first_thermal(M);
+  const double f0 = X.dt[X.o.frac + s0];
+  if (!mrw_possible_cell<REC>(M, rho, hl, Vl, f0)) return false;
+  C.c = c; C.rho = rho; C.hl = hl; C.Vl = Vl; C.s0 = s0;
+  if (!REC && !mrw_possible_now(M, c, s0, rho, hl, Vl, f0)) return false;
+  return true;
+}
+
+// Per-cell diffusion flags of the fast interaction kernel, one bit per leaf
+// cell in words of 32. k_mrw_cand marks, once per launch, the cells that
+// pass the temperature-free bounds; k_mrw_flags sets, before every fast
+// interaction kernel, the bits of those cells that the tally bound does not
+// rule out at that moment. The fast kernel hands a packet to the slow
+// kernel's exact test when its cell's bit is set: the flags read the
+// tallies as they stand when the kernel starts, which is one of the
+// readings immediate B&W allows (any value since the kernel began).
+template <typename R>
+__global__ void k_mrw_cand(const ModelDev *__restrict__ models, int nmodels) {
+  for (int mm = 0; mm < nmodels; ++mm) {
+    const ModelDev &M = models[mm];
+    if (!M.mrw_cand) continue;
+    const TabOff o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
+    const double f0 = M.tab[o.frac + first_thermal(M)];
+    const uint64_t nw = (M.ncell + 31) / 32;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw;
+         w += (uint64_t)gridDim.x * blockDim.x) {
+      uint32_t bits = 0u;
+      for (int b = 0; b < 32; ++b) {
+        const uint64_t c = w * 32 + (uint64_t)b;
+        if (c >= M.ncell) break;
+        const double rho = (double)gld((const R *)M.rho + c);
+        const double hl = leaf_edge(M, c);
+        const double Vl = (c < M.ncube) ? M.V : hl * hl * hl;
+        if (mrw_possible_cell<false>(M, rho, hl, Vl, f0)) bits |= 1u << b;
+      }
+      M.mrw_cand[w] = bits;
+      M.mrw_bits[w] = 0u;
     }
   }
+}
+
+template <typename R>
+__global__ void k_mrw_flags(const ModelDev *__restrict__ models, int nmodels) {
+  for (int mm = 0; mm < nmodels; ++mm) {
+    const ModelDev &M = models[mm];
+    if (!M.mrw_cand || M.ctl->inq == 0u) continue;
+    const TabOff o = tab_offsets(M.nl, M.ns, M.nsrc, M.nrows);
+    const int s0 = first_thermal(M);
+    const double f0 = M.tab[o.frac + s0];
+    const uint64_t nw = (M.ncell + 31) / 32;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw;
+         w += (uint64_t)gridDim.x * blockDim.x) {
+      uint32_t cand = gld(M.mrw_cand + w);
+      if (!cand) continue;
+      uint32_t bits = 0u;
+      while (cand) {
+        const int b = __builtin_ctz(cand);
+        cand &= cand - 1u;
+        const uint64_t c = w * 32 + (uint64_t)b;
+        const double rho = (double)gld((const R *)M.rho + c);
+        const double hl = leaf_edge(M, c);
+        const double Vl = (c < M.ncube) ? M.V : hl * hl * hl;
+        if (mrw_possible_now(M, (int64_t)c, s0, rho, hl, Vl, f0)) bits |= 1u << b;
+      }
+      M.mrw_bits[w] = bits;
+    }
+  }
+}
+
+// Modified random walk step (sect. 3.2): see the public header for the
+// trigger. Returns true when a step was taken.
+template <typename R, bool REC>
+__device__ bool mrw_step(Ctx<R> &X, Pkt<R> &P) {
+  const ModelDev &M = *X.M;
+  MrwCell C;
+  if (!mrw_candidate<R, REC>(X, P, C)) return false;
+  const int64_t c = C.c;
+  const double rho = C.rho, hl = C.hl, Vl = C.Vl;
+  const int s0 = C.s0;
   double T0 = mode_T(X, s0, c, rho, Vl);
   if (!REC) {
     // upper bound of kappa_R(T) on its table interval (build_tables proves
@@ -983,15 +1086,28 @@ __device__ void start_packet(Ctx<R> &X, Pkt<R> &P, uint64_t idx) {
 
 // Start of a flight: modified random walk steps while they apply, then the
 // optical depth of the flight. Returns a negative depth when the packet is
-// killed.
-template <typename R, bool REC>
-__device__ R flight_tau(Ctx<R> &X, Pkt<R> &P) {
+// killed. FAST (fast interaction kernel): a packet whose cell needs the
+// exact diffusion test sets *defer = 2 and returns before any draw; the slow
+// kernel then starts its flight with this function (FAST false).
+template <typename R, bool REC, bool FAST = false>
+__device__ R flight_tau(Ctx<R> &X, Pkt<R> &P, int *defer = nullptr) {
   const ModelDev &M = *X.M;
-  while (mrw_step<R, REC>(X, P)) {
-    P.n_int++;
-    if (M.max_int > 0 && P.n_int >= M.max_int) {
-      P.status = ST_KILLED;
-      return (R)-1;
+  if constexpr (FAST) {
+    if (M.mrw_tau > 0.0) {
+      double hl, Vl;
+      const int64_t c = pkt_leaf(M, P, hl, Vl);
+      if (!M.mrw_bits || ((gld(M.mrw_bits + (c >> 5)) >> (c & 31)) & 1u)) {
+        *defer = 2;
+        return (R)-1;
+      }
+    }
+  } else {
+    while (mrw_step<R, REC>(X, P)) {
+      P.n_int++;
+      if (M.max_int > 0 && P.n_int >= M.max_int) {
+        P.status = ST_KILLED;
+        return (R)-1;
+      }
     }
   }
   // per-cell draws are taken by the walk itself, cell by cell
@@ -1014,10 +1130,36 @@ static __device__ __noinline__ void sh_deposit(R *row, int order, double dx, dou
   });
 }
 
+// Eq. 4 for immediate B&W by the Hermite table alone (fast interaction
+// kernel): the caller has checked that the right-hand side lies at or above
+// the table's lower end; at or above its upper end, Phi(T_MAX), the
+// temperature is T_MAX (clamped).
+__device__ __forceinline__ double invert_T_table(const double *herm, int s, double rhs,
+                                                bool *clamped) {
+  const double *h = herm + (size_t)s * (3 + 2 * NH_TAB);
+  double x = (log(rhs) - h[0]) / h[1];
+  const int n = (int)h[2];
+  if (!(x >= 0.0)) x = 0.0;
+  if (!(x < (double)(n - 1))) {
+    *clamped = true;
+    return T_MAX;
+  }
+  int k = (int)x;
+  double t = x - (double)k, t2 = t * t, t3 = t2 * t;
+  const double *p = h + 3 + 2 * k;
+  double y = (2.0 * t3 - 3.0 * t2 + 1.0) * p[0] + (t3 - 2.0 * t2 + t) * h[1] * p[1] +
+             (-2.0 * t3 + 3.0 * t2) * p[2] + (t3 - t2) * h[1] * p[3];
+  return exp(y);
+}
+
 // Interaction at P.p in cell P.c: albedo split, HG scattering with its
-// event sums, or absorption with re-emission (or a PAH stop).
-template <typename R, bool REC>
-__device__ void interact(Ctx<R> &X, Pkt<R> &P) {
+// event sums, or absorption with re-emission (or a PAH stop). FAST (fast
+// interaction kernel: immediate B&W, no records, no moments): an absorption
+// in a cell where one packet's energy lies below the Eq. 4 table sets
+// *defer = 1 and returns before any tally or statistic changes, so that the
+// slow kernel can take the whole interaction again from the queued state.
+template <typename R, bool REC, bool FAST = false>
+__device__ void interact(Ctx<R> &X, Pkt<R> &P, int *defer = nullptr) {
   const ModelDev &M = *X.M;
   const int nl = M.nl, ns = M.ns;
   double hl, Vl;
@@ -1039,7 +1181,7 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
         R add = (R)(M.xi / M.ssca_unit) * hg_phase<R>(g, cb);
         gatomic_add((R *)M.ssca + ((int64_t)v * X.nc + c) * M.nimg + q, add);
       }
-      if (M.sh_order > 0) {
+      if (!FAST && M.sh_order > 0) {
         const int nlm = M.sh_order * M.sh_order;
         sh_deposit<R>((R *)M.sh + ((int64_t)c * M.nimg + q) * nlm, M.sh_order, (double)P.d[0],
                       (double)P.d[1], (double)P.d[2], (double)g, M.xi / M.ssca_unit);
@@ -1050,6 +1192,14 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
     stat_add(X.st, 5, 1ull);
   } else {
     int s = pick_asc<R, REC>(X.rt + X.o.r_fabs + j, nl, ns, usp, P.mm);
+    if constexpr (FAST) {
+      // Eq. 4's right-hand side is at least one packet's energy over the cell
+      if (s != M.pah &&
+          !(M.xi >= M.herm_pmin[s] * (4.0 * PI_D * X.dt[X.o.frac + s] * (double)P.rho * Vl))) {
+        *defer = 1;
+        return;
+      }
+    }
     P.n_abs++;
     stat_add(X.st, 6, 1ull);
     if (s == M.pah) {
@@ -1065,16 +1215,17 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P) {
       const R rho = P.rho;
       const bool thin = M.ref ? is_thin_h(X, rho, hl) : is_thin(X, rho);
       int64_t qk = (int64_t)s * X.nc + c;
-      double T;
+      double T = 0.0;
       if (M.mode == M_BW_TICKET) {
         uint64_t kold = thin ? gld(&M.k[qk])
                              : gatomic_add(&M.k[qk], (uint64_t)1);
         double e = (double)kold * M.xi + gld(&M.epath[qk]);  // racy read, as in mode_T
         double rhs = (e + M.xi) / (4.0 * PI_D * X.dt[X.o.frac + s] * (double)rho * Vl);
         bool cl = false;
-        T = invert_T_fast(M.herm, X.dt, X.o, nl, s, rhs, &cl);
+        if constexpr (FAST) T = invert_T_table(M.herm, s, rhs, &cl);
+        else T = invert_T_fast(M.herm, X.dt, X.o, nl, s, rhs, &cl);
         if (cl) stat_add(X.st, 9, 1ull);
-      } else {
+      } else if constexpr (!FAST) {
         if (!thin) gatomic_add(&M.k[qk], (uint64_t)1);
         T = mode_T(X, s, c, (double)rho, Vl);
       }
@@ -1293,6 +1444,7 @@ __global__ void k_wf_plan(const ModelDev *__restrict__ models, int nmodels, int 
     c->emitted += take;
     c->take = take;
     c->inq = s_held + take;
+    c->nslow = 0u;
   }
 }
 
@@ -1429,12 +1581,17 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
 
 // Interactions of the walked queue fcur (entries freed by escapes are
 // skipped); survivors sample their next flight and join flight-ready queue
-// 1 - fcur.
-template <typename R, bool REC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_wf_interact(const ModelDev *__restrict__ models, int nmodels, int fcur) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ unsigned long long s_stat[NSTAT];
+// 1 - fcur. FAST (immediate B&W without records or moments): the rare
+// interactions that need the FP64 Newton solve of Eq. 4 or the exact
+// diffusion test go to the walked queue's slow list instead (the entry
+// keeps the packet: untouched for a whole interaction, rewritten when only
+// the next flight's start remains) and k_wf_slow finishes them. Without the
+// out-of-line FP64 calls the fast kernel needs 158 VGPRs and no scratch; the
+// general one spills at 256.
+template <typename R, bool REC, bool FAST>
+__device__ __forceinline__ void interact_round(const ModelDev *__restrict__ models, int nmodels,
+                                               int fcur, unsigned char *lds_raw,
+                                               unsigned long long *s_stat) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int mm = 0; mm < nmodels; ++mm) {
@@ -1460,13 +1617,83 @@ k_wf_interact(const ModelDev *__restrict__ models, int nmodels, int fcur) {
       bool keep = false;
       if (i < hi && gld((const R *)qi.tau + i) >= (R)0) {
         (void)q_load<R, REC>(M, qi, i, P);
-        interact<R, REC>(X, P);
-        if (P.status == ST_ALIVE) tau = flight_tau<R, REC>(X, P);
-        keep = P.status == ST_ALIVE;
-        if (!keep) finish<R, REC>(X, P, true);
+        int defer = 0;
+        interact<R, REC, FAST>(X, P, &defer);
+        if (P.status == ST_ALIVE && defer == 0) tau = flight_tau<R, REC, FAST>(X, P, &defer);
+        if (FAST && defer != 0) {
+          if (defer == 2) q_store<R, REC>(qi, i, P, (R)0);
+          const uint32_t k = gatomic_add(&c->nslow, 1u);
+          qi.slow[k] = defer == 2 ? (i | SLOW_FLIGHT) : i;
+        } else {
+          keep = P.status == ST_ALIVE;
+          if (!keep) finish<R, REC>(X, P, true);
+        }
       }
       const uint32_t slot = seg_reserve(c, 1 - fcur, S, home, keep, lane, lt_mask);
       if (keep) store_or_drop<R, REC>(X, qo, slot, P, tau);
+    }
+    flush_block(X);
+  }
+}
+
+template <typename R, bool REC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_wf_interact(const ModelDev *__restrict__ models, int nmodels, int fcur) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ unsigned long long s_stat[NSTAT];
+  interact_round<R, REC, false>(models, nmodels, fcur, lds_raw, s_stat);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_wf_interact_fast(const ModelDev *__restrict__ models, int nmodels, int fcur) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ unsigned long long s_stat[NSTAT];
+  interact_round<R, false, true>(models, nmodels, fcur, lds_raw, s_stat);
+}
+
+// The slow list of the walked queue fcur: whole interactions (the queued
+// state as the fast kernel found it) or only the start of the next flight,
+// with the general device functions; survivors join queue 1 - fcur like
+// the fast kernel's.
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_wf_slow(const ModelDev *__restrict__ models, int nmodels, int fcur) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ unsigned long long s_stat[NSTAT];
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int mm = 0; mm < nmodels; ++mm) {
+    const ModelDev &M = models[(blockIdx.x + mm) % nmodels];
+    WfCtl *c = M.ctl;
+    const uint32_t n = c->nslow;  // written by the fast kernel before this launch
+    if (n == 0u) continue;
+    Ctx<R> X;
+    stage_model<R>(X, M, lds_raw, s_stat, true);
+    const QBuf &qi = M.q[fcur];
+    const QBuf &qo = M.q[1 - fcur];
+    const uint32_t S = M.qseg;
+    const int home = home_segment();
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwave = gridDim.x * (blockDim.x >> 6);
+    // every lane of a wave runs the same iterations (queue appends are
+    // wave-wide)
+    for (uint32_t b = wave * 64u; b < n; b += nwave * 64u) {
+      const uint32_t k = b + (uint32_t)lane;
+      Pkt<R> P;
+      R tau = (R)-1;
+      bool keep = false;
+      if (k < n) {
+        const uint32_t e = gld(qi.slow + k);
+        const uint32_t i = e & ~SLOW_FLIGHT;
+        (void)q_load<R, false>(M, qi, i, P);
+        if (!(e & SLOW_FLIGHT)) interact<R, false>(X, P);
+        if (P.status == ST_ALIVE) tau = flight_tau<R, false>(X, P);
+        keep = P.status == ST_ALIVE;
+        if (!keep) finish<R, false>(X, P, true);
+      }
+      const uint32_t slot = seg_reserve(c, 1 - fcur, S, home, keep, lane, lt_mask);
+      if (keep) store_or_drop<R, false>(X, qo, slot, P, tau);
     }
     flush_block(X);
   }
@@ -1482,7 +1709,7 @@ size_t walk_lds_bytes(int nl, int ns, int nsrc, int nrows, int ntheta, int occ_w
 template <typename R, bool REC>
 static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_full, int grid_walk,
                       size_t lds_full, size_t lds_walk, bool idx32, bool per_cell, bool refined,
-                      const hipEvent_t *ev, hipStream_t st) {
+                      int fast, const hipEvent_t *ev, hipStream_t st) {
   if (ev) (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((k_wf_emit<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
                      nmodels, fcur);
@@ -1505,9 +1732,29 @@ static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_
     hipLaunchKernelGGL((k_wf_walk<R, REC, false, false, false>), dim3(grid_walk), dim3(256),
                        lds_walk, st, d_models, nmodels, fcur);
   if (ev) (void)hipEventRecord(ev[2], st);
+  // the fast interaction kernel serves the FP32 walk (see interact_round)
+  if constexpr (!REC && sizeof(R) == 4) {
+    if (fast) {
+      if (fast == 2)
+        hipLaunchKernelGGL((k_mrw_flags<R>), dim3(grid_full), dim3(256), 0, st, d_models, nmodels);
+      hipLaunchKernelGGL((k_wf_interact_fast<R>), dim3(grid_full), dim3(256), lds_full, st,
+                         d_models, nmodels, fcur);
+      hipLaunchKernelGGL((k_wf_slow<R>), dim3(grid_full), dim3(256), lds_full, st, d_models,
+                         nmodels, fcur);
+      if (ev) (void)hipEventRecord(ev[3], st);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_wf_interact<R, REC>), dim3(grid_full), dim3(256), lds_full, st, d_models,
                      nmodels, fcur);
   if (ev) (void)hipEventRecord(ev[3], st);
+}
+
+// Candidate bits of the per-cell diffusion flags (once per launch, after
+// the models are on the device).
+hipError_t launch_mrw_cand(const ModelDev *d_models, int nmodels, int ncu, hipStream_t st) {
+  hipLaunchKernelGGL(k_mrw_cand<float>, dim3(ncu * 4), dim3(256), 0, st, d_models, nmodels);
+  return hipGetLastError();
 }
 
 // One round for nmodels models: plan, emit, walk, interact (stream order).
@@ -1515,15 +1762,15 @@ static void wf_phases(const ModelDev *d_models, int nmodels, int fcur, int grid_
 // four events) brackets the emission, walk and interaction kernels.
 hipError_t launch_wf_round(const ModelDev *d_models, int nmodels, bool fp64, bool rec, int fcur,
                            int grid_full, int grid_walk, size_t lds_full, size_t lds_walk,
-                           bool idx32, bool per_cell, bool refined, const hipEvent_t *ev,
-                           hipStream_t st) {
+                           bool idx32, bool per_cell, bool refined, int fast,
+                           const hipEvent_t *ev, hipStream_t st) {
   hipLaunchKernelGGL(k_wf_plan, dim3(nmodels), dim3(64), 0, st, d_models, nmodels, fcur);
   if (fp64) {
-    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, ev, st);
-    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, ev, st);
+    if (rec) wf_phases<double, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, fast, ev, st);
+    else wf_phases<double, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, fast, ev, st);
   } else {
-    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, ev, st);
-    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, ev, st);
+    if (rec) wf_phases<float, true>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, fast, ev, st);
+    else wf_phases<float, false>(d_models, nmodels, fcur, grid_full, grid_walk, lds_full, lds_walk, idx32, per_cell, refined, fast, ev, st);
   }
   return hipGetLastError();
 }
