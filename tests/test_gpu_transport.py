@@ -277,3 +277,33 @@ def test_fp32_walk_through_empty_bricks():
     assert sa["crossings"] == sb["crossings"]
     assert sa["crossings"] > 15 * m.n_packets
     np.testing.assert_array_equal(ea, eb)
+
+
+def test_sed_flux_of_a_bare_source(orc):
+    """Photon-counting SED (sect. 4) of a blackbody source in an empty grid:
+    every packet escapes unscattered, so in each polar bin and wavelength the
+    flux count xi / (dOmega D^2 w_j) is L_nu,j / (4 pi D^2) within the
+    bin's Poisson error (the source spectrum normalised to the luminosity on
+    the frequency quadrature)."""
+    m = mi.cube(n=8, n_packets=400_000, tau_v=1.0)
+    m.rho = np.zeros_like(m.rho)
+    D = 3.0e20
+    g = gpu_context(m, "fp64", views=np.array([[45.0, 0.0]]), img_idx=np.array([3]), distance=D)
+    st = g.run_packets(0, m.n_packets, m.seed, mode="bw_epoch", n_total=m.n_packets,
+                       sed_theta_bins=10)
+    assert st["escaped"] == m.n_packets and st["scatters"] + st["absorptions"] == 0
+    f, c = g.sed()
+    nu, w = orc.freq_grid(m.lam_um)
+    lnu = np.array([orc.planck(x, float(m.src_tbb[0])) for x in nu])
+    lnu *= float(m.src_lum[0]) / np.sum(w * lnu)
+    expect = np.broadcast_to(lnu / (4.0 * np.pi * D * D), f.shape)
+    ok = c > 300
+    assert ok.sum() >= 40
+    rel = f[ok] / expect[ok] - 1.0
+    assert np.all(np.abs(rel) < 5.0 / np.sqrt(c[ok].astype(float)))
+    # the counts themselves: the source spectrum's share per bin (chi^2)
+    pj = w * lnu / np.sum(w * lnu)
+    exp_c = m.n_packets / 10.0 * pj
+    sel = exp_c > 50
+    chi = np.sum((c[:, sel] - exp_c[sel]) ** 2 / exp_c[sel]) / (10 * sel.sum())
+    assert chi < 1.0 + 4.0 * np.sqrt(2.0 / (10 * sel.sum()))
