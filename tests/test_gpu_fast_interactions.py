@@ -58,3 +58,36 @@ def test_slow_list_takes_interactions_below_the_table(orc):
     assert o.invert_T(0, rmin) < 3.0
     hot = To[To > 0]
     assert 1.5 < np.median(hot) < 10.0
+
+
+def test_fp32_diffusion_steps_thick_cube(orc):
+    """Diffusion steps in the FP32 walk (fast kernel, slow list and per-cell
+    flags in immediate B&W; the general kernel in epoch B&W with one packet
+    per epoch) on a tau_V = 1e4 cube against the oracle's serial B&W at an
+    independent seed: every packet escapes (an interaction cap far above the
+    oracle's longest chain bounds the run), the number of diffusion steps and
+    the absorbed energy agree within 15 % (full chains amplify last-bit
+    differences, so only totals are compared), and the escape SED within its
+    Poisson spread."""
+    m = mi.cube(n=8, n_packets=2000, tau_v=1e4, nl=20)
+    o = orc.Oracle(m).run(mode=orc.BW_EPOCH, epoch=1, mrw_tau=8.0, mrw_gamma=2.0,
+                          seed=m.seed + 777)
+    assert o.stats["mrw_steps"] > 50 * m.n_packets
+    xi = float(m.src_lum.sum()) / m.n_packets
+    eo = o.k[0].sum() * xi + o.epath[0].sum()
+    so = o.sed.astype(float)
+    for mode, kw in (("bw_ticket", {}), ("bw_epoch", {"epoch_packets": 1})):
+        print("fp32 diffusion steps,", mode, flush=True)
+        g = gpu_context(m, "fp32")
+        st = g.run_packets(0, m.n_packets, m.seed, mode=mode, mrw_tau=8.0, mrw_gamma=2.0,
+                           n_total=m.n_packets, max_interactions=200_000, **kw)
+        assert st["killed"] == 0 and st["escaped"] == m.n_packets, (mode, st)
+        assert st["mrw_steps"] == pytest.approx(o.stats["mrw_steps"], rel=0.15), mode
+        k, ep, _ = g.tallies()
+        eg = k[0].astype(float).sum() * xi + ep[0].sum()
+        assert eg == pytest.approx(eo, rel=0.15), mode
+        sg = g.sed()[1].astype(float)
+        ok = (so + sg) > 30
+        dof = int(ok.sum())
+        c2 = np.sum((so[ok] - sg[ok]) ** 2 / (so[ok] + sg[ok])) / dof
+        assert dof > 10 and c2 < 1.0 + 4.0 * np.sqrt(2.0 / dof), (mode, c2, dof)
