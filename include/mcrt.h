@@ -285,14 +285,18 @@ mcrt_status mcrt_set_raytrace_mode(mcrt_ctx *ctx, int rt_mode);
  * kappa_sca (1 - g) per species and wavelength (albedo and extinction follow).
  * Rebuilds the tables. EINVAL on another law. */
 mcrt_status mcrt_set_scattering_law(mcrt_ctx *ctx, int law);
-/* Scattered light of the ray-tracer's source functions: MCRT_SSCA_PEELOFF
+/* Scattered light of the ray-tracer's source functions (sect. 4, Eq. 16:
+ * the scattering events seen from the observer): MCRT_SSCA_PEELOFF
  * (default), the per-view sums of the transport; MCRT_SSCA_MOMENTS, the
  * moments of the last run with sh_order > 0 evaluated toward each view set
- * (any views, set after the run) as sum_lm Y_lm(k_v) M_lm. */
+ * (any views, set after the run) as sum_lm Y_lm(k_v) M_lm. EINVAL on another
+ * value. */
 mcrt_status mcrt_set_scattered_light(mcrt_ctx *ctx, int source);
-/* Moments of the scattering events (erg/s), [n_img][order^2][cells] with
- * index l^2 + l + m, host or device destination; *order (nullable) receives
- * L + 1 (0 when none). out NULL: order only. ESTATE when there are none. */
+/* Moments of the scattering events (sect. 4: the stored events, kept as
+ * sum xi g^l Y_lm(d_in) per cell and imaged wavelength; erg/s),
+ * [n_img][order^2][cells] with index l^2 + l + m, FP64, host or device
+ * destination (mem); *order (nullable) receives L + 1 (0 when none). out
+ * NULL: order only. ESTATE when there are none. */
 mcrt_status mcrt_scattering_moments(mcrt_ctx *ctx, double *out, int *order, int mem,
                                     void *stream);
 
