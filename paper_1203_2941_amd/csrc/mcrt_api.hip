@@ -1737,7 +1737,7 @@ __global__ void k_d2f(const double *a, float *b, uint64_t n) {
   uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) b[i] = (float)a[i];
 }
-// Scattering sums from the device layout [view][cell][img] (in units of
+// Scattering sums from the device layout [cell][view][img] (in units of
 // `unit`) to the API layout [view][img][cell] in erg/s/sr.
 template <typename R>
 __global__ void k_ssca_out(const R *a, double *b, double unit, int nview, uint64_t ncell,
@@ -1748,7 +1748,7 @@ __global__ void k_ssca_out(const R *a, double *b, double unit, int nview, uint64
   for (; i < n; i += stride) {
     const uint64_t c = i % ncell, r = i / ncell;
     const uint64_t q = r % (uint64_t)nq, v = r / (uint64_t)nq;
-    b[i] = (double)a[(v * ncell + c) * (uint64_t)nq + q] * unit;
+    b[i] = (double)a[(c * (uint64_t)nview + v) * (uint64_t)nq + q] * unit;
   }
 }
 
@@ -1775,12 +1775,12 @@ extern "C" mcrt_status mcrt_set_scattering(mcrt_ctx *ctx, const double *ssca, in
     if (h[i] > mx) mx = h[i];
   }
   // store in units that keep the largest value near 2^20, in the device
-  // layout [view][cell][img]
+  // layout [cell][view][img]
   double unit = mx > 0.0 ? mx / 1048576.0 : 1.0;
-  const uint64_t nc = ctx->ncell, nq = (uint64_t)ctx->nimg;
+  const uint64_t nc = ctx->ncell, nq = (uint64_t)ctx->nimg, nv = (uint64_t)ctx->nview;
   auto dev_index = [&](uint64_t i) {  // API index [view][img][cell] -> device index
     const uint64_t c = i % nc, r = i / nc;
-    return ((r / nq) * nc + c) * nq + r % nq;
+    return (c * nv + r / nq) * nq + r % nq;
   };
   if (ctx->fp64) {
     std::vector<double> d(m);

@@ -173,7 +173,7 @@ struct ModelDev {
   uint32_t *kpah;             // [cells]
   const uint64_t *kpah_prefix;// [cells] exclusive prefix of kpah (PAH pass)
   uint64_t *sed;              // [ntheta][nl]
-  void *ssca;                 // [nview][nimg][cells] context precision
+  void *ssca;                 // [cells][nview][nimg] context precision
   void *rec;                  // records [n]
   uint64_t *counter;          // packet counter of the launch
   unsigned long long *stats;  // [NSTAT]

@@ -222,9 +222,10 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
       }
     }
     for (int v = 0; v < M.nview; ++v) {
-      // the scattering sums and S share the layout [view][cell][img]
+      // S is [view][cell][img]; the scattering sums are [cell][view][img] (a
+      // scattering event's view sums share cache lines)
       R *out = S + ((uint64_t)v * M.ncell + c) * nq;
-      const R *sc = ss ? ss + ((uint64_t)v * M.ncell + c) * nq : nullptr;
+      const R *sc = ss ? ss + ((uint64_t)c * M.nview + v) * nq : nullptr;
       R sv[MAX_IMG];
 #pragma unroll
       for (int q = 0; q < MAX_IMG; ++q) sv[q] = (R)0;

@@ -1179,7 +1179,7 @@ __device__ void interact(Ctx<R> &X, Pkt<R> &P, int *defer = nullptr) {
         R cb = P.d[0] * (R)M.kv[v][0] + P.d[1] * (R)M.kv[v][1] + P.d[2] * (R)M.kv[v][2];
         // sums kept in units of ssca_unit (the packet energy): erg/s sums overflow FP32
         R add = (R)(M.xi / M.ssca_unit) * hg_phase<R>(g, cb);
-        gatomic_add((R *)M.ssca + ((int64_t)v * X.nc + c) * M.nimg + q, add);
+        gatomic_add((R *)M.ssca + ((int64_t)c * M.nview + v) * M.nimg + q, add);
       }
       if (!FAST && M.sh_order > 0) {
         const int nlm = M.sh_order * M.sh_order;
