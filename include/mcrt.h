@@ -75,7 +75,8 @@ typedef struct {
   int32_t sed_theta_bins;    /* photon-counting SED bins, equal in cos(theta) */
   int32_t record;            /* 1: keep one mcrt_packet_record per packet */
   int32_t blocks_per_cu;     /* 256-thread blocks per compute unit of the emission and
-                                interaction kernels of a round (0 = 2; 1..32) */
+                                interaction kernels of a round (0 = 3 where the FP32 walk
+                                takes the fast interaction kernel, else 2; 1..32) */
   int32_t queue_depth;       /* packets per wavefront queue (0 = 2^25; 64..2^26) */
   int32_t walk_blocks_per_cu; /* 256-thread blocks per compute unit of the walk kernel
                                 (0 = 4; 1..32) */

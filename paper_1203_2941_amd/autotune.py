@@ -20,7 +20,7 @@ from .context import Context, run_batch
 
 CANDIDATES: List[Tuple[int, int, int]] = [
     (1 << 22, 4, 2), (1 << 23, 4, 2), (1 << 24, 4, 2), (1 << 25, 4, 2), (1 << 25, 3, 2),
-    (1 << 25, 4, 1), (1 << 26, 4, 2)]
+    (1 << 25, 4, 1), (1 << 26, 4, 2), (1 << 24, 4, 3), (1 << 25, 4, 3)]
 CACHE = os.environ.get("MCRT_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "mcrt_autotune.json"))
 

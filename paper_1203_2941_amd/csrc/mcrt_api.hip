@@ -1179,6 +1179,13 @@ static int fast_mode(const mcrt_ctx *ctx, const mcrt_run_opts *o) {
   return o->mrw_tau > 0.0 ? 2 : 1;
 }
 
+// Blocks per compute unit of the emission and interaction kernels when the
+// caller leaves it open: the fast interaction kernel fits three waves per
+// SIMD (158 VGPRs) and waits on memory, so a third block hides more of it
+// (measured on the 256^3 torus: interaction 73 -> 65 ms per step, no gain
+// from a fourth); the general kernels fit two.
+static int default_bpc(int fast) { return fast ? 3 : 2; }
+
 static mcrt_status ensure_mrw_flags(mcrt_ctx *ctx) {
   const size_t nw = (ctx->ncell + 31) / 32;
   if (ctx->d_mrw_flags && ctx->mrw_flags_cap >= nw) return MCRT_OK;
@@ -1381,11 +1388,11 @@ static mcrt_status transport_launch(mcrt_ctx *ctx, const mcrt_run_opts *o, uint6
                                 ctx->fp64);
   if (lds > ctx->lds_max || lds_w > ctx->lds_max)
     return fail(ctx, MCRT_EINVAL, "tables need %zu bytes of LDS (limit %zu): fewer wavelengths, species or SED bins", lds > lds_w ? lds : lds_w, ctx->lds_max);
-  const int gfull = ctx->num_cu * ((o && o->blocks_per_cu > 0) ? o->blocks_per_cu : 2);
-  const int gwalk = ctx->num_cu * ((o && o->walk_blocks_per_cu > 0) ? o->walk_blocks_per_cu : 4);
   const bool rec = o->record != 0;
   const bool per_cell = o->tau_mode == MCRT_TAU_PER_CELL;
   const int fast = fast_mode(ctx, o);
+  const int gfull = ctx->num_cu * (o->blocks_per_cu > 0 ? o->blocks_per_cu : default_bpc(fast));
+  const int gwalk = ctx->num_cu * (o->walk_blocks_per_cu > 0 ? o->walk_blocks_per_cu : 4);
   if (fast == 2) HIPCHK(launch_mrw_cand(ctx->d_model, 1, ctx->num_cu, st));
   const int every = 4;
   // the finishing kernel takes over once every packet has been started and
@@ -2375,8 +2382,9 @@ extern "C" mcrt_status mcrt_run_batch(mcrt_ctx *const *models, int n_models,
   }
   hipLaunchKernelGGL(k_wf_reset, dim3(n_models), dim3(256), 0, st, ctx->d_batch, n_models);
   HIPCHK(hipGetLastError());
-  if (fast_mode(ctx, opts) == 2) HIPCHK(launch_mrw_cand(ctx->d_batch, n_models, ctx->num_cu, st));
-  const int gfull = ctx->num_cu * (opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 2);
+  const int fast = fast_mode(ctx, opts);
+  if (fast == 2) HIPCHK(launch_mrw_cand(ctx->d_batch, n_models, ctx->num_cu, st));
+  const int gfull = ctx->num_cu * (opts->blocks_per_cu > 0 ? opts->blocks_per_cu : default_bpc(fast));
   const int gwalk = ctx->num_cu * (opts->walk_blocks_per_cu > 0 ? opts->walk_blocks_per_cu : 4);
   const bool per_cell = opts->tau_mode == MCRT_TAU_PER_CELL;
   bool refined = false;
