@@ -6,6 +6,8 @@ the MRW shortcuts of the record-free kernels."""
 import dataclasses
 import math
 
+import time
+
 import numpy as np
 import pytest
 
@@ -110,15 +112,8 @@ def test_fp32_lucy_with_packet_energy_above_float_max(orc):
 
 
 @pytest.mark.parametrize("precision", [
-    pytest.param("fp64", marks=pytest.mark.skip(
-        reason="a full GPU run was stopped after 180 s without output inside this case, with "
-               "kernels identical (same machine code) to a run where it passed in seconds: a "
-               "hang that comes and goes on the tau_V = 1e5 cube, cause not found, kept off the "
-               "GPU")),
-    pytest.param("fp32", marks=pytest.mark.skip(
-        reason="FP32 walk with diffusion steps on the tau_V = 1e5 cube ran over 180 s without "
-               "output on the GPU (the oracle needs ~2e3 events per packet here); cause not "
-               "found, kept off the GPU")),
+    "fp64",
+    "fp32",
 ])
 def test_mrw_shortcuts_change_nothing(orc, precision):
     """The record-free kernels skip the exact Rosseland mean (and in immediate
@@ -127,11 +122,14 @@ def test_mrw_shortcuts_change_nothing(orc, precision):
     steps. One epoch makes every packet independent in BW_EPOCH; in
     immediate B&W one packet per call makes the order deterministic."""
     m = mi.cube(n=8, n_packets=150, tau_v=1e5, nl=12, seed=8)
+    t0 = time.time()
     out = []
     for rec in (True, False):
         g = gpu_context(m, precision)
         st = g.run_packets(0, m.n_packets, m.seed, mode="bw_epoch", epoch_packets=10 ** 9,
                            mrw_tau=8.0, mrw_gamma=2.0, record=rec, n_total=m.n_packets)
+        print(f"epoch run, records {rec}: {st['mrw_steps']} diffusion steps, "
+              f"{time.time() - t0:.1f} s", flush=True)
         k, ep, _ = g.tallies()
         out.append((st, k, ep, g.sed()[1].copy()))
     (sa, ka, ea, fa), (sb, kb, eb, fb) = out
@@ -139,15 +137,20 @@ def test_mrw_shortcuts_change_nothing(orc, precision):
     assert np.array_equal(ka, kb) and np.array_equal(fa, fb)
     np.testing.assert_allclose(ea, eb, rtol=1e-12, atol=0)
     out = []
-    n = 40
+    # one packet per call runs its chain in a single lane (about 0.15 ms per
+    # diffusion step, 2e3 to 7e4 steps per packet here): the first n of
+    # n_total packets
+    n, n_total = 8, 40
     for rec in (True, False):
         g = gpu_context(m, precision)
         tot = {"mrw_steps": 0, "crossings": 0}
         for i in range(n):
             st = g.run_packets(i, 1, m.seed, mode="bw_ticket", mrw_tau=8.0, mrw_gamma=2.0,
-                               record=rec, n_total=n)
+                               record=rec, n_total=n_total)
             for key in tot:
                 tot[key] += st[key]
+            print(f"one-packet call {i}, records {rec}: {st['mrw_steps']} diffusion steps, "
+                  f"{time.time() - t0:.1f} s", flush=True)
         k, ep, _ = g.tallies()
         out.append((tot, k, ep))
     (ta, ka, ea), (tb, kb, eb) = out
