@@ -1491,6 +1491,46 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
   }
 }
 
+// The walk's share of a queued packet. Without records or per-cell draws a
+// flight reads only position, direction, cell, wavelength, sub-cube and
+// depth, and at an interaction changes only position, cell, sub-cube and
+// density (the depth field is cleared): the id, draw index, interaction
+// count, direction and wavelength stay in the entry as the interaction kernel
+// reads them. With records or per-cell draws the whole packet moves.
+template <typename R, bool REC, bool PC>
+__device__ __forceinline__ R q_load_walk(const ModelDev &M, const QBuf &b, uint32_t i, Pkt<R> &P) {
+  if constexpr (REC || PC) {
+    return q_load<R, REC>(M, b, i, P);
+  } else {
+    P.p[0] = gld((const R *)b.px + i); P.p[1] = gld((const R *)b.py + i);
+    P.p[2] = gld((const R *)b.pz + i);
+    P.d[0] = gld((const R *)b.dx + i); P.d[1] = gld((const R *)b.dy + i);
+    P.d[2] = gld((const R *)b.dz + i);
+    const R tau = gld((const R *)b.tau + i);
+    P.c[0] = gld(b.cx + i); P.c[1] = gld(b.cy + i); P.c[2] = gld(b.cz + i);
+    P.j = gld(b.j + i);
+    P.fpk = b.fine ? gld(b.fine + i) : 0u;
+    P.rho = (R)0;
+    P.status = ST_ALIVE;
+    P.n_cross = P.n_scat = P.n_abs = P.n_mrw = P.n_lucy = 0;
+    P.mm = 1e300;
+    return tau;
+  }
+}
+
+template <typename R, bool REC, bool PC>
+__device__ __forceinline__ void q_store_walk(const QBuf &b, uint32_t i, const Pkt<R> &P) {
+  if constexpr (REC || PC) {
+    q_store<R, REC>(b, i, P, (R)0);
+  } else {
+    ((R *)b.px)[i] = P.p[0]; ((R *)b.py)[i] = P.p[1]; ((R *)b.pz)[i] = P.p[2];
+    ((R *)b.rho)[i] = P.rho;
+    ((R *)b.tau)[i] = (R)0;
+    b.cx[i] = P.c[0]; b.cy[i] = P.c[1]; b.cz[i] = P.c[2];
+    if (b.fine) b.fine[i] = P.fpk;
+  }
+}
+
 // Voxel walk of every flight-ready packet of queue fcur to its next
 // interaction or out of the grid; the packet is written back to its own
 // entry. Lanes refill one by one from a wave-local chunk, so flights of
@@ -1536,7 +1576,7 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
           else if (rank - avail < fhi - flo) i = flo + (rank - avail);
           if (i != 0xFFFFFFFFu) {
             mine = i;
-            const R tau = q_load<R, REC>(M, qi, i, P);
+            const R tau = q_load_walk<R, REC, PC>(M, qi, i, P);
             if constexpr (REF) flight_setup_ref<R>(X, P, F, tau);
             else flight_setup<R>(X, P, F, tau);
             c0 = P.n_cross;
@@ -1568,7 +1608,7 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
       // the packet goes back to its own entry, which the interaction kernel
       // reads next; an escape leaves the entry marked free (depth < 0)
       if (r == 1) {
-        q_store<R, REC>(qi, mine, P, (R)0);
+        q_store_walk<R, REC, PC>(qi, mine, P);
       } else if (r == 2) {
         ((R *)qi.tau)[mine] = (R)-1;
         P.status = ST_ESCAPED;
