@@ -131,8 +131,8 @@ const char *mcrt_last_error(const mcrt_ctx *ctx);
 
 /* Grid of sect. 2: cubes of constant density rho (g/cm^3, [nz][ny][nx]).
  * dtype MCRT_FP64 (double) or MCRT_FP32 (float); converted to the context
- * precision. EINVAL: n <= 0, dcell <= 0, rho negative or not finite.
- * Resets tallies and temperatures. */
+ * precision. EINVAL: n <= 0 or more than 262143 cells on an axis,
+ * dcell <= 0, rho negative or not finite. Resets tallies and temperatures. */
 mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
                           double dcell, const void *rho, int dtype, int mem);
 /* One level of refinement (sect. 2: each cube divided into sub-cubes of
@@ -155,7 +155,8 @@ mcrt_status mcrt_set_refinement(mcrt_ctx *ctx, const uint8_t *ref, const void *r
 /* Clumpy torus of sect. 6 (Eq. 21 clump centres given, host [n][3] cm):
  * a cell takes rho_clump if its centre lies inside any clump (overlaps keep
  * the single-clump density), rho_inter inside the wedge r_in <= r <= r_out,
- * |z| <= r sin_theta1, else 0. Builds the grid on the device. */
+ * |z| <= r sin_theta1, else 0. Builds the grid on the device (grid limits
+ * as for mcrt_set_grid). */
 mcrt_status mcrt_voxelize_torus(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
                                 double dcell, int n_clumps, const double *centres,
                                 double r_clump, double rho_clump, double rho_inter,
@@ -164,7 +165,7 @@ mcrt_status mcrt_voxelize_torus(mcrt_ctx *ctx, int nx, int ny, int nz, const dou
  * an 8^3 Gauss-Legendre rule: power 2 is the r^-2 shell of sect. 5.1, power
  * 0 the constant-density envelope of the sect. 3.6 run-time comparison
  * (Table 1). EINVAL on rho0 < 0, r_in <= 0, r_out < r_in or a non-finite
- * value. */
+ * value, and on the grid limits of mcrt_set_grid. */
 mcrt_status mcrt_voxelize_shell(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3],
                                 double dcell, double rho0, double r_in, double r_out,
                                 double power);

@@ -778,6 +778,8 @@ extern "C" mcrt_status mcrt_set_grid(mcrt_ctx *ctx, int nx, int ny, int nz, cons
                                      double dcell, const void *rho, int dtype, int mem) {
   if (!ctx) return MCRT_EINVAL;
   if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, MCRT_EINVAL, "grid dimensions must be > 0");
+  if (nx > MAX_AXIS || ny > MAX_AXIS || nz > MAX_AXIS)
+    return fail(ctx, MCRT_EINVAL, "at most %d cells per axis", MAX_AXIS);
   if (!origin || !rho) return fail(ctx, MCRT_EINVAL, "origin and rho must be non-NULL");
   if (!(dcell > 0.0) || !std::isfinite(dcell)) return fail(ctx, MCRT_EINVAL, "dcell must be > 0");
   if (dtype != MCRT_FP64 && dtype != MCRT_FP32) return fail(ctx, MCRT_EINVAL, "bad dtype");
@@ -909,6 +911,8 @@ extern "C" mcrt_status mcrt_set_refinement(mcrt_ctx *ctx, const uint8_t *ref, co
 
 static mcrt_status grid_geom(mcrt_ctx *ctx, int nx, int ny, int nz, const double origin[3], double dcell) {
   if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, MCRT_EINVAL, "grid dimensions must be > 0");
+  if (nx > MAX_AXIS || ny > MAX_AXIS || nz > MAX_AXIS)
+    return fail(ctx, MCRT_EINVAL, "at most %d cells per axis", MAX_AXIS);
   if (!origin) return fail(ctx, MCRT_EINVAL, "origin is NULL");
   if (!(dcell > 0.0) || !std::isfinite(dcell)) return fail(ctx, MCRT_EINVAL, "dcell must be > 0");
   uint64_t n = (uint64_t)nx * ny * nz;
@@ -1331,15 +1335,14 @@ static mcrt_status ensure_queues(mcrt_ctx *ctx, const mcrt_run_opts *o, uint64_t
   if (Q <= ctx->qcap && ctx->d_q) return MCRT_OK;
   const size_t rs = rsize(ctx);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t per = 8 * al(Q * rs) + 4 * al(Q * 4) + al(Q * 8) + 9 * al(Q * 4) + al(Q * 8);
+  const size_t per = 8 * al(Q * rs) + 2 * al(Q * 8) + 9 * al(Q * 4) + al(Q * 8);
   HIPCHK(dev_alloc(&ctx->d_q, 2 * per));
   char *b = (char *)ctx->d_q;
   for (int k = 0; k < 2; ++k) {
     QBuf &q = ctx->q[k];
     void **rv[8] = {&q.px, &q.py, &q.pz, &q.dx, &q.dy, &q.dz, &q.rho, &q.tau};
     for (void **r : rv) { *r = b; b += al(Q * rs); }
-    int32_t **iv[4] = {&q.cx, &q.cy, &q.cz, &q.j};
-    for (int32_t **r : iv) { *r = (int32_t *)b; b += al(Q * 4); }
+    q.cj = (uint64_t *)b; b += al(Q * 8);
     q.pid = (uint64_t *)b; b += al(Q * 8);
     uint32_t **uv[9] = {&q.rngd, &q.nint, &q.ncross, &q.nscat, &q.nabs, &q.nmrw, &q.nlucy,
                         &q.fine, &q.slow};

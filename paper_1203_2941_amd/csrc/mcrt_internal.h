@@ -11,6 +11,12 @@
 namespace mcrt {
 
 constexpr int MAX_NL = 256;
+// Queued packets keep their cell (CJ_BITS per axis, x lowest) and wavelength
+// index (the top 64 - 3 CJ_BITS bits) in one 64-bit word: grids hold at most
+// MAX_AXIS cells per axis.
+constexpr int CJ_BITS = 18;
+constexpr int MAX_AXIS = (1 << CJ_BITS) - 1;
+static_assert(MAX_NL <= (1 << (64 - 3 * CJ_BITS)), "wavelength index fits the packed word");
 constexpr int MAX_NS = 4;
 constexpr int MAX_SRC = 8;
 constexpr int MAX_VIEW = 16;
@@ -85,7 +91,7 @@ __host__ __device__ inline TabOff tab_offsets(int nl, int ns, int nsrc, int nrow
 // R arrays are in the walk precision.
 struct QBuf {
   void *px, *py, *pz, *dx, *dy, *dz, *rho, *tau;
-  int32_t *cx, *cy, *cz, *j;
+  uint64_t *cj;  // cell and wavelength in one word (pack_cj)
   uint64_t *pid;
   uint32_t *rngd, *nint;
   uint32_t *ncross, *nscat, *nabs, *nmrw, *nlucy;  // kept for packet records

@@ -1304,14 +1304,25 @@ __device__ void flush_block(const Ctx<R> &X) {
   __syncthreads();
 }
 
+__device__ __forceinline__ uint64_t pack_cj(const int c[3], int j) {
+  return (uint64_t)(uint32_t)c[0] | ((uint64_t)(uint32_t)c[1] << CJ_BITS) |
+         ((uint64_t)(uint32_t)c[2] << (2 * CJ_BITS)) | ((uint64_t)(uint32_t)j << (3 * CJ_BITS));
+}
+__device__ __forceinline__ void unpack_cj(uint64_t w, int c[3], int &j) {
+  const uint64_t m = (1ull << CJ_BITS) - 1ull;
+  c[0] = (int)(w & m);
+  c[1] = (int)((w >> CJ_BITS) & m);
+  c[2] = (int)((w >> (2 * CJ_BITS)) & m);
+  j = (int)(w >> (3 * CJ_BITS));
+}
+
 template <typename R, bool REC>
 __device__ __forceinline__ void q_store(const QBuf &b, uint32_t i, const Pkt<R> &P, R tau) {
   ((R *)b.px)[i] = P.p[0]; ((R *)b.py)[i] = P.p[1]; ((R *)b.pz)[i] = P.p[2];
   ((R *)b.dx)[i] = P.d[0]; ((R *)b.dy)[i] = P.d[1]; ((R *)b.dz)[i] = P.d[2];
   ((R *)b.rho)[i] = P.rho;
   ((R *)b.tau)[i] = tau;
-  b.cx[i] = P.c[0]; b.cy[i] = P.c[1]; b.cz[i] = P.c[2];
-  b.j[i] = P.j;
+  b.cj[i] = pack_cj(P.c, P.j);
   b.pid[i] = P.pid;
   b.rngd[i] = P.rng.d;
   b.nint[i] = P.n_int;
@@ -1333,8 +1344,7 @@ __device__ __forceinline__ R q_load(const ModelDev &M, const QBuf &b, uint32_t i
   P.d[2] = gld((const R *)b.dz + i);
   P.rho = gld((const R *)b.rho + i);
   const R tau = gld((const R *)b.tau + i);
-  P.c[0] = gld(b.cx + i); P.c[1] = gld(b.cy + i); P.c[2] = gld(b.cz + i);
-  P.j = gld(b.j + i);
+  unpack_cj(gld(b.cj + i), P.c, P.j);
   P.pid = gld(b.pid + i);
   rng_init(P.rng, M.seed, P.pid, (uint32_t)M.iter, (uint32_t)M.model_id, M.pass == 2 ? 3u : 0u);
   P.rng.d = gld(b.rngd + i);
@@ -1492,9 +1502,10 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
 }
 
 // The walk's share of a queued packet. Without records or per-cell draws a
-// flight reads only position, direction, cell, wavelength, sub-cube and
-// depth, and at an interaction changes only position, cell, sub-cube and
-// density (the depth field is cleared): the id, draw index, interaction
+// flight reads only position, direction, cell and wavelength, sub-cube and
+// depth, and at an interaction changes only position, cell (the word it
+// shares with the wavelength), sub-cube and density (the depth field is
+// cleared): the id, draw index, interaction
 // count, direction and wavelength stay in the entry as the interaction kernel
 // reads them. With records or per-cell draws the whole packet moves.
 template <typename R, bool REC, bool PC>
@@ -1507,8 +1518,7 @@ __device__ __forceinline__ R q_load_walk(const ModelDev &M, const QBuf &b, uint3
     P.d[0] = gld((const R *)b.dx + i); P.d[1] = gld((const R *)b.dy + i);
     P.d[2] = gld((const R *)b.dz + i);
     const R tau = gld((const R *)b.tau + i);
-    P.c[0] = gld(b.cx + i); P.c[1] = gld(b.cy + i); P.c[2] = gld(b.cz + i);
-    P.j = gld(b.j + i);
+    unpack_cj(gld(b.cj + i), P.c, P.j);
     P.fpk = b.fine ? gld(b.fine + i) : 0u;
     P.rho = (R)0;
     P.status = ST_ALIVE;
@@ -1526,7 +1536,7 @@ __device__ __forceinline__ void q_store_walk(const QBuf &b, uint32_t i, const Pk
     ((R *)b.px)[i] = P.p[0]; ((R *)b.py)[i] = P.p[1]; ((R *)b.pz)[i] = P.p[2];
     ((R *)b.rho)[i] = P.rho;
     ((R *)b.tau)[i] = (R)0;
-    b.cx[i] = P.c[0]; b.cy[i] = P.c[1]; b.cz[i] = P.c[2];
+    b.cj[i] = pack_cj(P.c, P.j);
     if (b.fine) b.fine[i] = P.fpk;
   }
 }

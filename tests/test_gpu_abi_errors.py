@@ -48,6 +48,16 @@ def test_grid_rejects_bad_density():
         st = g.lib.mcrt_set_grid(g.h, nx, 4, 4, dp(org), dc, C.c_void_p(rho.ctypes.data),
                                  L.FP64, L.HOST)
         assert st == L.EINVAL
+    # queued packets keep their cell in 18 bits per axis
+    line = np.full(1 << 18, 1e-18)
+    for nx in ((1 << 18) - 1, 1 << 18):
+        st = g.lib.mcrt_set_grid(g.h, nx, 1, 1, dp(org), 1.0, C.c_void_p(line.ctypes.data),
+                                 L.FP64, L.HOST)
+        st, msg = status_and_msg(g, st)
+        if nx < (1 << 18):
+            assert st == L.OK, msg
+        else:
+            assert st == L.EINVAL and "per axis" in msg, msg
 
 
 def test_dust_rejects_bad_tables():
