@@ -46,13 +46,13 @@ def walk_alg_bytes(st, ns_thermal, rs=4):
 def walk_queue_bytes(st, rs=4):
     """Packet-state traffic of the wavefront design around the walk (not part
     of the method), for the record-free walk of the benchmark: per flight the
-    walk reads position, direction and depth (7 x rs) with cell and
-    wavelength (16 B); a flight that ends in an interaction writes back
-    position, density and cleared depth (5 x rs) with the cell (12 B); an
-    escape frees its entry (rs)."""
+    walk reads position, direction and depth (7 x rs) with the word holding
+    cell and wavelength (8 B); a flight that ends in an interaction writes
+    back position, density and cleared depth (5 x rs) with that word (8 B);
+    an escape frees its entry (rs)."""
     inter = st["scatters"] + st["absorptions"]
     flights = inter + st["escaped"]
-    return (7 * rs + 16) * flights + (5 * rs + 12) * inter + rs * st["escaped"]
+    return (7 * rs + 8) * flights + (5 * rs + 8) * inter + rs * st["escaped"]
 
 
 def cpu_worker(args):
