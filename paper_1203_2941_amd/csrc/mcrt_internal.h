@@ -17,6 +17,9 @@ constexpr int MAX_NL = 256;
 constexpr int CJ_BITS = 18;
 constexpr int MAX_AXIS = (1 << CJ_BITS) - 1;
 static_assert(MAX_NL <= (1 << (64 - 3 * CJ_BITS)), "wavelength index fits the packed word");
+// The word of an entry the walk frees (an escape): all ones, which names no
+// cell (an axis index is at most MAX_AXIS - 1).
+constexpr uint64_t CJ_FREE = ~0ull;
 constexpr int MAX_NS = 4;
 constexpr int MAX_SRC = 8;
 constexpr int MAX_VIEW = 16;

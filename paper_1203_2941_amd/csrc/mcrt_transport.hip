@@ -1504,10 +1504,10 @@ k_wf_emit(const ModelDev *__restrict__ models, int nmodels, int fcur) {
 // The walk's share of a queued packet. Without records or per-cell draws a
 // flight reads only position, direction, cell and wavelength, sub-cube and
 // depth, and at an interaction changes only position, cell (the word it
-// shares with the wavelength), sub-cube and density (the depth field is
-// cleared): the id, draw index, interaction
-// count, direction and wavelength stay in the entry as the interaction kernel
-// reads them. With records or per-cell draws the whole packet moves.
+// shares with the wavelength), sub-cube and density: the id, draw index,
+// interaction count, direction and wavelength stay in the entry as the
+// interaction kernel reads them, and that kernel does not read the depth.
+// With records or per-cell draws the whole packet moves.
 template <typename R, bool REC, bool PC>
 __device__ __forceinline__ R q_load_walk(const ModelDev &M, const QBuf &b, uint32_t i, Pkt<R> &P) {
   if constexpr (REC || PC) {
@@ -1535,7 +1535,6 @@ __device__ __forceinline__ void q_store_walk(const QBuf &b, uint32_t i, const Pk
   } else {
     ((R *)b.px)[i] = P.p[0]; ((R *)b.py)[i] = P.p[1]; ((R *)b.pz)[i] = P.p[2];
     ((R *)b.rho)[i] = P.rho;
-    ((R *)b.tau)[i] = (R)0;
     b.cj[i] = pack_cj(P.c, P.j);
     if (b.fine) b.fine[i] = P.fpk;
   }
@@ -1616,11 +1615,11 @@ k_wf_walk(const ModelDev *__restrict__ models, int nmodels, int fcur) {
         state = 0;
       }
       // the packet goes back to its own entry, which the interaction kernel
-      // reads next; an escape leaves the entry marked free (depth < 0)
+      // reads next; an escape leaves the entry marked free (CJ_FREE)
       if (r == 1) {
         q_store_walk<R, REC, PC>(qi, mine, P);
       } else if (r == 2) {
-        ((R *)qi.tau)[mine] = (R)-1;
+        qi.cj[mine] = CJ_FREE;
         P.status = ST_ESCAPED;
         finish<R, REC>(X, P, true);
       }
@@ -1665,7 +1664,7 @@ __device__ __forceinline__ void interact_round(const ModelDev *__restrict__ mode
       Pkt<R> P;
       R tau = (R)-1;
       bool keep = false;
-      if (i < hi && gld((const R *)qi.tau + i) >= (R)0) {
+      if (i < hi && gld(qi.cj + i) != CJ_FREE) {
         (void)q_load<R, REC>(M, qi, i, P);
         int defer = 0;
         interact<R, REC, FAST>(X, P, &defer);
