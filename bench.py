@@ -48,11 +48,11 @@ def walk_queue_bytes(st, rs=4):
     of the method), for the record-free walk of the benchmark: per flight the
     walk reads position, direction and depth (7 x rs) with the word holding
     cell and wavelength (8 B); a flight that ends in an interaction writes
-    back position, density and cleared depth (5 x rs) with that word (8 B);
-    an escape frees its entry (rs)."""
+    back position and density (4 x rs) with that word (8 B); an escape marks
+    that word free (8 B)."""
     inter = st["scatters"] + st["absorptions"]
     flights = inter + st["escaped"]
-    return (7 * rs + 8) * flights + (5 * rs + 8) * inter + rs * st["escaped"]
+    return (7 * rs + 8) * flights + (4 * rs + 8) * inter + 8 * st["escaped"]
 
 
 def cpu_worker(args):
