@@ -155,6 +155,26 @@ __device__ __forceinline__ void absorb_pair(float x, float &om, float &e) {
   om = -expm1f(-x);
   e = expf(-x);
 }
+// The same pair from one exponential (the adjoint's two sweeps): 1 - e^-x by
+// its Taylor series below 1/2 (8 terms: truncation under 2e-8 relative) and
+// as the difference above (e <= 0.61 there): within 1e-7 relative of the
+// exact value, against 6e-8 for a correctly rounded expm1f. FP64 keeps the
+// library pair.
+__device__ __forceinline__ void absorb_pair1(double x, double &om, double &e) {
+  absorb_pair(x, om, e);
+}
+__device__ __forceinline__ void absorb_pair1(float x, float &om, float &e) {
+  e = expf(-x);
+  float p = 1.0f / 40320.0f;
+  p = fmaf(-x, p, 1.0f / 5040.0f);
+  p = fmaf(-x, p, 1.0f / 720.0f);
+  p = fmaf(-x, p, 1.0f / 120.0f);
+  p = fmaf(-x, p, 1.0f / 24.0f);
+  p = fmaf(-x, p, 1.0f / 6.0f);
+  p = fmaf(-x, p, 0.5f);
+  p = fmaf(-x, p, 1.0f);
+  om = x < 0.5f ? x * p : 1.0f - e;
+}
 
 // S[v][c][q] = sum_s f_s kabs_s B(T_s)/kext + Ssca/(V w rho kext): one lane
 // per cell evaluates the view-independent emission once and writes the
@@ -450,7 +470,7 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
     for (int q = 0; q < MAX_IMG; ++q) {
       if (q >= nq) break;
       R om, e;
-      absorb_pair(r * (R)A.kext[q] * el, om, e);
+      absorb_pair1(r * (R)A.kext[q] * el, om, e);
       rem[q] += tr[q] * (double)sc[q] * (LIT ? 1.0 : (double)om);
       tr[q] *= (double)e;
     }
@@ -469,7 +489,7 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
     for (int q = 0; q < MAX_IMG; ++q) {
       if (q >= nq) break;
       R om, e;
-      absorb_pair(r * (R)A.kext[q] * el, om, e);
+      absorb_pair1(r * (R)A.kext[q] * el, om, e);
       double Sq = (double)sc[q];
       rem[q] -= tr[q] * Sq * (LIT ? 1.0 : (double)om);
       double dI = (LIT ? 0.0 : tr[q] * Sq * (double)e) - rem[q];
