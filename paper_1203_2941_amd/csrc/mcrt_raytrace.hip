@@ -332,11 +332,12 @@ __global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R
   const int nq = A.nimg;
   const R *rho = (const R *)A.rho;
   const R *S = (const R *)A.S + (uint64_t)v * A.ncell * nq;
-  double I[MAX_IMG], tr[MAX_IMG];
+  double I[MAX_IMG];
+  R tr[MAX_IMG];
 #pragma unroll
   for (int q = 0; q < MAX_IMG; ++q) {
     I[q] = 0.0;
-    tr[q] = 1.0;
+    tr[q] = (R)1;
   }
   double pe[3], dir[3];
   int c[3];
@@ -352,9 +353,9 @@ __global__ void __launch_bounds__(256) k_rt_fwd(const RtArgs *__restrict__ Ap, R
         if (q >= nq) break;
         R dtau = r * (R)A.kext[q] * el;
         R om, e;
-        absorb_pair(dtau, om, e);
-        I[q] += tr[q] * (double)sc[q] * (LIT ? 1.0 : (double)om);
-        tr[q] *= (double)e;
+        absorb_pair1(dtau, om, e);
+        I[q] += (double)tr[q] * (double)sc[q] * (LIT ? 1.0 : (double)om);
+        tr[q] *= e;
       }
     };
     if constexpr (REF) walk_leaves(A, pe, dir, c, seg);
