@@ -443,7 +443,8 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
   // wk = W kext (the weight of dI in dL/drho per unit length); rem = the
   // intensity that reaches the pixel from behind the current cell (I of the
   // whole ray less what the cells up to here contribute)
-  double wk[MAX_IMG], rem[MAX_IMG], tr[MAX_IMG];
+  double rem[MAX_IMG];
+  R wk[MAX_IMG], tr[MAX_IMG];
   bool any = false;
 #pragma unroll
   for (int q = 0; q < MAX_IMG; ++q) {
@@ -454,9 +455,9 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
       W *= V.apix_d2;
     }
     any |= (W != 0.0);
-    wk[q] = q < nq ? W * A.kext[q] : 0.0;
+    wk[q] = q < nq ? (R)(W * A.kext[q]) : (R)0;
     rem[q] = 0.0;
-    tr[q] = 1.0;
+    tr[q] = (R)1;
   }
   if (!any) return;
   double pe[3], dir[3];
@@ -472,14 +473,14 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
       if (q >= nq) break;
       R om, e;
       absorb_pair1(r * (R)A.kext[q] * el, om, e);
-      rem[q] += tr[q] * (double)sc[q] * (LIT ? 1.0 : (double)om);
-      tr[q] *= (double)e;
+      rem[q] += (double)tr[q] * (double)sc[q] * (LIT ? 1.0 : (double)om);
+      tr[q] *= e;
     }
   };
   if constexpr (REF) walk_leaves(A, pe, dir, c, sweep1);
   else walk(A, pe, dir, c, sweep1);
 #pragma unroll
-  for (int q = 0; q < MAX_IMG; ++q) tr[q] = 1.0;
+  for (int q = 0; q < MAX_IMG; ++q) tr[q] = (R)1;
   auto sweep2 = [&](int64_t cell, double ell) {
     R r = rho[cell];
     if (!LIT && !(r > (R)0)) return;
@@ -492,10 +493,10 @@ __global__ void __launch_bounds__(256) k_rt_adj(const RtArgs *__restrict__ Ap, c
       R om, e;
       absorb_pair1(r * (R)A.kext[q] * el, om, e);
       double Sq = (double)sc[q];
-      rem[q] -= tr[q] * Sq * (LIT ? 1.0 : (double)om);
-      double dI = (LIT ? 0.0 : tr[q] * Sq * (double)e) - rem[q];
-      g += wk[q] * ell * dI;
-      tr[q] *= (double)e;
+      rem[q] -= (double)tr[q] * Sq * (LIT ? 1.0 : (double)om);
+      double dI = (LIT ? 0.0 : (double)tr[q] * Sq * (double)e) - rem[q];
+      g += (double)wk[q] * ell * dI;
+      tr[q] *= e;
     }
     if (g != 0.0) atomicAdd(&drho[cell], (R)g);
   };
