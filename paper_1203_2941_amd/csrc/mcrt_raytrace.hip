@@ -7,7 +7,8 @@
 // and one contiguous vector of source functions S[view][cell][0..n_img)
 // that is built per view before the march (emission plus scattered light,
 // both per unit extinction; constant in the traced density).
-// Intensities and transmittances accumulate in FP64 in both precisions.
+// Intensities accumulate in FP64 in both precisions; transmittances and
+// adjoint weights are in the context precision.
 #include "mcrt_rtargs.h"
 
 namespace mcrt {
