@@ -202,6 +202,21 @@ __device__ __forceinline__ void load_row(const R *sc, int nq, R out[MAX_IMG]) {
 // LIT: the printed form of Eqs. 13-14; SH: scattered light formed from the
 // moments of the scattering events (else the per-view sums). Separate
 // instances keep the moment loop's registers out of the common case.
+// B_nu(T) for the source functions in the precision they are stored in:
+// FP32 for an FP32 context (expm1f; beyond x = 80 the value is below what an
+// FP32 source function resolves, so it is 0), FP64 otherwise.
+template <typename R>
+__device__ __forceinline__ double planck_r(double hnu, double a, double T) {
+  if constexpr (sizeof(R) == 8) {
+    return planck_d(hnu, a, T);
+  } else {
+    if (!(T > 0.0)) return 0.0;
+    const float x = (float)hnu / ((float)K_BO * (float)T);
+    if (!(x <= 80.0f)) return 0.0;
+    return (double)((float)a / expm1f(x));
+  }
+}
+
 template <typename R, bool LIT, bool SH>
 __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
   const ModelDev &M = *md;
@@ -229,7 +244,7 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
         for (int s = 0; s < M.ns; ++s) {
           if (s == M.pah) continue;
           e += M.tab[o.frac + s] * M.tab[o.kabs + s * M.nl + j] *
-               planck_d(M.tab[o.hnu + j], M.tab[o.a + j], T[s]);
+               planck_r<R>(M.tab[o.hnu + j], M.tab[o.a + j], T[s]);
         }
         if constexpr (LIT) {
           // printed form: the cell's emergent emission (1 - e^-tau_cell) e/K
