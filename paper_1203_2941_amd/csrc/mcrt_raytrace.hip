@@ -257,6 +257,22 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
         }
       }
     }
+    // per wavelength, the factor from a scattering sum to its source term
+    // (the same for every view)
+    double fs[MAX_IMG];
+#pragma unroll
+    for (int q = 0; q < MAX_IMG; ++q) {
+      fs[q] = 0.0;
+      if (q < nq && r > 0.0) {
+        const int j = M.img_j[q];
+        if constexpr (LIT) {  // Eq. 16: scattered intensity over the cell's face
+          const double hc = leaf_edge(M, c);
+          fs[q] = M.ssca_unit / (M.tab[o.w + j] * hc * hc);
+        } else {
+          fs[q] = M.ssca_unit / (leaf_volume(M, c) * M.tab[o.w + j] * r * M.tab[o.kext + j]);
+        }
+      }
+    }
     for (int v = 0; v < M.nview; ++v) {
       // S is [view][cell][img]; the scattering sums are [cell][view][img] (a
       // scattering event's view sums share cache lines)
@@ -303,16 +319,7 @@ __global__ void k_build_S(const ModelDev *__restrict__ md, R *S) {
 #pragma unroll
       for (int q = 0; q < MAX_IMG; ++q) {
         double val = em[q];
-        if (q < nq && (sc || SH) && r > 0.0) {
-          int j = M.img_j[q];
-          if constexpr (LIT) {  // Eq. 16: scattered intensity over the cell's face
-            const double hc = leaf_edge(M, c);
-            val += (double)sv[q] * M.ssca_unit / (M.tab[o.w + j] * hc * hc);
-          } else {
-            val += (double)sv[q] * M.ssca_unit /
-                   (leaf_volume(M, c) * M.tab[o.w + j] * r * M.tab[o.kext + j]);
-          }
-        }
+        if (q < nq && (sc || SH) && r > 0.0) val += (double)sv[q] * fs[q];
         vals[q] = (R)val;
       }
       if constexpr (sizeof(R) == 4 && MAX_IMG == 16) {
